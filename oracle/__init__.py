@@ -1,0 +1,24 @@
+"""FP64 CPU oracle of ReVo's neural loss-recovery forward pass.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import or call anything in this package.  It shares no
+code with the HIP path: the only common module is ``synth`` (seeded inputs),
+which holds none of the method's arithmetic.
+
+Every function is a plain, slow, direct statement of one step of the method
+(Sec. 3.4.1 architecture, App. B.1 design differences, App. B.3 k and T), in
+float64 unless a rounding emulation is requested for error budgeting.
+"""
+from .model import (
+    Arch, unpack_weights, normalise, zero_fill, sequence_frames, tubelet_vectors,
+    sinusoid, positional_embedding, linear, layer_norm, gelu, attention_head,
+    self_attention, transformer_block, forward, recover, composite, Rounding,
+    bf16_round,
+)
+
+__all__ = [
+    "Arch", "unpack_weights", "normalise", "zero_fill", "sequence_frames", "tubelet_vectors",
+    "sinusoid", "positional_embedding", "linear", "layer_norm", "gelu", "attention_head",
+    "self_attention", "transformer_block", "forward", "recover", "composite", "Rounding",
+    "bf16_round",
+]

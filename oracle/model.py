@@ -1,0 +1,366 @@
+"""FP64 oracle: ReVo's post-decode neural loss-recovery forward pass.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+What the paper fixes (Sec. 3.4.1, App. B.1, App. B.3): a ViViT / VideoMAE
+style encoder-decoder that takes the k closest clean frames plus the current
+corrupted frame and outputs one reconstructed frame; tubelets of T
+consecutive frames and a patch form one token; both visible and corrupted
+pixels are fed; no token shuffling; the same encoder-decoder at inference as
+in pretraining; scaled dot-product attention inside the Transformer blocks;
+positional embeddings encode the temporal distance between references and
+the corrupted target; separate RGB and depth models.  k = 5, T = 2.
+
+Where the paper is silent this oracle takes these readings: patch 16;
+encoder 384 wide x 12 blocks x 6 heads (MLP 1536), decoder 192 x 4 x 3 (MLP
+768); pre-LN blocks, LayerNorm eps 1e-6, exact-erf GELU, qkv bias; RGB /255,
+depth /4000 mm; lost target pixels zero-filled in every channel; no mask
+channel; a fixed three-axis sinusoidal positional embedding (temporal
+distance, patch row, patch column) added after the embedding and after the
+encoder-to-decoder projection; joint space-time attention over all tokens of
+one request; a head emitting the full tubelet, of which the target frame's
+time slot is kept; clamp to the valid range; received (unlost) pixels copied
+through and only lost pixels replaced by the prediction.
+"""
+import math
+from dataclasses import dataclass
+
+import numpy as np
+from scipy.special import erf
+
+PATCH = 16
+
+
+# --------------------------------------------------------------------------
+# architecture description and weight unpacking
+# --------------------------------------------------------------------------
+@dataclass(frozen=True)
+class Arch:
+    """Shapes of one modality's model (C = 3 for RGB, 1 for depth)."""
+    channels: int
+    k: int = 5
+    tubelet: int = 2
+    enc_dim: int = 384
+    enc_depth: int = 12
+    enc_heads: int = 6
+    dec_dim: int = 192
+    dec_depth: int = 4
+    dec_heads: int = 3
+
+    @property
+    def tub_len(self):
+        return self.tubelet * PATCH * PATCH * self.channels
+
+
+def unpack_weights(blob, arch):
+    """Split a flat FP32 blob into named float64 arrays (matrices [out][in]).
+
+    Order: emb, encoder blocks (ln1, qkv, proj, ln2, fc1, fc2), enc_norm,
+    e2d, decoder blocks, dec_norm, head; each matrix is followed by its bias.
+    """
+    blob = np.asarray(blob)
+    p = {}
+    pos = 0
+
+    def take(name, shape):
+        nonlocal pos
+        n = int(np.prod(shape))
+        if pos + n > blob.size:
+            raise ValueError("weight blob too short")
+        p[name] = blob[pos:pos + n].astype(np.float64).reshape(shape)
+        pos += n
+
+    De, Dd = arch.enc_dim, arch.dec_dim
+    take("emb.w", (De, arch.tub_len))
+    take("emb.b", (De,))
+    for i in range(arch.enc_depth):
+        _take_block(take, f"enc{i}.", De)
+    take("enc_norm.g", (De,))
+    take("enc_norm.b", (De,))
+    take("e2d.w", (Dd, De))
+    take("e2d.b", (Dd,))
+    for i in range(arch.dec_depth):
+        _take_block(take, f"dec{i}.", Dd)
+    take("dec_norm.g", (Dd,))
+    take("dec_norm.b", (Dd,))
+    take("head.w", (arch.tub_len, Dd))
+    take("head.b", (arch.tub_len,))
+    if pos != blob.size:
+        raise ValueError(f"weight blob has {blob.size} values, layout needs {pos}")
+    return p
+
+
+def _take_block(take, pre, D):
+    take(pre + "ln1.g", (D,))
+    take(pre + "ln1.b", (D,))
+    take(pre + "qkv.w", (3 * D, D))
+    take(pre + "qkv.b", (3 * D,))
+    take(pre + "proj.w", (D, D))
+    take(pre + "proj.b", (D,))
+    take(pre + "ln2.g", (D,))
+    take(pre + "ln2.b", (D,))
+    take(pre + "fc1.w", (4 * D, D))
+    take(pre + "fc1.b", (4 * D,))
+    take(pre + "fc2.w", (D, 4 * D))
+    take(pre + "fc2.b", (D,))
+
+
+# --------------------------------------------------------------------------
+# operand rounding (error budgeting only; identity for the FP64 oracle)
+# --------------------------------------------------------------------------
+def bf16_round(x):
+    """Round to the nearest bfloat16 value, ties to even, via float32.
+
+    The value is first rounded to float32 (as a float32 producer would hold
+    it), then its low 16 mantissa bits are rounded off.
+    """
+    f = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    u = ((u + 0x7FFF + lsb) & 0xFFFF0000).astype(np.uint32)
+    return u.view(np.float32).astype(np.float64)
+
+
+class Rounding:
+    """Where a reduced-precision GPU form rounds matrix-multiply operands.
+
+    ``Rounding()`` (the default) is exact FP64.  ``Rounding(bf16_round)``
+    rounds every matrix-product operand (pixel inputs, weights, LayerNorm
+    outputs, Q/K/V, attention probabilities, attention output, GELU output)
+    while sums, normalisation statistics, the residual stream and the
+    composite stay in FP64.  It never reorders any computation.
+    """
+
+    def __init__(self, fn=None):
+        self.fn = fn
+
+    def __call__(self, x):
+        return x if self.fn is None else self.fn(x)
+
+
+EXACT = Rounding()
+
+
+# --------------------------------------------------------------------------
+# input preparation (Sec. 3.3 zero-filled partial frames; Sec. 3.4.1 inputs)
+# --------------------------------------------------------------------------
+def normalise(frame, channels):
+    """Map a decoded frame to model units: RGB u8/255, depth u16 mm / 4000."""
+    if channels == 3:
+        return np.asarray(frame, np.float64) / 255.0
+    return np.asarray(frame, np.float64)[..., None] / 4000.0
+
+
+def zero_fill(x, mask):
+    """Set every channel of lost pixels (mask == 1) to zero."""
+    out = x.copy()
+    out[np.asarray(mask) != 0] = 0.0
+    return out
+
+
+def sequence_frames(ref_idx, t_target, k, T):
+    """Indices (into refs + [target]) and frame times of the model's input.
+
+    The k references are oldest first and the target comes last.  With fewer
+    than k references the oldest is repeated; the sequence is then padded at
+    the old end, again with the oldest frame, up to a multiple of T.
+    """
+    n_ref = len(ref_idx)
+    if n_ref == 0:
+        raise ValueError("no clean reference frame")
+    slots = [0] * (k - n_ref) + list(range(n_ref))
+    slots = slots + [n_ref]                       # the target
+    pad = (-len(slots)) % T
+    slots = [0] * pad + slots
+    times = [int(ref_idx[s]) if s < n_ref else int(t_target) for s in slots]
+    return slots, times
+
+
+def tubelet_vectors(frames, T):
+    """Cut F frames [F, H', W', C] into tubelet vectors.
+
+    Token n = j*P + y*(W'/16) + x for tubelet j (frames jT .. jT+T-1), patch
+    row y and column x; its vector element ((t*16 + py)*16 + px)*C + c holds
+    frame jT+t at pixel (16y+py, 16x+px), channel c.
+    """
+    F, Hp, Wp, C = frames.shape
+    J = F // T
+    gy, gx = Hp // PATCH, Wp // PATCH
+    U = np.empty((J * gy * gx, T * PATCH * PATCH * C))
+    for j in range(J):
+        for y in range(gy):
+            for x in range(gx):
+                blk = frames[j * T:(j + 1) * T, y * PATCH:(y + 1) * PATCH, x * PATCH:(x + 1) * PATCH, :]
+                U[j * gy * gx + y * gx + x] = blk.reshape(-1)
+    return U
+
+
+def sinusoid(d, s):
+    """Length-d sinusoid of a scalar position s: sin at even, cos at odd slots.
+
+    Element 2i is sin(s * 10000^(-2i/d)) and element 2i+1 the cosine.
+    """
+    out = np.empty(d)
+    for i in range(d // 2):
+        w = 10000.0 ** (-2.0 * i / d)
+        out[2 * i] = math.sin(s * w)
+        out[2 * i + 1] = math.cos(s * w)
+    return out
+
+
+def positional_embedding(D, tau, y, x):
+    """Fixed embedding of a token's temporal distance tau to the target and
+    its patch row and column: three length-D/3 sinusoids, concatenated."""
+    d = D // 3
+    return np.concatenate([sinusoid(d, tau), sinusoid(d, y), sinusoid(d, x)])
+
+
+def token_positions(D, taus, gy, gx):
+    """PE rows for every token of a request, in token order."""
+    rows = []
+    for tau in taus:
+        for y in range(gy):
+            for x in range(gx):
+                rows.append(positional_embedding(D, tau, y, x))
+    return np.stack(rows)
+
+
+# --------------------------------------------------------------------------
+# network layers
+# --------------------------------------------------------------------------
+def linear(x, w, b, rnd=EXACT):
+    """x W^T + b with W stored [out][in]."""
+    return rnd(x) @ rnd(w).T + b
+
+
+def layer_norm(x, g, b, eps=1e-6):
+    """Per-row (x - mean) / sqrt(biased variance + eps) * g + b."""
+    mu = x.mean(axis=-1, keepdims=True)
+    var = ((x - mu) ** 2).mean(axis=-1, keepdims=True)
+    return (x - mu) / np.sqrt(var + eps) * g + b
+
+
+def gelu(z):
+    """Exact GELU: z * Phi(z) = z/2 * (1 + erf(z / sqrt(2)))."""
+    return 0.5 * z * (1.0 + erf(z / math.sqrt(2.0)))
+
+
+def attention_head(q, k, v, rnd=EXACT, chunk=2048):
+    """softmax(q k^T / sqrt(d)) v over all keys, rows processed in chunks
+    (rows are independent, so chunking changes nothing)."""
+    d = q.shape[1]
+    out = np.empty((q.shape[0], v.shape[1]))
+    for r0 in range(0, q.shape[0], chunk):
+        s = q[r0:r0 + chunk] @ k.T / math.sqrt(d)
+        s -= s.max(axis=1, keepdims=True)
+        e = np.exp(s)
+        denom = e.sum(axis=1, keepdims=True)
+        out[r0:r0 + chunk] = (rnd(e) @ v) / denom
+    return out
+
+
+def self_attention(a, p, pre, heads, rnd=EXACT):
+    """Multi-head self-attention: qkv projection (columns Q | K | V, each
+    head-major with contiguous heads), per-head attention, output projection."""
+    N, D = a.shape
+    dh = D // heads
+    qkv = linear(a, p[pre + "qkv.w"], p[pre + "qkv.b"], rnd)
+    q, k, v = rnd(qkv[:, :D]), rnd(qkv[:, D:2 * D]), rnd(qkv[:, 2 * D:])
+    o = np.empty((N, D))
+    for h in range(heads):
+        sl = slice(h * dh, (h + 1) * dh)
+        o[:, sl] = attention_head(q[:, sl], k[:, sl], v[:, sl], rnd)
+    return linear(o, p[pre + "proj.w"], p[pre + "proj.b"], rnd)
+
+
+def transformer_block(h, p, pre, heads, rnd=EXACT):
+    """Pre-LN block: h + Attn(LN1(h)), then + FC2(GELU(FC1(LN2(.))))."""
+    h = h + self_attention(layer_norm(h, p[pre + "ln1.g"], p[pre + "ln1.b"]), p, pre, heads, rnd)
+    a = layer_norm(h, p[pre + "ln2.g"], p[pre + "ln2.b"])
+    z = rnd(gelu(linear(a, p[pre + "fc1.w"], p[pre + "fc1.b"], rnd)))
+    return h + linear(z, p[pre + "fc2.w"], p[pre + "fc2.b"], rnd)
+
+
+# --------------------------------------------------------------------------
+# whole forward pass and compositing
+# --------------------------------------------------------------------------
+def forward(refs, ref_idx, target, t_target, mask, params, arch, rnd=EXACT):
+    """Prediction of the target frame in model units, [H, W, C], unclamped.
+
+    refs: [n_ref, H, W(, 3)] clean frames oldest first; target: the received
+    frame; mask: [H, W] with 1 = lost.
+    """
+    C, T = arch.channels, arch.tubelet
+    H, W = np.asarray(target).shape[:2]
+    Hp, Wp = PATCH * -(-H // PATCH), PATCH * -(-W // PATCH)
+    gy, gx = Hp // PATCH, Wp // PATCH
+    slots, times = sequence_frames(ref_idx, t_target, arch.k, T)
+    seq = np.zeros((len(slots), Hp, Wp, C))
+    for i, s in enumerate(slots):
+        if s < len(ref_idx):
+            fr = normalise(refs[s], C)
+        else:
+            fr = zero_fill(normalise(target, C), mask)
+        seq[i, :H, :W, :] = fr
+    J = len(slots) // T
+    taus = [t_target - times[j * T] for j in range(J)]
+    U = tubelet_vectors(seq, T)
+    h = linear(U, params["emb.w"], params["emb.b"], rnd)
+    h = h + token_positions(arch.enc_dim, taus, gy, gx)
+    for i in range(arch.enc_depth):
+        h = transformer_block(h, params, f"enc{i}.", arch.enc_heads, rnd)
+    a = layer_norm(h, params["enc_norm.g"], params["enc_norm.b"])
+    z = linear(a, params["e2d.w"], params["e2d.b"], rnd)
+    z = z + token_positions(arch.dec_dim, taus, gy, gx)
+    for i in range(arch.dec_depth):
+        z = transformer_block(z, params, f"dec{i}.", arch.dec_heads, rnd)
+    P = gy * gx
+    zt = layer_norm(z[(J - 1) * P:], params["dec_norm.g"], params["dec_norm.b"])
+    o = linear(zt, params["head.w"], params["head.b"], rnd)   # [P, T*256*C]
+    slot = o.reshape(P, T, PATCH, PATCH, C)[:, T - 1]          # target time slot
+    pred = slot.reshape(gy, gx, PATCH, PATCH, C).transpose(0, 2, 1, 3, 4).reshape(Hp, Wp, C)
+    return pred[:H, :W, :]
+
+
+def composite(pred, received, mask, channels):
+    """Final frame from the prediction (model units) and the received frame.
+
+    Lost pixels take the clamped, denormalised prediction; received pixels
+    are copied unchanged.  Returns (float output, integer output):
+    RGB floats in [0, 1] and u8 codes; depth floats in mm and u16 codes.
+    Integer codes of lost pixels round half to even.
+    """
+    lost = np.asarray(mask) != 0
+    if channels == 3:
+        p = np.clip(pred, 0.0, 1.0)
+        recv_f = np.asarray(received, np.float64) / 255.0
+        out_f = np.where(lost[..., None], p, recv_f)
+        q = np.rint(255.0 * p).astype(np.uint8)
+        out_i = np.where(lost[..., None], q, received).astype(np.uint8)
+    else:
+        p = np.clip(4000.0 * pred[..., 0], 0.0, 65535.0)
+        recv_f = np.asarray(received, np.float64)
+        out_f = np.where(lost, p, recv_f)
+        q = np.rint(p).astype(np.uint16)
+        out_i = np.where(lost, q, received).astype(np.uint16)
+    return out_f, out_i
+
+
+def recover(req, blobs, enc_depth=12, dec_depth=4, k=5, tubelet=2, rnd=EXACT,
+            modalities=("rgb", "depth")):
+    """Recover both modalities of one request (a dict as made by synth).
+
+    blobs: (rgb_blob, depth_blob).  Returns {modality: (pred, out_f, out_i)}.
+    """
+    out = {}
+    for mod in modalities:
+        C = 3 if mod == "rgb" else 1
+        arch = Arch(channels=C, k=k, tubelet=tubelet, enc_depth=enc_depth, dec_depth=dec_depth)
+        params = unpack_weights(blobs[0] if C == 3 else blobs[1], arch)
+        refs = req["rgb_refs"] if C == 3 else req["depth_refs"]
+        target = req["rgb"] if C == 3 else req["depth"]
+        mask = req["mask_rgb"] if C == 3 else req["mask_depth"]
+        pred = forward(refs, req["ref_idx"], target, req["t_target"], mask, params, arch, rnd)
+        out_f, out_i = composite(pred, target, mask, C)
+        out[mod] = (pred, out_f, out_i)
+    return out
