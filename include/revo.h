@@ -1,0 +1,168 @@
+/*
+ * revo.h -- C ABI of the MI355X neural loss-recovery library.
+ *
+ * The library runs ReVo's post-decode neural loss recovery (Sec. 3.4.1 of
+ * the paper): for a frame whose packets were partly lost, it takes the k
+ * closest clean frames of the same stream and modality plus the corrupted
+ * frame and returns a reconstructed frame.  RGB and depth have separate
+ * models of the same architecture (Sec. 3.4.2).  The same clean references
+ * are reused for every corrupted frame until a new clean frame arrives,
+ * with the temporal distance to the target fed to the network (Sec. 3.4.1).
+ * Intact frames bypass recovery (Sec. 3.1 overview): a request without a
+ * loss mask is a clean frame, it updates the reference set and its output
+ * is a copy.  The decoder thread hands frames over and the display thread
+ * collects them (Sec. 4 receiver threads): submit and poll may be called
+ * from different threads.
+ *
+ * Model ("ViViT-S/16" reading of Sec. 3.4.1, App. B.1, App. B.3): tubelets
+ * of T frames x 16 x 16 pixels, encoder 384 wide x 12 pre-LN blocks x 6
+ * heads (MLP 1536), decoder 192 x 4 x 3 (MLP 768), joint space-time
+ * attention over all tokens of a request, a fixed three-axis sinusoidal
+ * positional embedding (temporal distance, patch row, patch column), and a
+ * head emitting the target frame's pixels.  Inputs are RGB u8/255 and
+ * depth u16 mm / 4000; lost target pixels are zero-filled (Sec. 3.3).
+ *
+ * Errors are negative return codes (revo_status).  Per-request failures
+ * are reported in revo_completion.status / .error.
+ */
+#ifndef REVO_H
+#define REVO_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define REVO_ABI_VERSION 1
+
+typedef struct revo_ctx revo_ctx; /* opaque: device memory, weights, rings, worker thread */
+
+enum revo_status {
+  REVO_OK = 0,
+  REVO_EAGAIN = 1,       /* queue full: poll, then submit again */
+  REVO_EINVAL = -22,     /* bad argument */
+  REVO_ENOMEM = -12,     /* device memory or HBM budget exhausted */
+  REVO_EDEVICE = -5,     /* HIP runtime error */
+  REVO_ENOREF = -61,     /* recovery asked for before any clean frame of the stream */
+  REVO_ENOTSUP = -95,    /* configuration this build does not support */
+  REVO_ESHUTDOWN = -108  /* context is being destroyed */
+};
+
+enum revo_precision {
+  REVO_FP32 = 0,  /* FP32 operands, FP32 MFMA */
+  REVO_BF16 = 1   /* BF16 operands, FP32 accumulation, FP32 residual/LN/softmax/composite */
+};
+
+enum revo_completion_status {
+  REVO_DONE = 0,    /* outputs written */
+  REVO_SHED = 1,    /* deadline could not be met; nothing written (display repeats the last frame) */
+  REVO_FAILED = 2   /* see revo_completion.error */
+};
+
+/* revo_request.flags */
+#define REVO_DEVICE_PTRS 0x1u /* every pointer of the request is a device pointer on cfg.device */
+#define REVO_HOLD 0x2u        /* keep queued: batch with the next submit that lacks this flag */
+
+/* revo_config.flags */
+#define REVO_CFG_SHED 0x1u    /* shed requests whose deadline cannot be met */
+
+typedef struct revo_config {
+  int device;                 /* HIP device ordinal */
+  int precision;              /* revo_precision */
+  int k;                      /* clean reference frames per recovery, 1..7 (paper: 5) */
+  int tubelet;                /* frames per tubelet T, 1..4 (paper: 2); (k+1) padded to a multiple of T */
+  int enc_depth;              /* encoder blocks; 0 = 12 */
+  int dec_depth;              /* decoder blocks; 0 = 4 */
+  int composite;              /* 1 = replace lost pixels only; 0 = raw clamped prediction everywhere */
+  int max_streams;            /* conference streams holding reference state (0 = 64) */
+  int max_batch;              /* requests per batch (0 = 16) */
+  int max_batch_tokens;       /* tokens per batch per modality (0 = from hbm_budget_bytes, else 43200) */
+  size_t hbm_budget_bytes;    /* cap on weights + workspaces + reference rings + staging (0 = none) */
+  float fps;                  /* default deadline is arrival + 1/fps (0 = 30) */
+  const float *weights_rgb;   /* host FP32 blob, layout below; copied at create */
+  size_t n_weights_rgb;
+  const float *weights_depth; /* host FP32 blob for the depth model */
+  size_t n_weights_depth;
+  unsigned flags;             /* REVO_CFG_* */
+} revo_config;
+
+/*
+ * Weight blob layout, per modality (C = 3 RGB, 1 depth; L = T*256*C; every
+ * matrix row-major [out][in], each followed by its bias):
+ *   emb.w [384][L] emb.b [384]
+ *   enc_depth x { ln1.g ln1.b [384]  qkv.w [1152][384] qkv.b [1152]
+ *                 proj.w [384][384] proj.b [384]  ln2.g ln2.b [384]
+ *                 fc1.w [1536][384] fc1.b [1536]  fc2.w [384][1536] fc2.b [384] }
+ *   enc_norm.g enc_norm.b [384]   e2d.w [192][384] e2d.b [192]
+ *   dec_depth x { same with 192 wide, qkv 576, MLP 768 }
+ *   dec_norm.g dec_norm.b [192]   head.w [L][192] head.b [L]
+ * qkv output columns are Q | K | V, each with heads of 64 contiguous.
+ * Tubelet vector element ((t*16 + py)*16 + px)*C + c is frame t of the
+ * tubelet at patch pixel (py, px), channel c.
+ */
+
+typedef struct revo_request {
+  unsigned stream_id;             /* < max_streams */
+  long long frame_index;          /* decode order index; temporal distance = target - reference */
+  int width, height;              /* frame size in pixels (>= 16 x 16, <= 4096 x 4096) */
+  unsigned flags;                 /* REVO_DEVICE_PTRS, REVO_HOLD */
+  const unsigned char *rgb;       /* H x W x 3 u8, or NULL: no RGB in this request */
+  const unsigned char *mask_rgb;  /* H x W u8, 1 = pixel lost; NULL = clean RGB frame */
+  const unsigned short *depth;    /* H x W u16 millimetres, or NULL */
+  const unsigned char *mask_depth;/* H x W u8; NULL = clean depth frame */
+  unsigned char *rgb_out;         /* H x W x 3 u8 output (may be NULL) */
+  unsigned short *depth_out;      /* H x W u16 output (may be NULL) */
+  float *rgb_out_f32;             /* optional H x W x 3 float output in [0, 1] */
+  float *depth_out_f32;           /* optional H x W float output in mm */
+  long long deadline_ns;          /* CLOCK_MONOTONIC; 0 = submit time + 1/fps */
+} revo_request;
+
+typedef struct revo_completion {
+  unsigned long long ticket;
+  unsigned stream_id;
+  long long frame_index;
+  int status;                     /* revo_completion_status */
+  int error;                      /* revo_status when status == REVO_FAILED */
+  long long submit_ns, done_ns;   /* CLOCK_MONOTONIC */
+} revo_completion;
+
+/* Fill cfg with the paper's configuration: BF16, k = 5, T = 2, 12 + 4 blocks,
+ * composite on, 30 fps.  Weights must still be set. */
+void revo_config_default(revo_config *cfg);
+
+/* Number of floats in one modality's weight blob (channels 3 or 1). */
+size_t revo_weight_count(int channels, int tubelet, int enc_depth, int dec_depth);
+
+/* Create a context on cfg->device: uploads and converts the weights, sizes
+ * the workspaces, starts the worker thread.  *out is set on success. */
+int revo_recover_create(const revo_config *cfg, revo_ctx **out);
+
+/* Queue one frame (RGB and/or depth) of one stream.  Non-blocking with
+ * respect to the GPU work: inputs are copied into library staging before
+ * it returns, so input buffers may be reused at once; output buffers must
+ * stay valid until poll reports the ticket.  A modality with a mask is
+ * recovered against the stream's clean references as they stand at this
+ * submit; a modality without a mask becomes the newest clean reference
+ * (a resolution change resets the stream's references) and is copied to
+ * the output.  Recovered frames never become references.
+ * Returns REVO_OK and sets *ticket, REVO_EAGAIN if the queue is full, or
+ * an error.  Recovery without any clean reference completes with
+ * status REVO_FAILED, error REVO_ENOREF. */
+int revo_recover_submit(revo_ctx *ctx, const revo_request *req, unsigned long long *ticket);
+
+/* Collect up to max completions, waiting up to timeout_us (0 = no wait,
+ * -1 = wait for at least one).  Returns the count (>= 0) or an error. */
+int revo_recover_poll(revo_ctx *ctx, revo_completion *out, int max, int timeout_us);
+
+/* Drain queued and in-flight work, stop the worker and free everything. */
+void revo_recover_destroy(revo_ctx *ctx);
+
+/* Static text for a revo_status code. */
+const char *revo_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REVO_H */

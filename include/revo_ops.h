@@ -1,0 +1,55 @@
+/*
+ * revo_ops.h -- single-kernel entry points of the recovery library.
+ *
+ * Each call runs one of the kernels the recovery network is made of, on
+ * caller-owned device buffers, so that every kernel can be checked on its
+ * own.  All pointers are device pointers on the current HIP device; stream
+ * may be NULL (the default stream).  Calls are asynchronous on that stream.
+ * They return 0 or a negative revo_status (REVO_EINVAL on shapes the
+ * kernel does not take, REVO_ENOTSUP on an unknown precision, REVO_EDEVICE
+ * when the launch fails).  precision is REVO_FP32 (float operands) or
+ * REVO_BF16 (bfloat16 operands, float accumulation).
+ */
+#ifndef REVO_OPS_H
+#define REVO_OPS_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum revo_op_epilogue {
+  REVO_EPI_STORE = 0,    /* out[m][n] = sum_k x[m][k] w[n][k] + bias[n]          (operand type) */
+  REVO_EPI_RESIDUAL = 1, /* out[m][n] += sum_k x[m][k] w[n][k] + bias[n]         (float)        */
+  REVO_EPI_GELU = 2      /* out[m][n] = GELU_erf(sum_k x[m][k] w[n][k] + bias[n]) (operand type) */
+};
+
+/* Linear layer of a Transformer block (Sec. 3.4.1): x [M][K] and w [N][K]
+ * row-major in the operand type, bias [N] float, out [M][N].
+ * Requires N % 64 == 0 and K % 64 == 0 (K % 32 for REVO_FP32). */
+int revo_op_linear(int precision, int epilogue, const void *x, const void *w, const float *bias,
+                   void *out, int M, int N, int K, void *stream);
+
+/* LayerNorm over rows of D <= 512 floats: y = (x - mean) / sqrt(var + 1e-6)
+ * * g + b with the biased variance; y in the operand type. */
+int revo_op_layernorm(int precision, const float *x, const float *g, const float *b, void *y,
+                      int rows, int D, void *stream);
+
+/* Scaled dot-product attention of one request with ntok tokens and
+ * `heads` heads of 64 (the attention inside each Transformer block,
+ * App. B.1): o[t][h*64 + d] = sum_j softmax_j(q_h[t] . k_h[j] / 8) v_h[j][d].
+ * Layouts (operand type): q and k [heads][ld][64] with q already
+ * multiplied by log2(e) / 8; vt [heads][64][ld] (V transposed);
+ * o [ntok][heads * 64].  ld >= ntok + 64 and rows ntok .. ld-1 of q, k
+ * and columns ntok .. ld-1 of vt must hold finite values (zeros). */
+int revo_op_attention(int precision, const void *q, const void *k, const void *vt, void *o,
+                      int heads, int ntok, int ld, void *stream);
+
+/* Element-wise float -> operand type conversion of n values
+ * (round to nearest even for REVO_BF16). */
+int revo_op_convert(int precision, const float *src, void *dst, long long n, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REVO_OPS_H */

@@ -1,0 +1,124 @@
+"""Python face of the C ABI: a Recoverer holds one revo_ctx."""
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib
+from ._lib import lib, check, RevoConfig, RevoRequest, RevoCompletion
+
+REVO_FP32, REVO_BF16 = 0, 1
+
+
+@dataclass
+class Completion:
+    ticket: int
+    stream_id: int
+    frame_index: int
+    status: int
+    error: int
+    submit_ns: int
+    done_ns: int
+
+
+def _ptr(x):
+    """Address of a numpy array or a torch tensor (None -> NULL)."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("arrays must be C-contiguous")
+        return x.ctypes.data
+    if hasattr(x, "data_ptr"):
+        if not x.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+        return x.data_ptr()
+    raise TypeError(type(x))
+
+
+class Recoverer:
+    """revo_recover_create / submit / poll / destroy."""
+
+    def __init__(self, weights_rgb, weights_depth, precision=REVO_BF16, device=0, k=5, tubelet=2,
+                 enc_depth=0, dec_depth=0, composite=1, max_streams=64, max_batch=16, max_batch_tokens=0,
+                 hbm_budget_bytes=0, fps=30.0, shed=False):
+        cfg = RevoConfig()
+        lib.revo_config_default(C.byref(cfg))
+        self._w = [np.ascontiguousarray(weights_rgb, np.float32), np.ascontiguousarray(weights_depth, np.float32)]
+        cfg.device, cfg.precision, cfg.k, cfg.tubelet = device, precision, k, tubelet
+        cfg.enc_depth, cfg.dec_depth, cfg.composite = enc_depth, dec_depth, composite
+        cfg.max_streams, cfg.max_batch, cfg.max_batch_tokens = max_streams, max_batch, max_batch_tokens
+        cfg.hbm_budget_bytes, cfg.fps = hbm_budget_bytes, fps
+        cfg.flags = _lib.REVO_CFG_SHED if shed else 0
+        cfg.weights_rgb = self._w[0].ctypes.data_as(C.POINTER(C.c_float))
+        cfg.n_weights_rgb = self._w[0].size
+        cfg.weights_depth = self._w[1].ctypes.data_as(C.POINTER(C.c_float))
+        cfg.n_weights_depth = self._w[1].size
+        h = C.c_void_p()
+        check(lib.revo_recover_create(C.byref(cfg), C.byref(h)), "revo_recover_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, stream_id, frame_index, width, height, rgb=None, mask_rgb=None, depth=None, mask_depth=None,
+               rgb_out=None, depth_out=None, rgb_out_f32=None, depth_out_f32=None, device_ptrs=False,
+               hold=False, deadline_ns=0):
+        """Queue one frame; returns the ticket, or None when the queue is full."""
+        r = RevoRequest()
+        r.stream_id, r.frame_index, r.width, r.height = stream_id, frame_index, width, height
+        r.flags = (_lib.REVO_DEVICE_PTRS if device_ptrs else 0) | (_lib.REVO_HOLD if hold else 0)
+        r.rgb, r.mask_rgb, r.depth, r.mask_depth = _ptr(rgb), _ptr(mask_rgb), _ptr(depth), _ptr(mask_depth)
+        r.rgb_out, r.depth_out = _ptr(rgb_out), _ptr(depth_out)
+        r.rgb_out_f32, r.depth_out_f32 = _ptr(rgb_out_f32), _ptr(depth_out_f32)
+        r.deadline_ns = deadline_ns
+        t = C.c_ulonglong()
+        rc = lib.revo_recover_submit(self._h, C.byref(r), C.byref(t))
+        if rc == _lib.REVO_EAGAIN:
+            return None
+        check(rc, "revo_recover_submit")
+        # outputs must outlive the call until poll reports the ticket
+        self._keep[t.value] = (rgb_out, depth_out, rgb_out_f32, depth_out_f32)
+        return t.value
+
+    def poll(self, max_n=64, timeout_us=-1):
+        buf = (RevoCompletion * max_n)()
+        n = check(lib.revo_recover_poll(self._h, buf, max_n, timeout_us), "revo_recover_poll")
+        out = []
+        for i in range(n):
+            c = buf[i]
+            self._keep.pop(c.ticket, None)
+            out.append(Completion(c.ticket, c.stream_id, c.frame_index, c.status, c.error, c.submit_ns, c.done_ns))
+        return out
+
+    def wait(self, tickets, timeout_us=120_000_000):
+        """Poll until every ticket in `tickets` has completed; returns {ticket: Completion}."""
+        want = set(tickets)
+        got = {}
+        while want:
+            cs = self.poll(64, timeout_us)
+            if not cs:
+                raise TimeoutError(f"tickets {sorted(want)} did not complete")
+            for c in cs:
+                got[c.ticket] = c
+                want.discard(c.ticket)
+        return got
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.revo_recover_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def weight_count(channels, tubelet=2, enc_depth=12, dec_depth=4):
+    return int(lib.revo_weight_count(channels, tubelet, enc_depth, dec_depth))

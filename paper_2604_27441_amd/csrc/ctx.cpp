@@ -1,0 +1,586 @@
+// Serving context behind revo_recover_create/submit/poll/destroy.
+//
+// submit() stages the caller's frames in device memory and queues a job;
+// one worker thread forms batches from the queue as the GPU frees up
+// (continuous batching: whatever arrived while the previous batch ran goes
+// into the next one, up to the token capacity of the workspaces), applies
+// clean frames to the per-stream reference rings in submission order, runs
+// the RGB and depth networks on two streams, and posts completions that
+// poll() hands out.  Deadlines follow the receiver's 1/fps budget (Sec. 3.3,
+// Eq. 1); with shedding enabled a job that cannot finish in time completes
+// as REVO_SHED, the analogue of the display repeating its last frame.
+#include <string.h>
+#include <time.h>
+
+#include <algorithm>
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "../../include/revo.h"
+#include "model.h"
+
+using namespace revo;
+
+namespace {
+
+long long now_ns() {
+  timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (long long)ts.tv_sec * 1000000000LL + ts.tv_nsec;
+}
+
+bool is_device_ptr(const void* p) {
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice;
+}
+
+// Size-bucketed cache of device allocations, accounted against a budget.
+class DevPool {
+ public:
+  size_t budget = 0;   // 0 = unlimited
+  size_t fixed = 0;    // weights + workspaces, charged once
+  size_t live = 0;     // bytes handed out or cached
+  std::mutex mu;
+  std::multimap<size_t, void*> free_;
+
+  static size_t round(size_t n) { return (n + 4095) & ~(size_t)4095; }
+
+  void* get(size_t n) {
+    n = round(n);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = free_.find(n);
+    if (it != free_.end()) {
+      void* p = it->second;
+      free_.erase(it);
+      return p;
+    }
+    if (budget && fixed + live + n > budget) {
+      // give back cached blocks of other sizes before refusing
+      for (auto f = free_.begin(); f != free_.end() && fixed + live + n > budget;) {
+        (void)hipFree(f->second);
+        live -= f->first;
+        f = free_.erase(f);
+      }
+      if (fixed + live + n > budget) return nullptr;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, n) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    live += n;
+    return p;
+  }
+  void put(void* p, size_t n) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(mu);
+    free_.emplace(round(n), p);
+  }
+  void clear() {
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto& f : free_) (void)hipFree(f.second);
+    free_.clear();
+  }
+};
+
+struct RefFrame {
+  void* dev = nullptr;
+  long long index = 0;
+};
+
+struct Ring {
+  int H = 0, W = 0;
+  std::deque<RefFrame> frames;  // oldest first, at most k
+};
+
+struct Mod {
+  bool present = false, clean = false;
+  int H = 0, W = 0;
+  void* staged = nullptr;      // received frame (device, library-owned)
+  uint8_t* mask = nullptr;     // loss mask (device, library-owned)
+  void* out_i = nullptr;       // caller output
+  float* out_f = nullptr;
+  bool out_dev = false;
+  void* out_i_st = nullptr;    // device staging of host outputs
+  float* out_f_st = nullptr;
+  float* pred = nullptr;
+  size_t frame_bytes = 0;
+  int error = 0;
+};
+
+struct Job {
+  unsigned long long ticket = 0;
+  unsigned stream = 0;
+  long long frame = 0;
+  unsigned flags = 0;
+  long long deadline = 0, submit_ns = 0;
+  Mod mod[2];
+  int status = REVO_DONE, error = 0;
+};
+
+}  // namespace
+
+struct revo_ctx {
+  revo_config cfg;
+  int T = 2, k = 5, J = 3, nframes = 6;
+  Prec prec = P_BF16;
+  ModelW model[2];
+  Workspace ws[2];
+  hipStream_t stream[2] = {nullptr, nullptr};
+  hipStream_t copy = nullptr;
+  std::mutex copy_mu;
+  DevPool pool;
+  std::vector<Ring> rings[2];
+
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Job*> queue;
+  std::deque<revo_completion> done;
+  bool stop = false;
+  std::atomic<unsigned long long> next_ticket{1};
+  std::thread worker;
+  int device_error = 0;
+  double sec_per_unit = 2e-11;  // cost model for shedding (seconds per work unit)
+};
+
+namespace {
+
+const int kMaxQueue = 4096;
+
+double work_units(int N) { return (double)N * N + 2300.0 * N; }
+
+void release_mod(revo_ctx* c, Mod& m, int C) {
+  const size_t px = (size_t)m.H * m.W;
+  if (m.staged) c->pool.put(m.staged, m.frame_bytes);
+  if (m.mask) c->pool.put(m.mask, px);
+  if (m.pred) c->pool.put(m.pred, px * C * 4);
+  if (m.out_i_st) c->pool.put(m.out_i_st, m.frame_bytes);
+  if (m.out_f_st) c->pool.put(m.out_f_st, px * C * 4);
+  m.staged = nullptr; m.mask = nullptr; m.pred = nullptr; m.out_i_st = nullptr; m.out_f_st = nullptr;
+}
+
+void finish(revo_ctx* c, Job* j) {
+  for (int q = 0; q < 2; ++q) release_mod(c, j->mod[q], q == 0 ? 3 : 1);
+  revo_completion rc;
+  rc.ticket = j->ticket;
+  rc.stream_id = j->stream;
+  rc.frame_index = j->frame;
+  rc.status = j->status;
+  rc.error = j->error;
+  rc.submit_ns = j->submit_ns;
+  rc.done_ns = now_ns();
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->done.push_back(rc);
+  }
+  c->cv_done.notify_all();
+  delete j;
+}
+
+// Push a clean frame into its stream's ring on the modality's stream (the
+// ring slot is only read by batches launched earlier on that same stream).
+int push_clean(revo_ctx* c, Job* j, int q) {
+  Mod& m = j->mod[q];
+  Ring& ring = c->rings[q][j->stream];
+  if (ring.H != m.H || ring.W != m.W) {
+    for (auto& f : ring.frames) c->pool.put(f.dev, (size_t)ring.H * ring.W * (q == 0 ? 3 : 2));
+    ring.frames.clear();
+    ring.H = m.H; ring.W = m.W;
+  }
+  RefFrame slot;
+  if ((int)ring.frames.size() >= c->k) {
+    slot = ring.frames.front();
+    ring.frames.pop_front();
+  } else {
+    slot.dev = c->pool.get(m.frame_bytes);
+    if (!slot.dev) return REVO_ENOMEM;
+  }
+  if (hipMemcpyAsync(slot.dev, m.staged, m.frame_bytes, hipMemcpyDeviceToDevice, c->stream[q]) != hipSuccess)
+    return REVO_EDEVICE;
+  slot.index = j->frame;
+  ring.frames.push_back(slot);
+  return 0;
+}
+
+// Fill one kernel descriptor for modality q of job j.
+void fill_desc(revo_ctx* c, Job* j, int q, ReqDesc& d) {
+  Mod& m = j->mod[q];
+  memset(&d, 0, sizeof(d));
+  d.H = m.H; d.W = m.W;
+  d.mask = m.clean ? nullptr : m.mask;
+  d.pred = m.pred;
+  d.out_i = m.out_dev ? m.out_i : m.out_i_st;
+  d.out_f = m.out_dev ? m.out_f : m.out_f_st;
+  if (m.clean) {
+    d.J = 1; d.nframes = 1;
+    d.frames[0] = m.staged;
+    return;
+  }
+  // frames: k references oldest first (the oldest repeated when fewer are
+  // held), padded at the old end to a multiple of T, then the target
+  const Ring& ring = c->rings[q][j->stream];
+  const int have = (int)ring.frames.size();
+  std::vector<RefFrame> seq;
+  for (int i = 0; i < c->k - have; ++i) seq.push_back(ring.frames.front());
+  for (const RefFrame& f : ring.frames) seq.push_back(f);
+  RefFrame tgt;
+  tgt.dev = m.staged;
+  tgt.index = j->frame;
+  seq.push_back(tgt);
+  while ((int)seq.size() % c->T) seq.insert(seq.begin(), seq.front());
+  d.nframes = (int)seq.size();
+  d.J = d.nframes / c->T;
+  for (int i = 0; i < d.nframes; ++i) d.frames[i] = seq[i].dev;
+  for (int jj = 0; jj < d.J; ++jj) d.tau[jj] = (float)(j->frame - seq[jj * c->T].index);
+}
+
+int run_batch(revo_ctx* c, std::vector<Job*>& batch) {
+  // descriptors: per modality, recoveries first, then clean copies
+  std::vector<std::pair<Job*, int>> rec[2], cln[2];
+  for (Job* j : batch) {
+    if (j->status != REVO_DONE) continue;
+    for (int q = 0; q < 2; ++q) {
+      Mod& m = j->mod[q];
+      if (!m.present || m.error) continue;
+      (m.clean ? cln[q] : rec[q]).push_back({j, q});
+    }
+  }
+  int rc = 0;
+  for (int q = 0; q < 2; ++q) {
+    Workspace& w = c->ws[q];
+    int n = 0;
+    for (auto& e : rec[q]) fill_desc(c, e.first, q, w.h_reqs[n++]);
+    const int nrec = n;
+    for (auto& e : cln[q]) fill_desc(c, e.first, q, w.h_reqs[n++]);
+    if (n == 0) continue;
+    int e = forward(c->model[q], w, nrec, n, c->cfg.composite, c->stream[q]);
+    if (e) rc = e;
+  }
+  for (int q = 0; q < 2; ++q)
+    if (hipStreamSynchronize(c->stream[q]) != hipSuccess) rc = REVO_EDEVICE;
+  // host outputs
+  for (Job* j : batch) {
+    if (j->status != REVO_DONE) continue;
+    for (int q = 0; q < 2; ++q) {
+      Mod& m = j->mod[q];
+      if (!m.present || m.error || m.out_dev) continue;
+      const size_t px = (size_t)m.H * m.W;
+      if (m.out_i && hipMemcpy(m.out_i, m.out_i_st, m.frame_bytes, hipMemcpyDeviceToHost) != hipSuccess) rc = REVO_EDEVICE;
+      if (m.out_f && hipMemcpy(m.out_f, m.out_f_st, px * (q == 0 ? 3 : 1) * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        rc = REVO_EDEVICE;
+    }
+  }
+  return rc;
+}
+
+void worker_main(revo_ctx* c) {
+  (void)hipSetDevice(c->cfg.device);
+  const int cap = c->cfg.max_batch_tokens;
+  const int max_batch = c->cfg.max_batch;
+  for (;;) {
+    std::vector<Job*> batch;
+    {
+      std::unique_lock<std::mutex> lk(c->mu);
+      for (;;) {
+        if (c->stop && c->queue.empty()) return;
+        if (!c->queue.empty()) {
+          bool release = c->stop;
+          for (Job* j : c->queue)
+            if (!(j->flags & REVO_HOLD)) { release = true; break; }
+          if (!release && now_ns() - c->queue.front()->submit_ns > 2000000LL) release = true;
+          if (release) break;
+          c->cv_work.wait_for(lk, std::chrono::microseconds(500));
+          continue;
+        }
+        c->cv_work.wait(lk);
+      }
+      // take jobs in order while they fit; stop before a clean frame of a
+      // stream that already has a recovery in this batch
+      int tokens[2] = {0, 0};
+      std::vector<unsigned> rec_streams[2];
+      while (!c->queue.empty() && (int)batch.size() < max_batch) {
+        Job* j = c->queue.front();
+        bool fits = true, conflict = false;
+        int add[2] = {0, 0};
+        for (int q = 0; q < 2; ++q) {
+          const Mod& m = j->mod[q];
+          if (!m.present) continue;
+          if (m.clean) {
+            for (unsigned s : rec_streams[q])
+              if (s == j->stream) conflict = true;
+          } else {
+            add[q] = (request_tokens(m.H, m.W, c->J) + 7) & ~7;  // rows start 8-aligned
+            if (tokens[q] + add[q] > cap) fits = false;
+          }
+        }
+        if (!batch.empty() && (conflict || !fits)) break;
+        c->queue.pop_front();
+        for (int q = 0; q < 2; ++q) {
+          tokens[q] += add[q];
+          if (j->mod[q].present && !j->mod[q].clean) rec_streams[q].push_back(j->stream);
+        }
+        batch.push_back(j);
+      }
+    }
+    c->cv_done.notify_all();  // queue space freed
+
+    // shedding, ring updates and reference checks in submission order
+    const long long t0 = now_ns();
+    double units = 0.0;
+    for (Job* j : batch) {
+      double ju = 0.0;
+      for (int q = 0; q < 2; ++q)
+        if (j->mod[q].present && !j->mod[q].clean) ju += work_units(request_tokens(j->mod[q].H, j->mod[q].W, c->J));
+      if ((c->cfg.flags & REVO_CFG_SHED) && ju > 0.0) {
+        const double finish = (double)t0 + 1e9 * c->sec_per_unit * (units + ju);
+        if ((double)j->deadline < finish) j->status = REVO_SHED;
+      }
+      if (j->status == REVO_DONE) units += ju;
+      for (int q = 0; q < 2; ++q) {
+        Mod& m = j->mod[q];
+        if (!m.present) continue;
+        if (m.clean) {
+          // clean frames always refresh the references, shed or not
+          const int e = push_clean(c, j, q);
+          if (e) { m.error = e; j->status = REVO_FAILED; j->error = e; }
+        } else if (j->status == REVO_DONE) {
+          const Ring& ring = c->rings[q][j->stream];
+          if (ring.frames.empty() || ring.H != m.H || ring.W != m.W) {
+            m.error = REVO_ENOREF; j->status = REVO_FAILED; j->error = REVO_ENOREF;
+            continue;
+          }
+          m.pred = (float*)c->pool.get((size_t)m.H * m.W * (q == 0 ? 3 : 1) * 4);
+          if (!m.pred) { m.error = REVO_ENOMEM; j->status = REVO_FAILED; j->error = REVO_ENOMEM; }
+        }
+      }
+    }
+    const int rc = run_batch(c, batch);
+    const double dt = (now_ns() - t0) * 1e-9;
+    if (units > 0.0 && rc == 0) c->sec_per_unit = 0.8 * c->sec_per_unit + 0.2 * (dt / units);
+    if (rc) {
+      c->device_error = rc;
+      for (Job* j : batch)
+        if (j->status == REVO_DONE) { j->status = REVO_FAILED; j->error = rc; }
+    }
+    for (Job* j : batch) finish(c, j);
+  }
+}
+
+int stage_mod(revo_ctx* c, Mod& m, const void* frame, const unsigned char* mask, void* out_i, float* out_f,
+              int C, int H, int W, bool dev) {
+  const size_t px = (size_t)H * W;
+  m.present = true;
+  m.clean = (mask == nullptr);
+  m.H = H; m.W = W;
+  m.frame_bytes = px * (C == 3 ? 3 : 2);
+  m.out_i = out_i; m.out_f = out_f; m.out_dev = dev;
+  m.staged = c->pool.get(m.frame_bytes);
+  if (!m.staged) return REVO_EAGAIN;
+  const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (hipMemcpyAsync(m.staged, frame, m.frame_bytes, kind, c->copy) != hipSuccess) return REVO_EDEVICE;
+  if (!m.clean) {
+    m.mask = (uint8_t*)c->pool.get(px);
+    if (!m.mask) return REVO_EAGAIN;
+    if (hipMemcpyAsync(m.mask, mask, px, kind, c->copy) != hipSuccess) return REVO_EDEVICE;
+  }
+  if (!dev) {
+    if (out_i && !(m.out_i_st = c->pool.get(m.frame_bytes))) return REVO_EAGAIN;
+    if (out_f && !(m.out_f_st = (float*)c->pool.get(px * C * 4))) return REVO_EAGAIN;
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+void revo_config_default(revo_config* cfg) {
+  if (!cfg) return;
+  memset(cfg, 0, sizeof(*cfg));
+  cfg->precision = REVO_BF16;
+  cfg->k = 5;
+  cfg->tubelet = 2;
+  cfg->composite = 1;
+  cfg->fps = 30.0f;
+}
+
+size_t revo_weight_count(int channels, int tubelet, int enc_depth, int dec_depth) {
+  if ((channels != 1 && channels != 3) || tubelet < 1 || enc_depth < 0 || dec_depth < 0) return 0;
+  return weight_count(channels, tubelet, enc_depth, dec_depth);
+}
+
+const char* revo_strerror(int code) {
+  switch (code) {
+    case REVO_OK: return "ok";
+    case REVO_EAGAIN: return "queue or staging full, poll and retry";
+    case REVO_EINVAL: return "invalid argument";
+    case REVO_ENOMEM: return "out of device memory or HBM budget";
+    case REVO_EDEVICE: return "HIP device error";
+    case REVO_ENOREF: return "no clean reference frame for this stream";
+    case REVO_ENOTSUP: return "unsupported configuration";
+    case REVO_ESHUTDOWN: return "context shutting down";
+  }
+  return "unknown error";
+}
+
+int revo_recover_create(const revo_config* cfg_in, revo_ctx** out) {
+  if (!cfg_in || !out) return REVO_EINVAL;
+  *out = nullptr;
+  revo_config cfg = *cfg_in;
+  if (cfg.precision != REVO_FP32 && cfg.precision != REVO_BF16) return REVO_ENOTSUP;
+  if (cfg.k < 1 || cfg.k > 7 || cfg.tubelet < 1 || cfg.tubelet > 4) return REVO_EINVAL;
+  const int T = cfg.tubelet;
+  const int nframes = (cfg.k + 1 + T - 1) / T * T;
+  if (nframes > REVO_MAX_FRAMES) return REVO_ENOTSUP;
+  if (cfg.enc_depth == 0) cfg.enc_depth = 12;
+  if (cfg.dec_depth == 0) cfg.dec_depth = 4;
+  if (cfg.enc_depth < 0 || cfg.dec_depth < 0 || cfg.enc_depth > 64 || cfg.dec_depth > 64) return REVO_EINVAL;
+  if (cfg.max_streams <= 0) cfg.max_streams = 64;
+  if (cfg.max_batch <= 0) cfg.max_batch = 16;
+  if (cfg.fps <= 0.0f) cfg.fps = 30.0f;
+  if (!cfg.weights_rgb || !cfg.weights_depth) return REVO_EINVAL;
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || cfg.device < 0 || cfg.device >= ndev) return REVO_EDEVICE;
+  if (hipSetDevice(cfg.device) != hipSuccess) return REVO_EDEVICE;
+
+  revo_ctx* c = new revo_ctx();
+  c->cfg = cfg;
+  c->T = T; c->k = cfg.k; c->nframes = nframes; c->J = nframes / T;
+  c->prec = cfg.precision == REVO_BF16 ? P_BF16 : P_FP32;
+  c->rings[0].resize(cfg.max_streams);
+  c->rings[1].resize(cfg.max_streams);
+  int rc = 0;
+  for (int q = 0; q < 2 && !rc; ++q)
+    if (hipStreamCreateWithFlags(&c->stream[q], hipStreamNonBlocking) != hipSuccess) rc = REVO_EDEVICE;
+  if (!rc && hipStreamCreateWithFlags(&c->copy, hipStreamNonBlocking) != hipSuccess) rc = REVO_EDEVICE;
+  if (!rc) rc = model_load(c->model[0], 3, T, cfg.enc_depth, cfg.dec_depth, c->prec, cfg.weights_rgb, cfg.n_weights_rgb, c->stream[0]);
+  if (!rc) rc = model_load(c->model[1], 1, T, cfg.enc_depth, cfg.dec_depth, c->prec, cfg.weights_depth, cfg.n_weights_depth, c->stream[1]);
+  if (!rc) {
+    size_t fixed = c->model[0].bytes + c->model[1].bytes;
+    int cap = cfg.max_batch_tokens;
+    if (cap <= 0) {
+      cap = 43200;
+      if (cfg.hbm_budget_bytes) {
+        // largest capacity whose two workspaces leave a quarter of the budget for rings and staging
+        const double per_tok = (double)(workspace_bytes(c->model[0], 1 << 16, cfg.max_batch) +
+                                        workspace_bytes(c->model[1], 1 << 16, cfg.max_batch)) / (1 << 16);
+        const double avail = 0.75 * (double)cfg.hbm_budget_bytes - (double)fixed;
+        cap = avail > 0 ? (int)std::min(avail / per_tok, 1.0e6) : 0;
+      }
+    }
+    if (cap < 64) rc = REVO_ENOMEM;
+    c->cfg.max_batch_tokens = cap;
+    if (!rc) rc = workspace_alloc(c->ws[0], c->model[0], cap, cfg.max_batch, c->stream[0]);
+    if (!rc) rc = workspace_alloc(c->ws[1], c->model[1], cap, cfg.max_batch, c->stream[1]);
+    fixed += c->ws[0].bytes + c->ws[1].bytes;
+    c->pool.fixed = fixed;
+    c->pool.budget = cfg.hbm_budget_bytes;
+    if (!rc && cfg.hbm_budget_bytes && fixed > cfg.hbm_budget_bytes) rc = REVO_ENOMEM;
+  }
+  if (rc) {
+    revo_recover_destroy(c);
+    return rc < 0 ? rc : REVO_EDEVICE;
+  }
+  c->worker = std::thread(worker_main, c);
+  *out = c;
+  return REVO_OK;
+}
+
+int revo_recover_submit(revo_ctx* c, const revo_request* r, unsigned long long* ticket) {
+  if (!c || !r) return REVO_EINVAL;
+  if (r->stream_id >= (unsigned)c->cfg.max_streams) return REVO_EINVAL;
+  if (r->width < 16 || r->height < 16 || r->width > 4096 || r->height > 4096) return REVO_EINVAL;
+  if (!r->rgb && !r->depth) return REVO_EINVAL;
+  if ((r->mask_rgb && !r->rgb) || (r->mask_depth && !r->depth)) return REVO_EINVAL;
+  if (((request_tokens(r->height, r->width, c->J) + 7) & ~7) > c->cfg.max_batch_tokens) return REVO_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->stop) return REVO_ESHUTDOWN;
+    if ((int)c->queue.size() >= kMaxQueue) return REVO_EAGAIN;
+  }
+  const bool dev = (r->flags & REVO_DEVICE_PTRS) != 0;
+  if (dev) {
+    // every device pointer must belong to the device (host memory would fault the kernels)
+    const void* ptrs[] = {r->rgb, r->mask_rgb, r->depth, r->mask_depth, r->rgb_out, r->depth_out, r->rgb_out_f32,
+                          r->depth_out_f32};
+    for (const void* p : ptrs)
+      if (p && !is_device_ptr(p)) return REVO_EINVAL;
+  }
+  Job* j = new Job();
+  j->stream = r->stream_id;
+  j->frame = r->frame_index;
+  j->flags = r->flags;
+  j->submit_ns = now_ns();
+  j->deadline = r->deadline_ns ? r->deadline_ns : j->submit_ns + (long long)(1e9 / c->cfg.fps);
+  int rc = 0;
+  {
+    std::lock_guard<std::mutex> lk(c->copy_mu);
+    (void)hipSetDevice(c->cfg.device);
+    if (r->rgb) rc = stage_mod(c, j->mod[0], r->rgb, r->mask_rgb, r->rgb_out, r->rgb_out_f32, 3, r->height, r->width, dev);
+    if (!rc && r->depth)
+      rc = stage_mod(c, j->mod[1], r->depth, r->mask_depth, r->depth_out, r->depth_out_f32, 1, r->height, r->width, dev);
+    if (hipStreamSynchronize(c->copy) != hipSuccess && !rc) rc = REVO_EDEVICE;
+  }
+  if (rc) {
+    for (int q = 0; q < 2; ++q) release_mod(c, j->mod[q], q == 0 ? 3 : 1);
+    delete j;
+    return rc;
+  }
+  j->ticket = c->next_ticket++;
+  if (ticket) *ticket = j->ticket;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->queue.push_back(j);
+  }
+  c->cv_work.notify_one();
+  return REVO_OK;
+}
+
+int revo_recover_poll(revo_ctx* c, revo_completion* out, int max, int timeout_us) {
+  if (!c || (!out && max > 0) || max < 0) return REVO_EINVAL;
+  std::unique_lock<std::mutex> lk(c->mu);
+  auto ready = [&] { return !c->done.empty(); };
+  if (timeout_us < 0) c->cv_done.wait(lk, ready);
+  else if (timeout_us > 0) c->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready);
+  int n = 0;
+  while (n < max && !c->done.empty()) {
+    out[n++] = c->done.front();
+    c->done.pop_front();
+  }
+  return n;
+}
+
+void revo_recover_destroy(revo_ctx* c) {
+  if (!c) return;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->stop = true;
+  }
+  c->cv_work.notify_all();
+  if (c->worker.joinable()) c->worker.join();
+  (void)hipSetDevice(c->cfg.device);
+  for (int q = 0; q < 2; ++q) {
+    if (c->stream[q]) (void)hipStreamSynchronize(c->stream[q]);
+    for (Ring& ring : c->rings[q])
+      for (auto& f : ring.frames) c->pool.put(f.dev, (size_t)ring.H * ring.W * (q == 0 ? 3 : 2));
+    workspace_free(c->ws[q]);
+    model_free(c->model[q]);
+  }
+  c->pool.clear();
+  for (int q = 0; q < 2; ++q)
+    if (c->stream[q]) (void)hipStreamDestroy(c->stream[q]);
+  if (c->copy) (void)hipStreamDestroy(c->copy);
+  delete c;
+}
+
+}  // extern "C"

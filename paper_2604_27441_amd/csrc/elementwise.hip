@@ -1,0 +1,152 @@
+// Row LayerNorm, the loss-mask composite and small conversion kernels.
+#include "kernels.h"
+
+namespace revo {
+
+namespace {
+
+// One wave per row: FP32 mean and biased variance over D features (D <= 512),
+// then (x - mean) / sqrt(var + 1e-6) * g + b, stored as the next product's
+// operand type.  With reqs set, output row i is request r's target-tubelet
+// token i - head_off (rows of the last tubelet only, for the head).
+template <class T>
+__global__ __launch_bounds__(256) void layernorm_kernel(const float* __restrict__ x, const float* __restrict__ g,
+                                                        const float* __restrict__ b, T* __restrict__ y, int rows,
+                                                        int D, const ReqDesc* reqs, int nreq) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  int src = row;
+  if (reqs) {
+    const int r = find_req_head(reqs, nreq, row);
+    const ReqDesc& d = reqs[r];
+    src = d.tok_off + (d.J - 1) * d.P + (row - d.head_off);
+  }
+  const float* xr = x + (size_t)src * D;
+  float v[8];
+  float s = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int c = lane + 64 * i;
+    v[i] = c < D ? xr[c] : 0.0f;
+    s += v[i];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  const float mean = s / (float)D;
+  float q = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int c = lane + 64 * i;
+    const float t = c < D ? v[i] - mean : 0.0f;
+    q += t * t;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o);
+  const float rstd = 1.0f / sqrtf(q / (float)D + 1e-6f);
+  T* yr = y + (size_t)row * D;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int c = lane + 64 * i;
+    if (c < D) yr[c] = (T)((v[i] - mean) * rstd * g[c] + b[c]);
+  }
+}
+
+// Final frame of one request: lost pixels take the clamped prediction
+// (RGB in [0, 1], depth in [0, 65535] mm) quantised half-to-even, received
+// pixels are copied unchanged.  A request without a mask is a clean frame
+// and is copied; composite == 0 gives every pixel the prediction.
+__global__ __launch_bounds__(256) void composite_kernel(const ReqDesc* __restrict__ reqs, int C, int composite) {
+  const ReqDesc& d = reqs[blockIdx.y];
+  const int npix = d.H * d.W;
+  const int pix = blockIdx.x * 256 + threadIdx.x;
+  if (pix >= npix) return;
+  const bool lost = d.mask != nullptr && (composite == 0 || d.mask[pix] != 0);
+  const void* recv = d.frames[d.nframes - 1];
+  if (C == 3) {
+    const uint8_t* rv = (const uint8_t*)recv + (size_t)pix * 3;
+    uint8_t* oi = (uint8_t*)d.out_i;
+    float* of = d.out_f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const size_t e = (size_t)pix * 3 + c;
+      if (lost) {
+        const float p = fminf(fmaxf(d.pred[e], 0.0f), 1.0f);
+        if (of) of[e] = p;
+        if (oi) oi[e] = (uint8_t)rintf(255.0f * p);
+      } else {
+        const uint8_t u = rv[c];
+        if (of) of[e] = (float)u / 255.0f;
+        if (oi) oi[e] = u;
+      }
+    }
+  } else {
+    const uint16_t* rv = (const uint16_t*)recv;
+    uint16_t* oi = (uint16_t*)d.out_i;
+    if (lost) {
+      const float p = fminf(fmaxf(4000.0f * d.pred[pix], 0.0f), 65535.0f);
+      if (d.out_f) d.out_f[pix] = p;
+      if (oi) oi[pix] = (uint16_t)rintf(p);
+    } else {
+      const uint16_t u = rv[pix];
+      if (d.out_f) d.out_f[pix] = (float)u;
+      if (oi) oi[pix] = u;
+    }
+  }
+}
+
+template <class T>
+__global__ void convert_kernel(const float* __restrict__ src, T* __restrict__ dst, long long n) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = (T)src[i];
+}
+
+__global__ void zero_kernel(uint4* __restrict__ p, long long n16) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n16) p[i] = make_uint4(0, 0, 0, 0);
+}
+
+__global__ void zero_tail_kernel(uint8_t* __restrict__ p, long long n) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+}  // namespace
+
+int launch_layernorm(Prec out_prec, const float* x, const float* g, const float* b, void* y, int rows, int D,
+                     const ReqDesc* reqs, int nreq, hipStream_t s) {
+  if (rows <= 0) return 0;
+  if (D > 512) return -22;
+  dim3 grid(cdiv(rows, 4));
+  if (out_prec == P_BF16) layernorm_kernel<__bf16><<<grid, 256, 0, s>>>(x, g, b, (__bf16*)y, rows, D, reqs, nreq);
+  else layernorm_kernel<float><<<grid, 256, 0, s>>>(x, g, b, (float*)y, rows, D, reqs, nreq);
+  return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+int launch_composite(const ReqDesc* reqs, int nreq, int channels, int max_pixels, int composite, hipStream_t s) {
+  if (nreq <= 0 || max_pixels <= 0) return 0;
+  composite_kernel<<<dim3(cdiv(max_pixels, 256), nreq), 256, 0, s>>>(reqs, channels, composite);
+  return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+int launch_convert(Prec prec, const float* src, void* dst, long long n, hipStream_t s) {
+  if (n <= 0) return 0;
+  const unsigned blocks = (unsigned)cdivll(n, 256);
+  if (prec == P_BF16) convert_kernel<__bf16><<<blocks, 256, 0, s>>>(src, (__bf16*)dst, n);
+  else if (prec == P_FP32) convert_kernel<float><<<blocks, 256, 0, s>>>(src, (float*)dst, n);
+  else return -95;
+  return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+int launch_fill_zero(void* p, long long bytes, hipStream_t s) {
+  if (bytes <= 0) return 0;
+  const long long n16 = bytes / 16;
+  if ((reinterpret_cast<uintptr_t>(p) & 15) == 0 && n16 > 0)
+    zero_kernel<<<(unsigned)cdivll(n16, 256), 256, 0, s>>>((uint4*)p, n16);
+  const long long done = ((reinterpret_cast<uintptr_t>(p) & 15) == 0) ? n16 * 16 : 0;
+  if (bytes > done)
+    zero_tail_kernel<<<(unsigned)cdivll(bytes - done, 256), 256, 0, s>>>((uint8_t*)p + done, bytes - done);
+  return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+}  // namespace revo

@@ -1,0 +1,320 @@
+// MFMA GEMM for every linear step of the recovery network, with the
+// tubelet-embedding gather fused into its operand loader and the bias /
+// GELU / residual / positional-embedding / head-split / unpatchify work fused
+// into its epilogue.
+//
+// Product: C^T[n][m] = sum_k W[n][k] * X[m][k] (weights [out][in], tokens
+// [M][K], both K-contiguous).  Weights feed the MFMA's A operand and tokens
+// its B operand, so each lane ends up owning one token and runs of four
+// consecutive output features: epilogue stores are 8/16-byte row segments.
+//
+// Tile: 128 tokens x BN features x one 128-byte K stage per operand row,
+// 4 waves in a 2 x 2 grid, LDS double-buffered (pitch padded to 144 bytes).
+#include "kernels.h"
+
+namespace revo {
+
+namespace {
+
+constexpr int BM = 128;
+constexpr int NT = 256;
+constexpr int PITCH_B = 144;
+
+template <class T> struct Vec4;
+template <> struct Vec4<float> {
+  __device__ static void store(float* p, const float v[4]) {
+    *reinterpret_cast<f32x4*>(p) = f32x4{v[0], v[1], v[2], v[3]};
+  }
+};
+template <> struct Vec4<__bf16> {
+  __device__ static void store(__bf16* p, const float v[4]) {
+    *reinterpret_cast<bf16x4*>(p) = bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+  }
+};
+
+template <class Op> __device__ inline typename Op::frag frag_of(const uint4& u, int g);
+template <> __device__ inline float frag_of<OpF32>(const uint4& u, int g) {
+  const uint32_t w = g == 0 ? u.x : g == 1 ? u.y : g == 2 ? u.z : u.w;
+  return __uint_as_float(w);
+}
+template <> __device__ inline bf16x8 frag_of<OpBF16>(const uint4& u, int) {
+  return __builtin_bit_cast(bf16x8, u);
+}
+
+__device__ inline float gelu_erf(float v) { return 0.5f * v * (1.0f + erff(v * 0.70710678118654752f)); }
+
+// Sinusoid of the three-axis positional embedding: column c of a D-wide
+// embedding for position s (axis c / (D/3)), sin at even, cos at odd columns.
+__device__ inline float pe_value(float s, int c, int d3) {
+  const int i2 = (c % d3) >> 1;
+  const float freq = exp2f(-(float)(2 * i2) / (float)d3 * 13.287712379549449f);  // log2(10000)
+  float sn, cs;
+  sincosf(s * freq, &sn, &cs);
+  return (c & 1) ? cs : sn;
+}
+
+// One 16-byte chunk (E elements) of a tubelet vector: element k of token
+// (j, y, x) is frame j*T + t, pixel (16y + py, 16x + px), channel c with
+// k = ((t*16 + py)*16 + px)*C + c.  Out-of-frame (padding) pixels and lost
+// target pixels read as zero; RGB is scaled by 1/255 and depth by 1/4000 mm.
+template <class Op>
+__device__ uint4 gather_chunk(const ReqDesc& d, int j, int y, int x, int k, int C) {
+  typedef typename Op::T T;
+  constexpr int E = 16 / sizeof(T);
+  union { uint4 u; T v[E]; } r;
+  const int rowlen = 16 * C;
+  const int rt = k / rowlen;
+  const int o = k - rt * rowlen;
+  const int Tt = d.nframes / d.J;
+  const int f = j * Tt + (rt >> 4);
+  const int Y = 16 * y + (rt & 15);
+  const bool target = (f == d.nframes - 1);
+  const int X0 = 16 * x;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int oe = o + e;
+    const int X = X0 + oe / C;
+    const int c = oe - (oe / C) * C;
+    float v = 0.0f;
+    if (Y < d.H && X < d.W) {
+      const size_t pix = (size_t)Y * d.W + X;
+      if (!(target && d.mask[pix])) {
+        if (C == 3) v = (float)((const uint8_t*)d.frames[f])[pix * 3 + c] / 255.0f;
+        else v = (float)((const uint16_t*)d.frames[f])[pix] / 4000.0f;
+      }
+    }
+    r.v[e] = Op::from_float(v);
+  }
+  return r.u;
+}
+
+template <class Op, int BN, int EPI, int XM>
+__global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
+  typedef typename Op::T T;
+  constexpr int BK = Op::BK;
+  constexpr int E = 16 / sizeof(T);
+  constexpr int PITCH = PITCH_B / sizeof(T);
+  constexpr int XC = BM * 8 / NT;
+  constexpr int WC = BN * 8 / NT;
+  constexpr int NSUB = BN / 64;
+  constexpr int G = 16 / (Op::KPL * sizeof(T));
+  constexpr int STEPS = BK / (2 * Op::KPL);
+  __shared__ __attribute__((aligned(16))) T xs[2][BM * PITCH];
+  __shared__ __attribute__((aligned(16))) T ws[2][BN * PITCH];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int half = lane >> 5, l32 = lane & 31;
+  const int m0 = blockIdx.x * BM;
+  const int n0 = blockIdx.y * BN;
+  const int KT = a.K / BK;
+  const T* __restrict__ W = (const T*)a.W;
+  const T* __restrict__ X = (const T*)a.X;
+
+  // gather: token coordinates of this thread's rows
+  int g_req[XC], g_j[XC], g_y[XC], g_x[XC];
+  if (XM == X_GATHER) {
+#pragma unroll
+    for (int i = 0; i < XC; ++i) {
+      const int m = m0 + ((tid + i * NT) >> 3);
+      g_req[i] = -1;
+      if (m < a.M) {
+        const int r = find_req_tok(a.reqs, a.nreq, m);
+        const ReqDesc& d = a.reqs[r];
+        const int t = m - d.tok_off;
+        const int j = t / d.P, p = t - (t / d.P) * d.P;
+        // rows past the request's J * P tokens are alignment gaps: zero
+        if (j < d.J) { g_req[i] = r; g_j[i] = j; g_y[i] = p / d.gx; g_x[i] = p - (p / d.gx) * d.gx; }
+      }
+    }
+  }
+
+  uint4 xr[XC], wr[WC];
+  auto load_stage = [&](int kt) {
+    const int k0 = kt * BK;
+#pragma unroll
+    for (int i = 0; i < XC; ++i) {
+      const int c = tid + i * NT, row = c >> 3, kc = c & 7;
+      const int m = m0 + row;
+      if (XM == X_DENSE) {
+        xr[i] = m < a.M ? *reinterpret_cast<const uint4*>(X + (size_t)m * a.K + k0 + kc * E)
+                        : make_uint4(0, 0, 0, 0);
+      } else {
+        xr[i] = g_req[i] >= 0 ? gather_chunk<Op>(a.reqs[g_req[i]], g_j[i], g_y[i], g_x[i], k0 + kc * E, a.channels)
+                              : make_uint4(0, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < WC; ++i) {
+      const int c = tid + i * NT, row = c >> 3, kc = c & 7;
+      wr[i] = *reinterpret_cast<const uint4*>(W + (size_t)(n0 + row) * a.K + k0 + kc * E);
+    }
+  };
+  auto store_stage = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < XC; ++i) {
+      const int c = tid + i * NT, row = c >> 3, kc = c & 7;
+      *reinterpret_cast<uint4*>(&xs[buf][row * PITCH + kc * E]) = xr[i];
+    }
+#pragma unroll
+    for (int i = 0; i < WC; ++i) {
+      const int c = tid + i * NT, row = c >> 3, kc = c & 7;
+      *reinterpret_cast<uint4*>(&ws[buf][row * PITCH + kc * E]) = wr[i];
+    }
+  };
+
+  const int wn = wave >> 1, wm = wave & 1;
+  f32x16 acc[NSUB][2];
+#pragma unroll
+  for (int i = 0; i < NSUB; ++i) { acc[i][0] = f32x16{}; acc[i][1] = f32x16{}; }
+
+  load_stage(0);
+  store_stage(0);
+  __syncthreads();
+  for (int kt = 0; kt < KT; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < KT) load_stage(kt + 1);
+#pragma unroll
+    for (int s = 0; s < STEPS; s += G) {
+      const int koff = half * (BK / 2) + s * Op::KPL;
+      uint4 wf[NSUB], xf[2];
+#pragma unroll
+      for (int ns = 0; ns < NSUB; ++ns)
+        wf[ns] = *reinterpret_cast<const uint4*>(&ws[buf][(wn * (BN / 2) + ns * 32 + l32) * PITCH + koff]);
+#pragma unroll
+      for (int ms = 0; ms < 2; ++ms)
+        xf[ms] = *reinterpret_cast<const uint4*>(&xs[buf][(wm * 64 + ms * 32 + l32) * PITCH + koff]);
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int ns = 0; ns < NSUB; ++ns)
+#pragma unroll
+          for (int ms = 0; ms < 2; ++ms)
+            Op::mma(acc[ns][ms], frag_of<Op>(wf[ns], g), frag_of<Op>(xf[ms], g));
+    }
+    if (kt + 1 < KT) store_stage(buf ^ 1);
+    __syncthreads();
+  }
+
+  // ---------------------------------------------------------------- epilogue
+#pragma unroll
+  for (int ms = 0; ms < 2; ++ms) {
+    const int m = m0 + wm * 64 + ms * 32 + l32;
+    if (m >= a.M) continue;
+    int r = 0, tj = 0, ty = 0, tx = 0;
+    if (EPI == EPI_PE) {
+      r = find_req_tok(a.reqs, a.nreq, m);
+      const ReqDesc& d = a.reqs[r];
+      const int t = m - d.tok_off;
+      tj = t / d.P;
+      const int p = t - tj * d.P;
+      ty = p / d.gx; tx = p - ty * d.gx;
+    } else if (EPI == EPI_HEAD) {
+      r = find_req_head(a.reqs, a.nreq, m);
+      const ReqDesc& d = a.reqs[r];
+      const int p = m - d.head_off;
+      ty = p / d.gx; tx = p - ty * d.gx;
+    }
+#pragma unroll
+    for (int ns = 0; ns < NSUB; ++ns) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int n = n0 + wn * (BN / 2) + ns * 32 + g * 8 + half * 4;
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = acc[ns][ms][4 * g + e] + a.bias[n + e];
+        if (EPI == EPI_STORE) {
+          Vec4<T>::store((T*)a.out + (size_t)m * a.ldo + n, v);
+        } else if (EPI == EPI_GELU) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = gelu_erf(v[e]);
+          Vec4<T>::store((T*)a.out + (size_t)m * a.ldo + n, v);
+        } else if (EPI == EPI_RESIDUAL) {
+          float* p = (float*)a.out + (size_t)m * a.ldo + n;
+          f32x4 old = *reinterpret_cast<f32x4*>(p);
+          *reinterpret_cast<f32x4*>(p) = f32x4{old[0] + v[0], old[1] + v[1], old[2] + v[2], old[3] + v[3]};
+        } else if (EPI == EPI_PE) {
+          const ReqDesc& d = a.reqs[r];
+          const int d3 = a.N / 3;
+          const int axis = n / d3;
+          const float s = axis == 0 ? (tj < d.J ? d.tau[tj] : 0.0f) : axis == 1 ? (float)ty : (float)tx;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] += pe_value(s, n + e, d3);
+          float* p = (float*)a.out + (size_t)m * a.ldo + n;
+          *reinterpret_cast<f32x4*>(p) = f32x4{v[0], v[1], v[2], v[3]};
+        } else if (EPI == EPI_QKV) {
+          const int D = a.heads * 64;
+          const int part = n / D, hd = (n % D) >> 6, dd = n & 63;
+          if (part == 0) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] *= a.qscale;
+            Vec4<T>::store((T*)a.q + ((size_t)hd * a.ldqk + m) * 64 + dd, v);
+          } else if (part == 1) {
+            Vec4<T>::store((T*)a.k + ((size_t)hd * a.ldqk + m) * 64 + dd, v);
+          } else {
+            T* vt = (T*)a.vt + ((size_t)hd * 64 + dd) * a.ldv + m;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) vt[(size_t)e * a.ldv] = Op::from_float(v[e]);
+          }
+        } else if (EPI == EPI_HEAD) {
+          const ReqDesc& d = a.reqs[r];
+          const int C = a.channels;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int c = n + e;
+            const int py = c / (16 * C);
+            const int px = (c / C) & 15;
+            const int ch = c - (c / C) * C;
+            const int Y = 16 * ty + py, Xp = 16 * tx + px;
+            if (Y < d.H && Xp < d.W) d.pred[((size_t)Y * d.W + Xp) * C + ch] = v[e];
+          }
+        }
+      }
+    }
+  }
+}
+
+template <class Op, int EPI, int XM>
+int launch_t(const GemmArgs& a, hipStream_t s) {
+  const int gm = cdiv(a.M, BM);
+  if (a.N % 128 == 0) {
+    gemm_kernel<Op, 128, EPI, XM><<<dim3(gm, a.N / 128), NT, 0, s>>>(a);
+  } else {
+    gemm_kernel<Op, 64, EPI, XM><<<dim3(gm, a.N / 64), NT, 0, s>>>(a);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+template <class Op>
+int launch_op(int epi, int xmode, const GemmArgs& a, hipStream_t s) {
+  if (xmode == X_GATHER) {
+    if (epi != EPI_PE) return -22;
+    return launch_t<Op, EPI_PE, X_GATHER>(a, s);
+  }
+  switch (epi) {
+    case EPI_STORE: return launch_t<Op, EPI_STORE, X_DENSE>(a, s);
+    case EPI_RESIDUAL: return launch_t<Op, EPI_RESIDUAL, X_DENSE>(a, s);
+    case EPI_GELU: return launch_t<Op, EPI_GELU, X_DENSE>(a, s);
+    case EPI_QKV: return launch_t<Op, EPI_QKV, X_DENSE>(a, s);
+    case EPI_PE: return launch_t<Op, EPI_PE, X_DENSE>(a, s);
+    case EPI_HEAD: return launch_t<Op, EPI_HEAD, X_DENSE>(a, s);
+  }
+  return -22;
+}
+
+}  // namespace
+
+int launch_gemm(Prec prec, int epi, int xmode, const GemmArgs& a, hipStream_t s) {
+  if (a.M <= 0) return 0;
+  if (a.N % 64 != 0) return -22;
+  if (prec == P_BF16) {
+    if (a.K % OpBF16::BK != 0) return -22;
+    return launch_op<OpBF16>(epi, xmode, a, s);
+  }
+  if (prec == P_FP32) {
+    if (a.K % OpF32::BK != 0) return -22;
+    return launch_op<OpF32>(epi, xmode, a, s);
+  }
+  return -95;
+}
+
+}  // namespace revo

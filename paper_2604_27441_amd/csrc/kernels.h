@@ -1,0 +1,98 @@
+// Device-side request descriptors and host launchers of the recovery kernels.
+#pragma once
+#include "common.h"
+
+#define REVO_MAX_FRAMES 8
+#define REVO_PATCH 16
+
+namespace revo {
+
+// One request of a batch, as the kernels see it (lives in device memory).
+// Token rows of request r are [tok_off, tok_off + J * P): tubelet j, patch
+// row y, column x sits at tok_off + j * P + y * gx + x.
+struct ReqDesc {
+  int tok_off;          // first token row in the batch
+  int head_off;         // first row in the compact target-tubelet buffer
+  int H, W;             // frame size in pixels
+  int gy, gx, P;        // patch grid: ceil(H/16), ceil(W/16), gy * gx
+  int J;                // tubelets per request
+  int nframes;          // J * T frames, oldest first, the target last
+  int pad_;
+  float tau[REVO_MAX_FRAMES];           // temporal distance of tubelet j
+  const void* frames[REVO_MAX_FRAMES];  // u8 HWC (C = 3) or u16 HW (C = 1)
+  const uint8_t* mask;                  // target loss mask, H * W, 1 = lost
+  float* pred;                          // H * W * C prediction, model units
+  void* out_i;                          // u8 HWC / u16 HW output (nullable)
+  float* out_f;                         // float output (nullable)
+};
+
+// GEMM epilogues.  The product is C^T[n][m] = sum_k W[n][k] X[m][k].
+enum EpiMode {
+  EPI_STORE = 0,     // out[m][n] = acc + bias[n]                (OutT)
+  EPI_RESIDUAL = 1,  // res[m][n] += acc + bias[n]               (fp32)
+  EPI_GELU = 2,      // out[m][n] = gelu(acc + bias[n])          (OutT)
+  EPI_QKV = 3,       // q/k [h][m][64] (q scaled), vt [h][64][ldv]
+  EPI_PE = 4,        // out[m][n] = acc + bias[n] + PE(token m, n)  (fp32)
+  EPI_HEAD = 5,      // pred pixel of compact target row m, slot column n
+};
+
+enum XMode {
+  X_DENSE = 0,       // X [M][K] row-major
+  X_GATHER = 1,      // tubelet vectors gathered from the request's frames
+};
+
+struct GemmArgs {
+  int M, N, K;
+  const void* X;     // X_DENSE: [M][K] operand elements
+  const void* W;     // [N][K] operand elements
+  const float* bias; // [N]
+  void* out;         // EPI_STORE / GELU / PE: [M][ldo]; RESIDUAL: fp32 [M][ldo]
+  int ldo;
+  // EPI_QKV
+  void* q; void* k; void* vt; int heads; int ldqk; int ldv; float qscale;
+  // gather / PE / head
+  const ReqDesc* reqs; int nreq; int channels;
+};
+
+struct AttnArgs {
+  const void* q;     // [heads][ldqk rows][64], pre-scaled by log2(e)/sqrt(64)
+  const void* k;     // [heads][ldqk rows][64]
+  const void* vt;    // [heads][64][ldv]
+  void* o;           // [M][heads * 64]
+  int heads, ldqk, ldv;
+  const ReqDesc* reqs; int nreq;
+  const int* work;   // per workgroup: (request << 16) | q-tile
+  int nwork;
+};
+
+int launch_gemm(Prec prec, int epi, int xmode, const GemmArgs& a, hipStream_t s);
+int launch_attention(Prec prec, const AttnArgs& a, hipStream_t s);
+// y = LN(x) * g + b over rows of length D.  With reqs set, output row i is
+// the target-tubelet token (i - head_off) of the request owning compact row i.
+int launch_layernorm(Prec out_prec, const float* x, const float* g, const float* b,
+                     void* y, int rows, int D, const ReqDesc* reqs, int nreq, hipStream_t s);
+// Output frames.  Requests with a null mask are clean frames (copied).  With
+// composite == 0 every pixel of a recovered frame takes the prediction.
+int launch_composite(const ReqDesc* reqs, int nreq, int channels, int max_pixels, int composite, hipStream_t s);
+int launch_convert(Prec prec, const float* src, void* dst, long long n, hipStream_t s);
+int launch_fill_zero(void* p, long long bytes, hipStream_t s);
+
+// row -> request lookup over the ascending tok_off (or head_off) values
+__device__ inline int find_req_tok(const ReqDesc* r, int n, int m) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (r[mid].tok_off <= m) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+__device__ inline int find_req_head(const ReqDesc* r, int n, int m) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (r[mid].head_off <= m) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace revo

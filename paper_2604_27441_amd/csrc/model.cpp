@@ -1,0 +1,217 @@
+// Weights upload, workspace sizing and the launch sequence of the recovery
+// network (Sec. 3.4.1: tubelet embedding, encoder, decoder over all tokens,
+// reconstruction of the target frame; App. B.1: no token shuffling).
+#include "model.h"
+
+#include <string.h>
+
+namespace revo {
+
+namespace {
+
+size_t esize(Prec p) { return p == P_BF16 ? 2 : 4; }
+
+size_t block_count(int D) { return 2 * D + 3 * D * D + 3 * D + D * D + D + 2 * D + 4 * D * D + 4 * D + 4 * D * D + D; }
+
+}  // namespace
+
+size_t weight_count(int C, int T, int ne, int nd) {
+  const size_t L = (size_t)T * 256 * C;
+  const size_t De = 384, Dd = 192;
+  return De * L + De + ne * block_count(De) + 2 * De + Dd * De + Dd + nd * block_count(Dd) + 2 * Dd + L * Dd + L;
+}
+
+int model_load(ModelW& m, int C, int T, int ne, int nd, Prec p, const float* host_blob, size_t n, hipStream_t s) {
+  m.C = C; m.T = T; m.ne = ne; m.nd = nd; m.prec = p;
+  m.count = weight_count(C, T, ne, nd);
+  if (n != m.count || !host_blob) return -22;
+  REVO_HIP_TRY(hipMalloc(&m.master, m.count * 4));
+  REVO_HIP_TRY(hipMemcpy(m.master, host_blob, m.count * 4, hipMemcpyHostToDevice));
+  REVO_HIP_TRY(hipMalloc(&m.ops, m.count * esize(p)));
+  m.bytes = m.count * (4 + esize(p));
+  int rc = launch_convert(p, m.master, m.ops, (long long)m.count, s);
+  if (rc) return rc;
+  REVO_HIP_TRY(hipStreamSynchronize(s));
+
+  size_t pos = 0;
+  auto mat = [&](size_t rows, size_t cols) {
+    const void* q = (const char*)m.ops + pos * esize(p);
+    pos += rows * cols;
+    return q;
+  };
+  auto vec = [&](size_t len) {
+    const float* q = m.master + pos;
+    pos += len;
+    return q;
+  };
+  auto block = [&](int D) {
+    BlockW b;
+    b.ln1_g = vec(D); b.ln1_b = vec(D);
+    b.qkv_w = mat(3 * D, D); b.qkv_b = vec(3 * D);
+    b.proj_w = mat(D, D); b.proj_b = vec(D);
+    b.ln2_g = vec(D); b.ln2_b = vec(D);
+    b.fc1_w = mat(4 * D, D); b.fc1_b = vec(4 * D);
+    b.fc2_w = mat(D, 4 * D); b.fc2_b = vec(D);
+    return b;
+  };
+  const int L = m.tub_len();
+  m.emb_w = mat(m.De, L); m.emb_b = vec(m.De);
+  m.enc.clear();
+  for (int i = 0; i < ne; ++i) m.enc.push_back(block(m.De));
+  m.enc_g = vec(m.De); m.enc_b = vec(m.De);
+  m.e2d_w = mat(m.Dd, m.De); m.e2d_b = vec(m.Dd);
+  m.dec.clear();
+  for (int i = 0; i < nd; ++i) m.dec.push_back(block(m.Dd));
+  m.dec_g = vec(m.Dd); m.dec_b = vec(m.Dd);
+  m.head_w = mat(L, m.Dd); m.head_b = vec(L);
+  return pos == m.count ? 0 : -22;
+}
+
+void model_free(ModelW& m) {
+  if (m.master) (void)hipFree(m.master);
+  if (m.ops) (void)hipFree(m.ops);
+  m.master = nullptr; m.ops = nullptr;
+}
+
+int request_tokens(int H, int W, int J) { return J * cdiv(H, REVO_PATCH) * cdiv(W, REVO_PATCH); }
+
+size_t workspace_bytes(const ModelW& m, int cap, int max_req) {
+  const size_t e = esize(m.prec);
+  const size_t ld = (size_t)cap + 64;
+  const size_t De = m.De;
+  size_t b = 0;
+  b += (size_t)cap * De * 4;             // h
+  b += (size_t)cap * De * e;             // a
+  b += 2 * (size_t)m.He * ld * 64 * e;   // q, k
+  b += (size_t)m.He * 64 * ld * e;       // vt
+  b += (size_t)cap * De * e;             // o
+  b += (size_t)cap * 4 * De * e;         // hid
+  b += (size_t)cap * m.Dd * 4;           // z
+  b += (size_t)cap * m.Dd * e;           // ahead (target rows <= cap)
+  b += (size_t)max_req * sizeof(ReqDesc) + (size_t)(cap / 128 + max_req + 1) * 4;
+  return b + 16 * 256;
+}
+
+int workspace_alloc(Workspace& w, const ModelW& m, int cap, int max_req, hipStream_t s) {
+  w.cap = cap; w.head_cap = cap; w.ld = cap + 64; w.max_req = max_req; w.prec = m.prec;
+  w.max_work = cap / 128 + max_req + 1;
+  const size_t e = esize(m.prec);
+  const size_t De = m.De;
+  auto get = [&](void** p, size_t bytes) -> int {
+    REVO_HIP_TRY(hipMalloc(p, bytes));
+    w.bytes += bytes;
+    return launch_fill_zero(*p, (long long)bytes, s);
+  };
+  int rc = 0;
+  rc |= get((void**)&w.h, (size_t)cap * De * 4);
+  rc |= get(&w.a, (size_t)cap * De * e);
+  rc |= get(&w.q, (size_t)m.He * w.ld * 64 * e);
+  rc |= get(&w.k, (size_t)m.He * w.ld * 64 * e);
+  rc |= get(&w.vt, (size_t)m.He * 64 * w.ld * e);
+  rc |= get(&w.o, (size_t)cap * De * e);
+  rc |= get(&w.hid, (size_t)cap * 4 * De * e);
+  rc |= get((void**)&w.z, (size_t)cap * m.Dd * 4);
+  rc |= get(&w.ahead, (size_t)cap * m.Dd * e);
+  rc |= get((void**)&w.d_reqs, (size_t)max_req * sizeof(ReqDesc));
+  rc |= get((void**)&w.d_work, (size_t)w.max_work * 4);
+  if (rc) return rc < 0 ? rc : -5;
+  REVO_HIP_TRY(hipHostMalloc((void**)&w.h_reqs, (size_t)max_req * sizeof(ReqDesc), hipHostMallocDefault));
+  REVO_HIP_TRY(hipHostMalloc((void**)&w.h_work, (size_t)w.max_work * 4, hipHostMallocDefault));
+  memset(w.h_reqs, 0, (size_t)max_req * sizeof(ReqDesc));
+  REVO_HIP_TRY(hipStreamSynchronize(s));
+  return 0;
+}
+
+void workspace_free(Workspace& w) {
+  void* dev[] = {w.h, w.a, w.q, w.k, w.vt, w.o, w.hid, w.z, w.ahead, w.d_reqs, w.d_work};
+  for (void* p : dev)
+    if (p) (void)hipFree(p);
+  if (w.h_reqs) (void)hipHostFree(w.h_reqs);
+  if (w.h_work) (void)hipHostFree(w.h_work);
+  w = Workspace();
+}
+
+int forward(const ModelW& m, Workspace& w, int nrec, int nall, int composite, hipStream_t s) {
+  if (nall <= 0) return 0;
+  if (nall > w.max_req || nrec > nall) return -22;
+  // token and head-row offsets, attention work list
+  int M = 0, Mh = 0, nwork = 0, max_pix = 0;
+  for (int r = 0; r < nall; ++r) {
+    ReqDesc& d = w.h_reqs[r];
+    d.gy = cdiv(d.H, REVO_PATCH);
+    d.gx = cdiv(d.W, REVO_PATCH);
+    d.P = d.gy * d.gx;
+    if (d.H * d.W > max_pix) max_pix = d.H * d.W;
+    if (r >= nrec) { d.tok_off = M; d.head_off = Mh; continue; }
+    M = (M + 7) & ~7;  // 16-byte aligned V^T columns for every request
+    d.tok_off = M;
+    d.head_off = Mh;
+    const int N = d.J * d.P;
+    for (int qt = 0; qt * 128 < N; ++qt) {
+      if (nwork >= w.max_work) return -22;
+      w.h_work[nwork++] = (r << 16) | qt;
+    }
+    M += N;
+    Mh += d.P;
+  }
+  if (M > w.cap) return -22;
+  REVO_HIP_TRY(hipMemcpyAsync(w.d_reqs, w.h_reqs, (size_t)nall * sizeof(ReqDesc), hipMemcpyHostToDevice, s));
+  if (nrec > 0) {
+    REVO_HIP_TRY(hipMemcpyAsync(w.d_work, w.h_work, (size_t)nwork * 4, hipMemcpyHostToDevice, s));
+    const Prec p = m.prec;
+    int rc = 0;
+    GemmArgs g;
+    memset(&g, 0, sizeof(g));
+    g.reqs = w.d_reqs; g.nreq = nrec; g.channels = m.C;
+    // tubelet embedding (implicit GEMM over the gathered frames) + PE
+    g.M = M; g.N = m.De; g.K = m.tub_len(); g.W = m.emb_w; g.bias = m.emb_b; g.out = w.h; g.ldo = m.De;
+    if ((rc = launch_gemm(p, EPI_PE, X_GATHER, g, s))) return rc;
+
+    AttnArgs at;
+    memset(&at, 0, sizeof(at));
+    at.q = w.q; at.k = w.k; at.vt = w.vt; at.o = w.o; at.ldqk = w.ld; at.ldv = w.ld;
+    at.reqs = w.d_reqs; at.nreq = nrec; at.work = w.d_work; at.nwork = nwork;
+
+    auto run_block = [&](const BlockW& b, float* x, int D, int heads) -> int {
+      int e;
+      if ((e = launch_layernorm(p, x, b.ln1_g, b.ln1_b, w.a, M, D, nullptr, 0, s))) return e;
+      GemmArgs q = g;
+      q.X = w.a; q.K = D; q.N = 3 * D; q.W = b.qkv_w; q.bias = b.qkv_b;
+      q.q = w.q; q.k = w.k; q.vt = w.vt; q.heads = heads; q.ldqk = w.ld; q.ldv = w.ld;
+      q.qscale = 1.4426950408889634f / 8.0f;  // log2(e) / sqrt(64)
+      if ((e = launch_gemm(p, EPI_QKV, X_DENSE, q, s))) return e;
+      at.heads = heads;
+      if ((e = launch_attention(p, at, s))) return e;
+      GemmArgs pr = g;
+      pr.X = w.o; pr.K = D; pr.N = D; pr.W = b.proj_w; pr.bias = b.proj_b; pr.out = x; pr.ldo = D;
+      if ((e = launch_gemm(p, EPI_RESIDUAL, X_DENSE, pr, s))) return e;
+      if ((e = launch_layernorm(p, x, b.ln2_g, b.ln2_b, w.a, M, D, nullptr, 0, s))) return e;
+      GemmArgs f1 = g;
+      f1.X = w.a; f1.K = D; f1.N = 4 * D; f1.W = b.fc1_w; f1.bias = b.fc1_b; f1.out = w.hid; f1.ldo = 4 * D;
+      if ((e = launch_gemm(p, EPI_GELU, X_DENSE, f1, s))) return e;
+      GemmArgs f2 = g;
+      f2.X = w.hid; f2.K = 4 * D; f2.N = D; f2.W = b.fc2_w; f2.bias = b.fc2_b; f2.out = x; f2.ldo = D;
+      return launch_gemm(p, EPI_RESIDUAL, X_DENSE, f2, s);
+    };
+    for (const BlockW& b : m.enc)
+      if ((rc = run_block(b, w.h, m.De, m.He))) return rc;
+    // encoder norm, projection to the decoder width + PE
+    if ((rc = launch_layernorm(p, w.h, m.enc_g, m.enc_b, w.a, M, m.De, nullptr, 0, s))) return rc;
+    GemmArgs e2 = g;
+    e2.X = w.a; e2.K = m.De; e2.N = m.Dd; e2.W = m.e2d_w; e2.bias = m.e2d_b; e2.out = w.z; e2.ldo = m.Dd;
+    if ((rc = launch_gemm(p, EPI_PE, X_DENSE, e2, s))) return rc;
+    for (const BlockW& b : m.dec)
+      if ((rc = run_block(b, w.z, m.Dd, m.Hd))) return rc;
+    // decoder norm and head on the target tubelet only, target time slot only
+    if ((rc = launch_layernorm(p, w.z, m.dec_g, m.dec_b, w.ahead, Mh, m.Dd, w.d_reqs, nrec, s))) return rc;
+    const int slot = (m.T - 1) * 256 * m.C;
+    GemmArgs hd = g;
+    hd.M = Mh; hd.X = w.ahead; hd.K = m.Dd; hd.N = 256 * m.C;
+    hd.W = (const char*)m.head_w + (size_t)slot * m.Dd * esize(p);
+    hd.bias = m.head_b + slot;
+    if ((rc = launch_gemm(p, EPI_HEAD, X_DENSE, hd, s))) return rc;
+  }
+  return launch_composite(w.d_reqs, nall, m.C, max_pix, composite, s);
+}
+
+}  // namespace revo

@@ -1,0 +1,60 @@
+// Device-resident model weights, batch workspaces and the forward pass.
+#pragma once
+#include <vector>
+
+#include "kernels.h"
+
+namespace revo {
+
+struct BlockW {
+  const float *ln1_g, *ln1_b, *qkv_b, *proj_b, *ln2_g, *ln2_b, *fc1_b, *fc2_b;
+  const void *qkv_w, *proj_w, *fc1_w, *fc2_w;
+};
+
+struct ModelW {
+  int C = 3, T = 2, De = 384, Dd = 192, He = 6, Hd = 3, ne = 12, nd = 4;
+  Prec prec = P_BF16;
+  float* master = nullptr;  // FP32 blob on the device (biases, LN parameters)
+  void* ops = nullptr;      // operand-precision copy of the blob (matrices)
+  size_t count = 0;
+  const void *emb_w = nullptr, *e2d_w = nullptr, *head_w = nullptr;
+  const float *emb_b = nullptr, *e2d_b = nullptr, *head_b = nullptr;
+  const float *enc_g = nullptr, *enc_b = nullptr, *dec_g = nullptr, *dec_b = nullptr;
+  std::vector<BlockW> enc, dec;
+  size_t bytes = 0;
+  int tub_len() const { return T * REVO_PATCH * REVO_PATCH * C; }
+};
+
+size_t weight_count(int C, int T, int ne, int nd);
+int model_load(ModelW& m, int C, int T, int ne, int nd, Prec p, const float* host_blob, size_t n, hipStream_t s);
+void model_free(ModelW& m);
+
+// Activation buffers for one batch of one modality.  Token rows are the
+// batch's requests one after the other, each starting at a multiple of 8; q/k/vt carry ld >= cap + 64 rows so
+// the last key block of any request stays inside the (zeroed) allocation.
+struct Workspace {
+  int cap = 0, head_cap = 0, ld = 0, max_req = 0, max_work = 0;
+  Prec prec = P_BF16;
+  float* h = nullptr;
+  void *a = nullptr, *q = nullptr, *k = nullptr, *vt = nullptr, *o = nullptr, *hid = nullptr, *ahead = nullptr;
+  float* z = nullptr;
+  ReqDesc* d_reqs = nullptr;
+  int* d_work = nullptr;
+  ReqDesc* h_reqs = nullptr;  // pinned host mirror
+  int* h_work = nullptr;      // pinned host mirror
+  size_t bytes = 0;
+};
+
+size_t workspace_bytes(const ModelW& m, int cap, int max_req);
+int workspace_alloc(Workspace& w, const ModelW& m, int cap, int max_req, hipStream_t s);
+void workspace_free(Workspace& w);
+
+// Tokens of one request at frame size H x W.
+int request_tokens(int H, int W, int J);
+
+// Runs the network for w.h_reqs[0 .. nrec) and the composite for
+// w.h_reqs[0 .. nall) (entries nrec.. are clean frames: copy only).  The
+// caller fills frames/mask/outputs/size fields; offsets are set here.
+int forward(const ModelW& m, Workspace& w, int nrec, int nall, int composite, hipStream_t s);
+
+}  // namespace revo

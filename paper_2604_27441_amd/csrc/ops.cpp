@@ -1,0 +1,96 @@
+// Single-kernel entry points (revo_ops.h): thin launch wrappers over the
+// kernels the forward pass uses, for per-kernel checks.
+#include <string.h>
+
+#include <mutex>
+
+#include "../../include/revo.h"
+#include "../../include/revo_ops.h"
+#include "kernels.h"
+
+using namespace revo;
+
+namespace {
+
+bool prec_of(int precision, Prec* p) {
+  if (precision == REVO_FP32) { *p = P_FP32; return true; }
+  if (precision == REVO_BF16) { *p = P_BF16; return true; }
+  return false;
+}
+
+}  // namespace
+
+extern "C" {
+
+int revo_op_linear(int precision, int epilogue, const void* x, const void* w, const float* bias, void* out, int M,
+                   int N, int K, void* stream) {
+  Prec p;
+  if (!prec_of(precision, &p)) return REVO_ENOTSUP;
+  if (M < 0 || N <= 0 || K <= 0 || !x || !w || !bias || !out) return REVO_EINVAL;
+  if (N % 64 || K % (p == P_BF16 ? 64 : 32)) return REVO_EINVAL;
+  int epi;
+  switch (epilogue) {
+    case REVO_EPI_STORE: epi = EPI_STORE; break;
+    case REVO_EPI_RESIDUAL: epi = EPI_RESIDUAL; break;
+    case REVO_EPI_GELU: epi = EPI_GELU; break;
+    default: return REVO_EINVAL;
+  }
+  GemmArgs a;
+  memset(&a, 0, sizeof(a));
+  a.M = M; a.N = N; a.K = K; a.X = x; a.W = w; a.bias = bias; a.out = out; a.ldo = N;
+  return launch_gemm(p, epi, X_DENSE, a, (hipStream_t)stream);
+}
+
+int revo_op_layernorm(int precision, const float* x, const float* g, const float* b, void* y, int rows, int D,
+                      void* stream) {
+  Prec p;
+  if (!prec_of(precision, &p)) return REVO_ENOTSUP;
+  if (rows < 0 || D <= 0 || D > 512 || !x || !g || !b || !y) return REVO_EINVAL;
+  return launch_layernorm(p, x, g, b, y, rows, D, nullptr, 0, (hipStream_t)stream);
+}
+
+int revo_op_attention(int precision, const void* q, const void* k, const void* vt, void* o, int heads, int ntok,
+                      int ld, void* stream) {
+  Prec p;
+  if (!prec_of(precision, &p)) return REVO_ENOTSUP;
+  if (heads <= 0 || ntok <= 0 || ld < ntok + 64 || !q || !k || !vt || !o) return REVO_EINVAL;
+  if (ld % 8) return REVO_EINVAL;  // 16-byte aligned vt rows
+  const int ntile = (ntok + 127) / 128;
+  if (ntile > 0xFFFF) return REVO_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  // one request covering all tokens; descriptor and work list in device memory
+  ReqDesc h;
+  memset(&h, 0, sizeof(h));
+  h.J = 1; h.P = ntok; h.gy = 1; h.gx = ntok; h.H = 1; h.W = ntok; h.nframes = 1;
+  ReqDesc* d = nullptr;
+  int* work = nullptr;
+  if (hipMalloc(&d, sizeof(ReqDesc)) != hipSuccess) return REVO_ENOMEM;
+  if (hipMalloc(&work, ntile * sizeof(int)) != hipSuccess) { (void)hipFree(d); return REVO_ENOMEM; }
+  int* hw = new int[ntile];
+  for (int i = 0; i < ntile; ++i) hw[i] = i;
+  int rc = 0;
+  if (hipMemcpy(d, &h, sizeof(h), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(work, hw, ntile * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+    rc = REVO_EDEVICE;
+  delete[] hw;
+  if (!rc) {
+    AttnArgs a;
+    memset(&a, 0, sizeof(a));
+    a.q = q; a.k = k; a.vt = vt; a.o = o; a.heads = heads; a.ldqk = ld; a.ldv = ld;
+    a.reqs = d; a.nreq = 1; a.work = work; a.nwork = ntile;
+    rc = launch_attention(p, a, s);
+    if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = REVO_EDEVICE;
+  }
+  (void)hipFree(d);
+  (void)hipFree(work);
+  return rc;
+}
+
+int revo_op_convert(int precision, const float* src, void* dst, long long n, void* stream) {
+  Prec p;
+  if (!prec_of(precision, &p)) return REVO_ENOTSUP;
+  if (n < 0 || !src || !dst) return REVO_EINVAL;
+  return launch_convert(p, src, dst, n, (hipStream_t)stream);
+}
+
+}  // extern "C"

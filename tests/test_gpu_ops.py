@@ -1,0 +1,136 @@
+"""Each HIP kernel on its own, through revo_op_*, against the FP64 oracle's
+same layer (linear, LayerNorm, GELU, attention of Sec. 3.4.1 / App. B.1)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+FP32, BF16 = 0, 1
+RNG = np.random.default_rng(77)
+
+
+def _lib():
+    import paper_2604_27441_amd as pkg
+    return pkg.lib
+
+
+def _dt(prec):
+    return torch.float32 if prec == FP32 else torch.bfloat16
+
+
+def _as_op(a, prec):
+    """Host operand rounded to the kernel's operand type, and its exact float64 value."""
+    t = torch.tensor(a, dtype=torch.float32).to(_dt(prec))
+    return t.cuda(), t.to(torch.float64).numpy()
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+@pytest.mark.parametrize("M,N,K", [(1, 64, 64), (300, 192, 384), (1000, 1152, 384), (257, 384, 1536), (77, 64, 192)])
+@pytest.mark.parametrize("epi", [0, 1, 2])
+def test_linear(prec, M, N, K, epi):
+    x = RNG.standard_normal((M, K))
+    w = RNG.standard_normal((N, K)) * math.sqrt(2.0 / K)
+    b = 0.1 * RNG.standard_normal(N)
+    xd, x64 = _as_op(x, prec)
+    wd, w64 = _as_op(w, prec)
+    bd = torch.tensor(b, dtype=torch.float32).cuda()
+    b64 = bd.double().cpu().numpy()
+    ref = oracle.linear(x64, w64, b64)
+    if epi == 1:
+        res = RNG.standard_normal((M, N)).astype(np.float32)
+        out = torch.tensor(res).cuda()
+        ref = ref + res
+    else:
+        out = torch.zeros((M, N), dtype=torch.float32 if prec == FP32 or epi == 1 else torch.bfloat16).cuda()
+        if epi == 2:
+            ref = oracle.gelu(ref)
+    rc = _lib().revo_op_linear(prec, epi, xd.data_ptr(), wd.data_ptr(), bd.data_ptr(), out.data_ptr(), M, N, K, None)
+    assert rc == 0
+    torch.cuda.synchronize()
+    got = out.double().cpu().numpy()
+    # accumulation in FP32 over K terms; a BF16 result is additionally rounded once (2^-9 relative)
+    scale = np.abs(ref).max() + 1e-30
+    tol = 2e-6 * math.sqrt(K) * scale if (prec == FP32 or epi == 1) else 4e-3 * np.abs(ref) + 2e-6 * math.sqrt(K) * scale
+    assert np.all(np.abs(got - ref) <= tol + 1e-7), float(np.abs(got - ref).max())
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+@pytest.mark.parametrize("rows,D", [(1, 384), (1000, 384), (333, 192), (5, 24)])
+def test_layernorm(prec, rows, D):
+    x = (RNG.standard_normal((rows, D)) * 3 + 2).astype(np.float32)
+    g = (1 + 0.1 * RNG.standard_normal(D)).astype(np.float32)
+    b = (0.1 * RNG.standard_normal(D)).astype(np.float32)
+    y = torch.zeros((rows, D), dtype=_dt(prec)).cuda()
+    rc = _lib().revo_op_layernorm(prec, torch.tensor(x).cuda().data_ptr(), torch.tensor(g).cuda().data_ptr(),
+                                  torch.tensor(b).cuda().data_ptr(), y.data_ptr(), rows, D, None)
+    assert rc == 0
+    torch.cuda.synchronize()
+    ref = oracle.layer_norm(x.astype(np.float64), g.astype(np.float64), b.astype(np.float64))
+    got = y.double().cpu().numpy()
+    tol = 1e-5 if prec == FP32 else 4e-3 * np.abs(ref) + 1e-5
+    assert np.all(np.abs(got - ref) <= tol), float(np.abs(got - ref).max())
+
+
+def _attn_inputs(heads, ntok, prec, scale=1.0, ld=None):
+    ld = ld or ((ntok + 64 + 7) // 8 * 8)
+    q = RNG.standard_normal((heads, ntok, 64)) * scale
+    k = RNG.standard_normal((heads, ntok, 64)) * scale
+    v = RNG.standard_normal((heads, ntok, 64))
+    dt = _dt(prec)
+    # operand values as the kernel sees them
+    q_op = torch.tensor(q * (math.log2(math.e) / 8), dtype=torch.float32).to(dt)
+    k_op = torch.tensor(k, dtype=torch.float32).to(dt)
+    v_op = torch.tensor(v, dtype=torch.float32).to(dt)
+    qd = torch.zeros((heads, ld, 64), dtype=dt)
+    kd = torch.zeros((heads, ld, 64), dtype=dt)
+    vt = torch.zeros((heads, 64, ld), dtype=dt)
+    qd[:, :ntok] = q_op
+    kd[:, :ntok] = k_op
+    vt[:, :, :ntok] = v_op.transpose(1, 2)
+    q64 = q_op.double().numpy() / (math.log2(math.e) / 8)
+    return qd.cuda(), kd.cuda(), vt.cuda(), q64, k_op.double().numpy(), v_op.double().numpy(), ld
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+@pytest.mark.parametrize("heads,ntok", [(1, 1), (2, 63), (6, 576), (3, 1000), (1, 4099)])
+def test_attention(prec, heads, ntok):
+    qd, kd, vt, q64, k64, v64, ld = _attn_inputs(heads, ntok, prec, scale=1.5)
+    o = torch.zeros((ntok, heads * 64), dtype=_dt(prec)).cuda()
+    rc = _lib().revo_op_attention(prec, qd.data_ptr(), kd.data_ptr(), vt.data_ptr(), o.data_ptr(), heads, ntok, ld, None)
+    assert rc == 0
+    got = o.double().cpu().numpy()
+    for h in range(heads):
+        ref = oracle.attention_head(q64[h], k64[h], v64[h])
+        g = got[:, h * 64:(h + 1) * 64]
+        if prec == FP32:
+            assert np.abs(g - ref).max() < 2e-5 * np.abs(v64[h]).max(), float(np.abs(g - ref).max())
+        else:
+            # probabilities rounded to bf16 (2^-9 relative) and the output rounded once more
+            err = np.abs(g - ref)
+            assert err.max() < 1.5e-2 * np.abs(v64[h]).max(), float(err.max())
+            assert np.sqrt(np.mean(err ** 2)) < 4e-3 * np.sqrt(np.mean(ref ** 2)) + 1e-3
+
+
+def test_attention_uniform_keys_average_values():
+    """Equal keys give the mean of V exactly up to rounding (softmax is uniform)."""
+    heads, ntok = 2, 300
+    qd, kd, vt, q64, k64, v64, ld = _attn_inputs(heads, ntok, FP32)
+    kd[:, :ntok] = kd[:, :1].clone()
+    o = torch.zeros((ntok, heads * 64), dtype=torch.float32).cuda()
+    assert _lib().revo_op_attention(FP32, qd.data_ptr(), kd.data_ptr(), vt.data_ptr(), o.data_ptr(), heads, ntok, ld, None) == 0
+    got = o.double().cpu().numpy()
+    for h in range(heads):
+        assert np.allclose(got[:, h * 64:(h + 1) * 64], v64[h].mean(0), atol=2e-6)
+
+
+def test_convert_bf16_rounding():
+    x = (RNG.standard_normal(100003) * np.exp(RNG.uniform(-30, 30, 100003))).astype(np.float32)
+    y = torch.zeros(x.size, dtype=torch.bfloat16).cuda()
+    assert _lib().revo_op_convert(BF16, torch.tensor(x).cuda().data_ptr(), y.data_ptr(), x.size, None) == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(y.double().cpu().numpy(), oracle.bf16_round(x))

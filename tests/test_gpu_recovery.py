@@ -1,0 +1,163 @@
+"""End-to-end parity of the HIP recovery path (through the C ABI) against the
+FP64 oracle, plus the serving semantics of the paper's receiver: clean frames
+become references, recovered frames never do, the same references serve later
+targets through the temporal-distance embedding (Sec. 3.4.1)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import check_received_and_codes, compare, push_refs, recover
+
+pytestmark = pytest.mark.gpu
+
+FP32, BF16 = 0, 1
+SMALL = dict(enc_depth=2, dec_depth=1)
+
+
+def _rec(blobs, prec, **kw):
+    from paper_2604_27441_amd import Recoverer
+    kw.setdefault("max_batch_tokens", 8192)
+    return Recoverer(blobs[0], blobs[1], precision=prec, **kw)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    req = synth.make_batch("c1")[0]
+    blobs = synth.make_weights(0)
+    ref = oracle.recover(req, blobs)
+    return req, blobs, ref
+
+
+@pytest.fixture(scope="module")
+def c1_bf16_budget(c1):
+    """Error of the BF16-rounding oracle against the exact one: the budget the
+    BF16 kernels are held to (twice its MSE, four times its max error)."""
+    req, blobs, ref = c1
+    emu = oracle.recover(req, blobs, rnd=oracle.Rounding(oracle.bf16_round))
+    gpu_like = {"rgb_f": emu["rgb"][1], "depth_f": emu["depth"][1]}
+    return compare(req, gpu_like, ref)
+
+
+def test_c1_fp32_parity(c1):
+    req, blobs, ref = c1
+    with _rec(blobs, FP32) as rec:
+        push_refs(rec, 0, req)
+        out = recover(rec, [(0, req)])[0]
+    assert out["completion"].status == 0
+    check_received_and_codes(req, out)
+    e = compare(req, out, ref)
+    print("c1 fp32", e)
+    assert e["rgb_psnr"] >= 80.0, e
+    assert e["depth_maxabs"] <= 0.5, e
+
+
+def test_c1_bf16_parity(c1, c1_bf16_budget):
+    req, blobs, ref = c1
+    with _rec(blobs, BF16) as rec:
+        push_refs(rec, 0, req)
+        out = recover(rec, [(0, req)])[0]
+    check_received_and_codes(req, out)
+    e = compare(req, out, ref)
+    b = c1_bf16_budget
+    print("c1 bf16", e, "budget", b)
+    assert e["rgb_psnr"] >= 45.0, e
+    assert e["rgb_psnr"] >= b["rgb_psnr"] - 3.02, (e, b)          # MSE <= 2x the rounding oracle's
+    assert e["depth_rms_lost"] <= np.sqrt(2.0) * b["depth_rms_lost"], (e, b)
+    assert e["depth_maxabs"] <= 4.0 * b["depth_maxabs"], (e, b)
+
+
+def _small(prec, req, k=5, T=2, n_ref=None, blobs=None, **kw):
+    blobs = blobs or synth.make_weights(3, tubelet=T, perturb_seed=4, **SMALL)
+    refs = {}
+    ref = None
+    with _rec(blobs, prec, k=k, tubelet=T, **SMALL, **kw) as rec:
+        push_refs(rec, 0, req, n_ref=n_ref)
+        out = recover(rec, [(0, req)])[0]
+    r2 = dict(req)
+    if n_ref is not None:
+        for key in ("rgb_refs", "depth_refs", "ref_idx"):
+            r2[key] = req[key][len(req["ref_idx"]) - n_ref:]
+    ref = oracle.recover(r2, blobs, k=k, tubelet=T, **SMALL)
+    return out, ref
+
+
+@pytest.mark.parametrize("H,W", [(16, 16), (40, 56), (20, 36), (192, 256), (100, 30)])
+def test_ragged_sizes_fp32(H, W):
+    req = synth.make_request(31, 32, H, W, loss=("stripes", 0.5))
+    out, ref = _small(FP32, req)
+    check_received_and_codes(req, out)
+    e = compare(req, out, ref)
+    assert e["rgb_maxabs"] <= 1e-4 and e["depth_maxabs"] <= 0.5, e
+
+
+@pytest.mark.parametrize("k,T,n_ref", [(5, 2, 2), (4, 2, None), (5, 3, None), (3, 1, None), (7, 2, 5)])
+def test_history_and_tubelet_variants(k, T, n_ref):
+    req = synth.make_request(41, 42, 48, 64, k=k, loss=("stripes", 0.5))
+    out, ref = _small(FP32, req, k=k, T=T, n_ref=n_ref)
+    e = compare(req, out, ref)
+    assert e["rgb_maxabs"] <= 1e-4 and e["depth_maxabs"] <= 0.5, e
+
+
+def test_raw_prediction_without_composite():
+    req = synth.make_request(51, 52, 48, 64, loss=("stripes", 0.5))
+    out, ref = _small(FP32, req, composite=0)
+    assert np.abs(out["rgb_f"] - np.clip(ref["rgb"][0], 0, 1)).max() <= 1e-4
+    assert np.abs(out["depth_f"] - np.clip(4000 * ref["depth"][0][..., 0], 0, 65535)).max() <= 0.5
+
+
+def test_batch_invariance_and_host_pointers():
+    """A request gives the same bytes alone and inside a mixed batch of other
+    streams and resolutions, and through host or device pointers."""
+    blobs = synth.make_weights(3, perturb_seed=4, **SMALL)
+    reqs = [synth.make_request(61 + i, 62 + i, H, W, loss=("stripes", 0.4))
+            for i, (H, W) in enumerate([(48, 64), (40, 56), (96, 128), (20, 36)])]
+    for prec in (FP32, BF16):
+        with _rec(blobs, prec, **SMALL) as rec:
+            for s, r in enumerate(reqs):
+                push_refs(rec, s, r)
+            mixed = recover(rec, list(enumerate(reqs)))
+            alone = [recover(rec, [(s, r)])[0] for s, r in enumerate(reqs)]
+            host = recover(rec, [(2, reqs[2])], device_ptrs=False)[0]
+        for a, b in zip(mixed, alone):
+            for key in ("rgb", "depth", "rgb_f", "depth_f"):
+                assert np.array_equal(a[key], b[key]), key
+        for key in ("rgb", "depth", "rgb_f", "depth_f"):
+            assert np.array_equal(host[key], alone[2][key]), key
+
+
+def test_references_reused_across_later_targets():
+    """Two corrupted frames in a row use the same clean references; the second
+    one sees a larger temporal distance (no recovered frame enters the ring)."""
+    blobs = synth.make_weights(3, perturb_seed=4, **SMALL)
+    req = synth.make_request(71, 72, 48, 64, loss=("stripes", 0.5))
+    later = dict(req)
+    later["t_target"] = req["t_target"] + 2
+    with _rec(blobs, FP32, **SMALL) as rec:
+        push_refs(rec, 0, req)
+        a = recover(rec, [(0, req)])[0]
+        b = recover(rec, [(0, later)])[0]
+    ra = oracle.recover(req, blobs, **SMALL)
+    rb = oracle.recover(later, blobs, **SMALL)
+    assert compare(req, a, ra)["rgb_maxabs"] <= 1e-4
+    assert compare(later, b, rb)["rgb_maxabs"] <= 1e-4
+
+
+def test_clean_frame_copy_and_missing_references():
+    blobs = synth.make_weights(3, **SMALL)
+    req = synth.make_request(81, 82, 32, 48, loss=("stripes", 0.5))
+    with _rec(blobs, BF16, **SMALL) as rec:
+        # recovery before any clean frame of the stream
+        out = recover(rec, [(5, req)])[0]
+        assert out["completion"].status == 2 and out["completion"].error == -61
+        # a clean frame comes back unchanged
+        clean = dict(req)
+        clean["mask_rgb"] = np.zeros_like(req["mask_rgb"])
+        clean["mask_depth"] = np.zeros_like(req["mask_depth"])
+        push_refs(rec, 5, req)
+        out = recover(rec, [(5, clean)])[0]
+        assert np.array_equal(out["rgb"], req["rgb"]) and np.array_equal(out["depth"], req["depth"])
+        # a resolution change drops the stream's references
+        other = synth.make_request(83, 84, 48, 64, loss=("stripes", 0.5))
+        out = recover(rec, [(5, other)])[0]
+        assert out["completion"].status == 2 and out["completion"].error == -61
