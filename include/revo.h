@@ -66,6 +66,7 @@ enum revo_completion_status {
 
 /* revo_config.flags */
 #define REVO_CFG_SHED 0x1u    /* shed requests whose deadline cannot be met */
+#define REVO_CFG_PROFILE 0x2u /* time every kernel launch with HIP events (see revo_get_stats) */
 
 typedef struct revo_config {
   int device;                 /* HIP device ordinal */
@@ -157,6 +158,26 @@ int revo_recover_poll(revo_ctx *ctx, revo_completion *out, int max, int timeout_
 
 /* Drain queued and in-flight work, stop the worker and free everything. */
 void revo_recover_destroy(revo_ctx *ctx);
+
+/* Counters of a context.  The *_ms and *_flop fields are filled only with
+ * REVO_CFG_PROFILE: GPU time between HIP events recorded on the stream of
+ * each launch, and algorithmic FLOPs (2 per multiply-add of the layer's
+ * definition: attention 4 * N^2 * 64 per head and request, a linear layer
+ * 2 * tokens * out * in; alignment rows and padding excluded). */
+typedef struct revo_stats {
+  long long batches;                /* batches run */
+  long long served, shed, failed;   /* completions by status */
+  long long attn_launches;          /* flash-attention kernel launches */
+  double attn_ms, attn_flop;
+  long long gemm_launches;          /* linear-layer launches (embedding, blocks, e2d, head) */
+  double gemm_ms, gemm_flop;
+  long long other_launches;         /* LayerNorm and composite launches */
+  double other_ms;
+  double forward_ms;                /* whole forward passes, both modalities summed */
+} revo_stats;
+
+/* Copy the counters into *out; reset = 1 zeroes them afterwards. */
+int revo_get_stats(revo_ctx *ctx, revo_stats *out, int reset);
 
 /* Static text for a revo_status code. */
 const char *revo_strerror(int code);

@@ -13,7 +13,7 @@ lib = C.CDLL(LIB_PATH)
 
 REVO_OK, REVO_EAGAIN = 0, 1
 REVO_DEVICE_PTRS, REVO_HOLD = 0x1, 0x2
-REVO_CFG_SHED = 0x1
+REVO_CFG_SHED, REVO_CFG_PROFILE = 0x1, 0x2
 REVO_DONE, REVO_SHED, REVO_FAILED = 0, 1, 2
 
 
@@ -47,6 +47,15 @@ class RevoCompletion(C.Structure):
     ]
 
 
+class RevoStats(C.Structure):
+    _fields_ = [
+        ("batches", C.c_longlong), ("served", C.c_longlong), ("shed", C.c_longlong), ("failed", C.c_longlong),
+        ("attn_launches", C.c_longlong), ("attn_ms", C.c_double), ("attn_flop", C.c_double),
+        ("gemm_launches", C.c_longlong), ("gemm_ms", C.c_double), ("gemm_flop", C.c_double),
+        ("other_launches", C.c_longlong), ("other_ms", C.c_double), ("forward_ms", C.c_double),
+    ]
+
+
 _sigs = {
     "revo_config_default": (None, [C.POINTER(RevoConfig)]),
     "revo_weight_count": (C.c_size_t, [C.c_int, C.c_int, C.c_int, C.c_int]),
@@ -55,6 +64,7 @@ _sigs = {
     "revo_recover_poll": (C.c_int, [C.c_void_p, C.POINTER(RevoCompletion), C.c_int, C.c_int]),
     "revo_recover_destroy": (None, [C.c_void_p]),
     "revo_strerror": (C.c_char_p, [C.c_int]),
+    "revo_get_stats": (C.c_int, [C.c_void_p, C.POINTER(RevoStats), C.c_int]),
     "revo_op_linear": (C.c_int, [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_int, C.c_int, C.c_int, C.c_void_p]),
     "revo_op_layernorm": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,

@@ -150,6 +150,8 @@ struct revo_ctx {
   std::thread worker;
   int device_error = 0;
   double sec_per_unit = 2e-11;  // cost model for shedding (seconds per work unit)
+  std::mutex stats_mu;
+  revo_stats stats;
 };
 
 namespace {
@@ -371,6 +373,28 @@ void worker_main(revo_ctx* c) {
       for (Job* j : batch)
         if (j->status == REVO_DONE) { j->status = REVO_FAILED; j->error = rc; }
     }
+    {
+      std::lock_guard<std::mutex> lk(c->stats_mu);
+      revo_stats& st = c->stats;
+      st.batches += 1;
+      for (Job* j : batch) {
+        if (j->status == REVO_DONE) st.served++;
+        else if (j->status == REVO_SHED) st.shed++;
+        else st.failed++;
+      }
+      for (int q = 0; q < 2; ++q) {
+        Prof& p = c->ws[q].prof;
+        if (!p.on) continue;
+        if (rc == 0) (void)prof_collect(p);
+        p.recs.clear();
+        p.used = 0;
+        st.attn_launches += p.count[PK_ATTN]; st.attn_ms += p.ms[PK_ATTN]; st.attn_flop += p.flop[PK_ATTN];
+        st.gemm_launches += p.count[PK_GEMM]; st.gemm_ms += p.ms[PK_GEMM]; st.gemm_flop += p.flop[PK_GEMM];
+        st.other_launches += p.count[PK_OTHER]; st.other_ms += p.ms[PK_OTHER];
+        st.forward_ms += p.ms[PK_FORWARD];
+        for (int k = 0; k < PK_N; ++k) { p.ms[k] = 0; p.flop[k] = 0; p.count[k] = 0; }
+      }
+    }
     for (Job* j : batch) finish(c, j);
   }
 }
@@ -454,6 +478,7 @@ int revo_recover_create(const revo_config* cfg_in, revo_ctx** out) {
   if (hipSetDevice(cfg.device) != hipSuccess) return REVO_EDEVICE;
 
   revo_ctx* c = new revo_ctx();
+  memset(&c->stats, 0, sizeof(c->stats));
   c->cfg = cfg;
   c->T = T; c->k = cfg.k; c->nframes = nframes; c->J = nframes / T;
   c->prec = cfg.precision == REVO_BF16 ? P_BF16 : P_FP32;
@@ -482,6 +507,8 @@ int revo_recover_create(const revo_config* cfg_in, revo_ctx** out) {
     c->cfg.max_batch_tokens = cap;
     if (!rc) rc = workspace_alloc(c->ws[0], c->model[0], cap, cfg.max_batch, c->stream[0]);
     if (!rc) rc = workspace_alloc(c->ws[1], c->model[1], cap, cfg.max_batch, c->stream[1]);
+    if (!rc && (cfg.flags & REVO_CFG_PROFILE))
+      for (int q = 0; q < 2 && !rc; ++q) rc = prof_init(c->ws[q].prof, 1024);
     fixed += c->ws[0].bytes + c->ws[1].bytes;
     c->pool.fixed = fixed;
     c->pool.budget = cfg.hbm_budget_bytes;
@@ -558,6 +585,14 @@ int revo_recover_poll(revo_ctx* c, revo_completion* out, int max, int timeout_us
     c->done.pop_front();
   }
   return n;
+}
+
+int revo_get_stats(revo_ctx* c, revo_stats* out, int reset) {
+  if (!c || !out) return REVO_EINVAL;
+  std::lock_guard<std::mutex> lk(c->stats_mu);
+  *out = c->stats;
+  if (reset) memset(&c->stats, 0, sizeof(c->stats));
+  return REVO_OK;
 }
 
 void revo_recover_destroy(revo_ctx* c) {

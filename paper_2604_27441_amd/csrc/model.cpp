@@ -73,6 +73,57 @@ void model_free(ModelW& m) {
   m.master = nullptr; m.ops = nullptr;
 }
 
+int prof_init(Prof& p, int events) {
+  p.pool.resize(events);
+  for (auto& e : p.pool) REVO_HIP_TRY(hipEventCreate(&e));
+  p.on = true;
+  return 0;
+}
+
+void prof_free(Prof& p) {
+  for (auto& e : p.pool) (void)hipEventDestroy(e);
+  p.pool.clear();
+  p.on = false;
+}
+
+int prof_collect(Prof& p) {
+  for (const auto& r : p.recs) {
+    float ms = 0.0f;
+    REVO_HIP_TRY(hipEventElapsedTime(&ms, p.pool[r.a], p.pool[r.b]));
+    p.ms[r.kind] += ms;
+    p.flop[r.kind] += r.flop;
+    p.count[r.kind] += 1;
+  }
+  p.recs.clear();
+  p.used = 0;
+  return 0;
+}
+
+namespace {
+
+// Event pair around one launch when profiling; no-op otherwise.
+struct ProfScope {
+  Prof& p;
+  hipStream_t s;
+  int a = -1, kind;
+  double flop;
+  ProfScope(Prof& p_, hipStream_t s_, int kind_, double flop_) : p(p_), s(s_), kind(kind_), flop(flop_) {
+    if (p.on && p.used + 2 <= (int)p.pool.size()) {
+      a = p.used;
+      p.used += 2;
+      (void)hipEventRecord(p.pool[a], s);
+    }
+  }
+  ~ProfScope() {
+    if (a >= 0) {
+      (void)hipEventRecord(p.pool[a + 1], s);
+      p.recs.push_back({a, a + 1, kind, flop});
+    }
+  }
+};
+
+}  // namespace
+
 int request_tokens(int H, int W, int J) { return J * cdiv(H, REVO_PATCH) * cdiv(W, REVO_PATCH); }
 
 size_t workspace_bytes(const ModelW& m, int cap, int max_req) {
@@ -123,6 +174,7 @@ int workspace_alloc(Workspace& w, const ModelW& m, int cap, int max_req, hipStre
 }
 
 void workspace_free(Workspace& w) {
+  prof_free(w.prof);
   void* dev[] = {w.h, w.a, w.q, w.k, w.vt, w.o, w.hid, w.z, w.ahead, w.d_reqs, w.d_work};
   for (void* p : dev)
     if (p) (void)hipFree(p);
@@ -155,6 +207,21 @@ int forward(const ModelW& m, Workspace& w, int nrec, int nall, int composite, hi
     Mh += d.P;
   }
   if (M > w.cap) return -22;
+  double Mreal = 0.0, Mh_real = Mh, attn_pairs = 0.0;  // tokens, head rows, sum of N^2
+  for (int r = 0; r < nrec; ++r) {
+    const double N = (double)w.h_reqs[r].J * w.h_reqs[r].P;
+    Mreal += N;
+    attn_pairs += N * N;
+  }
+  ProfScope whole(w.prof, s, PK_FORWARD, 0.0);
+  auto gemm = [&](int epi, int xm, const GemmArgs& ga, double rows) {
+    ProfScope ps(w.prof, s, PK_GEMM, 2.0 * rows * ga.N * ga.K);
+    return launch_gemm(m.prec, epi, xm, ga, s);
+  };
+  auto ln = [&](const float* x, const float* gg, const float* bb, void* y, int rows, int D, const ReqDesc* rq, int nq) {
+    ProfScope ps(w.prof, s, PK_OTHER, 0.0);
+    return launch_layernorm(m.prec, x, gg, bb, y, rows, D, rq, nq, s);
+  };
   REVO_HIP_TRY(hipMemcpyAsync(w.d_reqs, w.h_reqs, (size_t)nall * sizeof(ReqDesc), hipMemcpyHostToDevice, s));
   if (nrec > 0) {
     REVO_HIP_TRY(hipMemcpyAsync(w.d_work, w.h_work, (size_t)nwork * 4, hipMemcpyHostToDevice, s));
@@ -165,7 +232,7 @@ int forward(const ModelW& m, Workspace& w, int nrec, int nall, int composite, hi
     g.reqs = w.d_reqs; g.nreq = nrec; g.channels = m.C;
     // tubelet embedding (implicit GEMM over the gathered frames) + PE
     g.M = M; g.N = m.De; g.K = m.tub_len(); g.W = m.emb_w; g.bias = m.emb_b; g.out = w.h; g.ldo = m.De;
-    if ((rc = launch_gemm(p, EPI_PE, X_GATHER, g, s))) return rc;
+    if ((rc = gemm(EPI_PE, X_GATHER, g, Mreal))) return rc;
 
     AttnArgs at;
     memset(&at, 0, sizeof(at));
@@ -174,43 +241,47 @@ int forward(const ModelW& m, Workspace& w, int nrec, int nall, int composite, hi
 
     auto run_block = [&](const BlockW& b, float* x, int D, int heads) -> int {
       int e;
-      if ((e = launch_layernorm(p, x, b.ln1_g, b.ln1_b, w.a, M, D, nullptr, 0, s))) return e;
+      if ((e = ln(x, b.ln1_g, b.ln1_b, w.a, M, D, nullptr, 0))) return e;
       GemmArgs q = g;
       q.X = w.a; q.K = D; q.N = 3 * D; q.W = b.qkv_w; q.bias = b.qkv_b;
       q.q = w.q; q.k = w.k; q.vt = w.vt; q.heads = heads; q.ldqk = w.ld; q.ldv = w.ld;
       q.qscale = 1.4426950408889634f / 8.0f;  // log2(e) / sqrt(64)
-      if ((e = launch_gemm(p, EPI_QKV, X_DENSE, q, s))) return e;
+      if ((e = gemm(EPI_QKV, X_DENSE, q, Mreal))) return e;
       at.heads = heads;
-      if ((e = launch_attention(p, at, s))) return e;
+      {
+        ProfScope ps(w.prof, s, PK_ATTN, 4.0 * 64.0 * heads * attn_pairs);
+        if ((e = launch_attention(p, at, s))) return e;
+      }
       GemmArgs pr = g;
       pr.X = w.o; pr.K = D; pr.N = D; pr.W = b.proj_w; pr.bias = b.proj_b; pr.out = x; pr.ldo = D;
-      if ((e = launch_gemm(p, EPI_RESIDUAL, X_DENSE, pr, s))) return e;
-      if ((e = launch_layernorm(p, x, b.ln2_g, b.ln2_b, w.a, M, D, nullptr, 0, s))) return e;
+      if ((e = gemm(EPI_RESIDUAL, X_DENSE, pr, Mreal))) return e;
+      if ((e = ln(x, b.ln2_g, b.ln2_b, w.a, M, D, nullptr, 0))) return e;
       GemmArgs f1 = g;
       f1.X = w.a; f1.K = D; f1.N = 4 * D; f1.W = b.fc1_w; f1.bias = b.fc1_b; f1.out = w.hid; f1.ldo = 4 * D;
-      if ((e = launch_gemm(p, EPI_GELU, X_DENSE, f1, s))) return e;
+      if ((e = gemm(EPI_GELU, X_DENSE, f1, Mreal))) return e;
       GemmArgs f2 = g;
       f2.X = w.hid; f2.K = 4 * D; f2.N = D; f2.W = b.fc2_w; f2.bias = b.fc2_b; f2.out = x; f2.ldo = D;
-      return launch_gemm(p, EPI_RESIDUAL, X_DENSE, f2, s);
+      return gemm(EPI_RESIDUAL, X_DENSE, f2, Mreal);
     };
     for (const BlockW& b : m.enc)
       if ((rc = run_block(b, w.h, m.De, m.He))) return rc;
     // encoder norm, projection to the decoder width + PE
-    if ((rc = launch_layernorm(p, w.h, m.enc_g, m.enc_b, w.a, M, m.De, nullptr, 0, s))) return rc;
+    if ((rc = ln(w.h, m.enc_g, m.enc_b, w.a, M, m.De, nullptr, 0))) return rc;
     GemmArgs e2 = g;
     e2.X = w.a; e2.K = m.De; e2.N = m.Dd; e2.W = m.e2d_w; e2.bias = m.e2d_b; e2.out = w.z; e2.ldo = m.Dd;
-    if ((rc = launch_gemm(p, EPI_PE, X_DENSE, e2, s))) return rc;
+    if ((rc = gemm(EPI_PE, X_DENSE, e2, Mreal))) return rc;
     for (const BlockW& b : m.dec)
       if ((rc = run_block(b, w.z, m.Dd, m.Hd))) return rc;
     // decoder norm and head on the target tubelet only, target time slot only
-    if ((rc = launch_layernorm(p, w.z, m.dec_g, m.dec_b, w.ahead, Mh, m.Dd, w.d_reqs, nrec, s))) return rc;
+    if ((rc = ln(w.z, m.dec_g, m.dec_b, w.ahead, Mh, m.Dd, w.d_reqs, nrec))) return rc;
     const int slot = (m.T - 1) * 256 * m.C;
     GemmArgs hd = g;
     hd.M = Mh; hd.X = w.ahead; hd.K = m.Dd; hd.N = 256 * m.C;
     hd.W = (const char*)m.head_w + (size_t)slot * m.Dd * esize(p);
     hd.bias = m.head_b + slot;
-    if ((rc = launch_gemm(p, EPI_HEAD, X_DENSE, hd, s))) return rc;
+    if ((rc = gemm(EPI_HEAD, X_DENSE, hd, Mh_real))) return rc;
   }
+  ProfScope ps(w.prof, s, PK_OTHER, 0.0);
   return launch_composite(w.d_reqs, nall, m.C, max_pix, composite, s);
 }
 

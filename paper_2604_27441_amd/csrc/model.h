@@ -29,6 +29,23 @@ size_t weight_count(int C, int T, int ne, int nd);
 int model_load(ModelW& m, int C, int T, int ne, int nd, Prec p, const float* host_blob, size_t n, hipStream_t s);
 void model_free(ModelW& m);
 
+// Optional per-launch GPU timing with events on the launching stream.
+enum ProfKind { PK_ATTN = 0, PK_GEMM = 1, PK_OTHER = 2, PK_FORWARD = 3, PK_N = 4 };
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  struct Rec { int a, b, kind; double flop; };
+  std::vector<Rec> recs;
+  int used = 0;
+  double ms[PK_N] = {0, 0, 0, 0};
+  double flop[PK_N] = {0, 0, 0, 0};
+  long long count[PK_N] = {0, 0, 0, 0};
+};
+int prof_init(Prof& p, int events);
+void prof_free(Prof& p);
+// Adds the finished batch's records to the totals (call after the stream synchronised).
+int prof_collect(Prof& p);
+
 // Activation buffers for one batch of one modality.  Token rows are the
 // batch's requests one after the other, each starting at a multiple of 8; q/k/vt carry ld >= cap + 64 rows so
 // the last key block of any request stays inside the (zeroed) allocation.
@@ -43,6 +60,7 @@ struct Workspace {
   ReqDesc* h_reqs = nullptr;  // pinned host mirror
   int* h_work = nullptr;      // pinned host mirror
   size_t bytes = 0;
+  Prof prof;
 };
 
 size_t workspace_bytes(const ModelW& m, int cap, int max_req);

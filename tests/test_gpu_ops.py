@@ -66,8 +66,8 @@ def test_layernorm(prec, rows, D):
     g = (1 + 0.1 * RNG.standard_normal(D)).astype(np.float32)
     b = (0.1 * RNG.standard_normal(D)).astype(np.float32)
     y = torch.zeros((rows, D), dtype=_dt(prec)).cuda()
-    rc = _lib().revo_op_layernorm(prec, torch.tensor(x).cuda().data_ptr(), torch.tensor(g).cuda().data_ptr(),
-                                  torch.tensor(b).cuda().data_ptr(), y.data_ptr(), rows, D, None)
+    xd, gd, bd = torch.tensor(x).cuda(), torch.tensor(g).cuda(), torch.tensor(b).cuda()  # alive across the launch
+    rc = _lib().revo_op_layernorm(prec, xd.data_ptr(), gd.data_ptr(), bd.data_ptr(), y.data_ptr(), rows, D, None)
     assert rc == 0
     torch.cuda.synchronize()
     ref = oracle.layer_norm(x.astype(np.float64), g.astype(np.float64), b.astype(np.float64))
@@ -131,6 +131,7 @@ def test_attention_uniform_keys_average_values():
 def test_convert_bf16_rounding():
     x = (RNG.standard_normal(100003) * np.exp(RNG.uniform(-30, 30, 100003))).astype(np.float32)
     y = torch.zeros(x.size, dtype=torch.bfloat16).cuda()
-    assert _lib().revo_op_convert(BF16, torch.tensor(x).cuda().data_ptr(), y.data_ptr(), x.size, None) == 0
+    xd = torch.tensor(x).cuda()
+    assert _lib().revo_op_convert(BF16, xd.data_ptr(), y.data_ptr(), x.size, None) == 0
     torch.cuda.synchronize()
     assert np.array_equal(y.double().cpu().numpy(), oracle.bf16_round(x))
