@@ -4,12 +4,19 @@
 //
 // Each wave owns 32 queries.  Scores are computed transposed, S^T = K Q^T,
 // so that the 32x32 MFMA accumulator puts one query per lane (lanes l and
-// l+32 hold disjoint halves of the keys): the running max, the rescale of
-// the output and the row sum stay lane-local, with one cross-half exchange
-// per key block.  The output is also accumulated transposed, O^T = V^T P^T,
-// so the probabilities feed the MFMA straight from the score registers; V
-// is stored transposed ([head][dim][token]) by the QKV epilogue for that.
-// Q arrives pre-scaled by log2(e)/8, so probabilities are exp2(s - m).
+// l+32 hold disjoint halves of the keys): the running max, the row sum and
+// the rescale of the output stay lane-local, with one cross-half exchange
+// (v_permlane32_swap) per key block.  The output is also accumulated
+// transposed, O^T = V^T P^T, so the probabilities feed the MFMA straight
+// from the score registers; V is stored transposed ([head][dim][token]) by
+// the QKV epilogue for that.  Q arrives pre-scaled by log2(e)/8, so
+// probabilities are exp2(s - m).
+//
+// The running max is updated lazily: a query keeps its max until a block's
+// scores exceed it by more than 8 (in log2 units), so probabilities stay
+// below 2^8 and the output rescale is skipped for almost every block; the
+// final division by the row sum makes the result independent of the max
+// used.  Only the last key block of a request checks key bounds.
 // K and V^T blocks of 64 keys are double-buffered in LDS.
 #include "kernels.h"
 
@@ -21,159 +28,213 @@ constexpr int NT = 256;
 constexpr int QT = 128;   // queries per workgroup (4 waves x 32)
 constexpr int KB = 64;    // keys per block
 constexpr float NEG_BIG = -1.0e30f;
+constexpr float LAZY = 8.0f;
+
+// max / sum of a value and its partner lane (l ^ 32)
+__device__ __forceinline__ float xhalf_max(float x) {
+  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+__device__ __forceinline__ float xhalf_sum(float x) {
+  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+template <class T>
+struct AttnTile {
+  static constexpr int E = 16 / sizeof(T);   // elements per 16-byte chunk
+  static constexpr int PITCH = 64 + E;       // padded LDS row pitch (elements)
+  static constexpr int CPR = 64 / E;         // 16-byte chunks per 64-element row
+  static constexpr int LC = KB * CPR / NT;   // chunks per thread per tile
+  static constexpr int QCH = 32 / E;         // Q chunks per lane
+};
+
+// One 64-key block for one wave: scores, online softmax, P V accumulation.
+template <class Op, bool MASK>
+__device__ __forceinline__ void attn_block(const typename Op::T* __restrict__ kt, const typename Op::T* __restrict__ vt,
+                                           const uint4 (&qf)[AttnTile<typename Op::T>::QCH], f32x16 (&oacc)[2],
+                                           float& m_run, float& l_run, int lane, int kvalid) {
+  typedef typename Op::T T;
+  typedef AttnTile<T> A;
+  const int half = lane >> 5, l32 = lane & 31;
+
+  // S^T = K Q^T for two 32-key subtiles
+  f32x16 sacc[2] = {f32x16{}, f32x16{}};
+#pragma unroll
+  for (int kc = 0; kc < A::QCH; ++kc) {
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      const uint4 kf = *reinterpret_cast<const uint4*>(kt + (st * 32 + l32) * A::PITCH + half * 32 + kc * A::E);
+      if constexpr (sizeof(T) == 2) {
+        Op::mma(sacc[st], __builtin_bit_cast(bf16x8, kf), __builtin_bit_cast(bf16x8, qf[kc]));
+      } else {
+        Op::mma(sacc[st], __uint_as_float(kf.x), __uint_as_float(qf[kc].x));
+        Op::mma(sacc[st], __uint_as_float(kf.y), __uint_as_float(qf[kc].y));
+        Op::mma(sacc[st], __uint_as_float(kf.z), __uint_as_float(qf[kc].z));
+        Op::mma(sacc[st], __uint_as_float(kf.w), __uint_as_float(qf[kc].w));
+      }
+    }
+  }
+  if constexpr (MASK) {
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (st * 32 + acc_row(i, lane) >= kvalid) sacc[st][i] = NEG_BIG;
+  }
+
+  // block max of this query
+  float m0 = fmaxf(fmaxf(sacc[0][0], sacc[0][1]), sacc[0][2]);
+  float m1 = fmaxf(fmaxf(sacc[1][0], sacc[1][1]), sacc[1][2]);
+#pragma unroll
+  for (int i = 3; i < 15; i += 2) {
+    m0 = fmaxf(fmaxf(m0, sacc[0][i]), sacc[0][i + 1]);
+    m1 = fmaxf(fmaxf(m1, sacc[1][i]), sacc[1][i + 1]);
+  }
+  float mloc = fmaxf(fmaxf(m0, sacc[0][15]), fmaxf(m1, sacc[1][15]));
+  mloc = xhalf_max(mloc);
+  const bool grow = mloc > m_run + LAZY;
+  if (__any(grow)) {
+    const float m_new = grow ? mloc : m_run;
+    const float alpha = __builtin_amdgcn_exp2f(m_run - m_new);
+    m_run = m_new;
+    l_run *= alpha;
+#pragma unroll
+    for (int ds = 0; ds < 2; ++ds)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) oacc[ds][i] *= alpha;
+  }
+
+  // probabilities and their row sum (two partial sums per subtile)
+  float ls0 = 0.0f, ls1 = 0.0f, ls2 = 0.0f, ls3 = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 16; i += 2) {
+    sacc[0][i] = __builtin_amdgcn_exp2f(sacc[0][i] - m_run);
+    sacc[0][i + 1] = __builtin_amdgcn_exp2f(sacc[0][i + 1] - m_run);
+    sacc[1][i] = __builtin_amdgcn_exp2f(sacc[1][i] - m_run);
+    sacc[1][i + 1] = __builtin_amdgcn_exp2f(sacc[1][i + 1] - m_run);
+    ls0 += sacc[0][i];
+    ls1 += sacc[0][i + 1];
+    ls2 += sacc[1][i];
+    ls3 += sacc[1][i + 1];
+  }
+  l_run += (ls0 + ls1) + (ls2 + ls3);
+
+  // O^T += V^T P^T, contraction over the block's keys
+#pragma unroll
+  for (int st = 0; st < 2; ++st) {
+    if constexpr (sizeof(T) == 2) {
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        // registers 8g..8g+7 hold keys st*32 + g*16 + {half*4 + 0..3, 8 + half*4 + 0..3}
+        bf16x8 pf;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) pf[e] = (__bf16)sacc[st][8 * g + e];
+        const int key = st * 32 + g * 16 + half * 4;
+#pragma unroll
+        for (int ds = 0; ds < 2; ++ds) {
+          const T* vrow = vt + (ds * 32 + l32) * A::PITCH;
+          const uint2 lo = *reinterpret_cast<const uint2*>(vrow + key);
+          const uint2 hi = *reinterpret_cast<const uint2*>(vrow + key + 8);
+          Op::mma(oacc[ds], __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y)), pf);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        // registers 4g..4g+3 hold keys st*32 + g*8 + half*4 + 0..3
+        const int key = st * 32 + g * 8 + half * 4;
+#pragma unroll
+        for (int ds = 0; ds < 2; ++ds) {
+          const uint4 vv = *reinterpret_cast<const uint4*>(vt + (ds * 32 + l32) * A::PITCH + key);
+          Op::mma(oacc[ds], __uint_as_float(vv.x), sacc[st][4 * g + 0]);
+          Op::mma(oacc[ds], __uint_as_float(vv.y), sacc[st][4 * g + 1]);
+          Op::mma(oacc[ds], __uint_as_float(vv.z), sacc[st][4 * g + 2]);
+          Op::mma(oacc[ds], __uint_as_float(vv.w), sacc[st][4 * g + 3]);
+        }
+      }
+    }
+  }
+}
 
 template <class Op>
 __global__ __launch_bounds__(NT, 2) void attn_kernel(const AttnArgs a) {
   typedef typename Op::T T;
-  constexpr int E = 16 / sizeof(T);          // elements per 16-byte chunk
-  constexpr int PITCH = 64 + E;              // padded row pitch in elements
-  constexpr int CPR = 64 / E;                // 16-byte chunks per 64-element row
-  constexpr int LC = KB * CPR / NT;          // chunks per thread per tile
-  __shared__ __attribute__((aligned(16))) T ks[2][KB * PITCH];   // [key][dim]
-  __shared__ __attribute__((aligned(16))) T vs[2][64 * PITCH];   // [dim][key]
+  typedef AttnTile<T> A;
+  __shared__ __attribute__((aligned(16))) T ks[2][KB * A::PITCH];   // [key][dim]
+  __shared__ __attribute__((aligned(16))) T vs[2][64 * A::PITCH];   // [dim][key]
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int half = lane >> 5, l32 = lane & 31;
+  const int half = lane >> 5;
   const int w = a.work[blockIdx.x];
   const int r = w >> 16, qt = w & 0xFFFF;
   const int hd = blockIdx.y;
   const ReqDesc& d = a.reqs[r];
   const int N = d.J * d.P;
   const int base = d.tok_off;
-  const int q_local = qt * QT + wave * 32 + l32;
+  const int q_local = qt * QT + wave * 32 + (lane & 31);
   const int q = base + q_local;
 
   const T* __restrict__ Kg = (const T*)a.k + ((size_t)hd * a.ldqk + base) * 64;
   const T* __restrict__ Vg = (const T*)a.vt + (size_t)hd * 64 * a.ldv + base;
 
-  // Q^T fragment: this lane's query, dims [half*32, half*32 + 32)
-  constexpr int QCH = 32 / E;
-  uint4 qf[QCH];
+  // Q^T fragment: this lane's query, dims [half*32, half*32 + 32); queries
+  // past the request (ragged last tile) load row `base` and are never stored
+  uint4 qf[A::QCH];
   {
-    // queries past the request (ragged last tile) load row `base`; never stored
     const T* qp = (const T*)a.q + ((size_t)hd * a.ldqk + (q_local < N ? q : base)) * 64 + half * 32;
 #pragma unroll
-    for (int i = 0; i < QCH; ++i) qf[i] = reinterpret_cast<const uint4*>(qp)[i];
+    for (int i = 0; i < A::QCH; ++i) qf[i] = reinterpret_cast<const uint4*>(qp)[i];
   }
 
-  uint4 kr[LC], vr[LC];
-  auto load_block = [&](int kb) {
+  // per-thread chunk coordinates of a K / V^T tile
+  int c_row[A::LC], c_col[A::LC];
 #pragma unroll
-    for (int i = 0; i < LC; ++i) {
-      const int c = tid + i * NT, row = c / CPR, cc = c % CPR;
-      kr[i] = *reinterpret_cast<const uint4*>(Kg + (size_t)(kb + row) * 64 + cc * E);
-      vr[i] = *reinterpret_cast<const uint4*>(Vg + (size_t)row * a.ldv + kb + cc * E);
-    }
-  };
-  auto store_block = [&](int buf) {
+  for (int i = 0; i < A::LC; ++i) {
+    const int c = tid + i * NT;
+    c_row[i] = c / A::CPR;
+    c_col[i] = (c % A::CPR) * A::E;
+  }
+  uint4 kr[A::LC], vr[A::LC];
 #pragma unroll
-    for (int i = 0; i < LC; ++i) {
-      const int c = tid + i * NT, row = c / CPR, cc = c % CPR;
-      *reinterpret_cast<uint4*>(&ks[buf][row * PITCH + cc * E]) = kr[i];
-      *reinterpret_cast<uint4*>(&vs[buf][row * PITCH + cc * E]) = vr[i];
-    }
-  };
+  for (int i = 0; i < A::LC; ++i) {
+    kr[i] = *reinterpret_cast<const uint4*>(Kg + (size_t)c_row[i] * 64 + c_col[i]);
+    vr[i] = *reinterpret_cast<const uint4*>(Vg + (size_t)c_row[i] * a.ldv + c_col[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < A::LC; ++i) {
+    *reinterpret_cast<uint4*>(&ks[0][c_row[i] * A::PITCH + c_col[i]]) = kr[i];
+    *reinterpret_cast<uint4*>(&vs[0][c_row[i] * A::PITCH + c_col[i]]) = vr[i];
+  }
+  __syncthreads();
 
   f32x16 oacc[2] = {f32x16{}, f32x16{}};
   float m_run = NEG_BIG, l_run = 0.0f;
   const int nkb = (N + KB - 1) / KB;
-
-  load_block(0);
-  store_block(0);
-  __syncthreads();
   for (int b = 0; b < nkb; ++b) {
     const int buf = b & 1;
     const int kb = b * KB;
-    if (b + 1 < nkb) load_block(kb + KB);
-
-    // S^T = K Q^T for two 32-key subtiles
-    f32x16 sacc[2] = {f32x16{}, f32x16{}};
+    // prefetch the next block (the last iteration re-reads its own block,
+    // written to the idle buffer and never read)
+    const int kn = b + 1 < nkb ? kb + KB : kb;
 #pragma unroll
-    for (int kc = 0; kc < QCH; ++kc) {          // one 16-byte chunk of dims per lane
-#pragma unroll
-      for (int st = 0; st < 2; ++st) {
-        const uint4 kf = *reinterpret_cast<const uint4*>(&ks[buf][(st * 32 + l32) * PITCH + half * 32 + kc * E]);
-        if constexpr (sizeof(T) == 2) {
-          Op::mma(sacc[st], __builtin_bit_cast(bf16x8, kf), __builtin_bit_cast(bf16x8, qf[kc]));
-        } else {
-          Op::mma(sacc[st], __uint_as_float(kf.x), __uint_as_float(qf[kc].x));
-          Op::mma(sacc[st], __uint_as_float(kf.y), __uint_as_float(qf[kc].y));
-          Op::mma(sacc[st], __uint_as_float(kf.z), __uint_as_float(qf[kc].z));
-          Op::mma(sacc[st], __uint_as_float(kf.w), __uint_as_float(qf[kc].w));
-        }
-      }
+    for (int i = 0; i < A::LC; ++i) {
+      kr[i] = *reinterpret_cast<const uint4*>(Kg + (size_t)(kn + c_row[i]) * 64 + c_col[i]);
+      vr[i] = *reinterpret_cast<const uint4*>(Vg + (size_t)c_row[i] * a.ldv + kn + c_col[i]);
     }
-
-    // online softmax (lane-local per query, halves exchanged once)
-    float mloc = NEG_BIG;
-    const bool ragged = kb + KB > N;
+    if (kb + KB <= N)
+      attn_block<Op, false>(ks[buf], vs[buf], qf, oacc, m_run, l_run, lane, KB);
+    else
+      attn_block<Op, true>(ks[buf], vs[buf], qf, oacc, m_run, l_run, lane, N - kb);
 #pragma unroll
-    for (int st = 0; st < 2; ++st)
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        if (ragged && kb + st * 32 + acc_row(i, lane) >= N) sacc[st][i] = NEG_BIG;
-        mloc = fmaxf(mloc, sacc[st][i]);
-      }
-    mloc = fmaxf(mloc, __shfl_xor(mloc, 32));
-    const float m_new = fmaxf(m_run, mloc);
-    const float alpha = exp2f(m_run - m_new);
-    m_run = m_new;
-    float lsum = 0.0f;
-#pragma unroll
-    for (int st = 0; st < 2; ++st)
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const float p = exp2f(sacc[st][i] - m_new);
-        sacc[st][i] = p;
-        lsum += p;
-      }
-    l_run = l_run * alpha + lsum;
-#pragma unroll
-    for (int ds = 0; ds < 2; ++ds)
-#pragma unroll
-      for (int i = 0; i < 16; ++i) oacc[ds][i] *= alpha;
-
-    // O^T += V^T P^T, contraction over the block's keys
-#pragma unroll
-    for (int st = 0; st < 2; ++st) {
-      if constexpr (sizeof(T) == 2) {
-#pragma unroll
-        for (int g = 0; g < 2; ++g) {
-          // registers 8g..8g+7 hold keys st*32 + g*16 + {half*4 + 0..3, 8 + half*4 + 0..3}
-          bf16x8 pf;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) pf[e] = (__bf16)sacc[st][8 * g + e];
-          const int key = st * 32 + g * 16 + half * 4;
-#pragma unroll
-          for (int ds = 0; ds < 2; ++ds) {
-            const T* vrow = &vs[buf][(ds * 32 + l32) * PITCH];
-            const uint2 lo = *reinterpret_cast<const uint2*>(vrow + key);
-            const uint2 hi = *reinterpret_cast<const uint2*>(vrow + key + 8);
-            const uint4 vv = make_uint4(lo.x, lo.y, hi.x, hi.y);
-            Op::mma(oacc[ds], __builtin_bit_cast(bf16x8, vv), pf);
-          }
-        }
-      } else {
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          // registers 4g..4g+3 hold keys st*32 + g*8 + half*4 + 0..3
-          const int key = st * 32 + g * 8 + half * 4;
-#pragma unroll
-          for (int ds = 0; ds < 2; ++ds) {
-            const uint4 vv = *reinterpret_cast<const uint4*>(&vs[buf][(ds * 32 + l32) * PITCH + key]);
-            Op::mma(oacc[ds], __uint_as_float(vv.x), sacc[st][4 * g + 0]);
-            Op::mma(oacc[ds], __uint_as_float(vv.y), sacc[st][4 * g + 1]);
-            Op::mma(oacc[ds], __uint_as_float(vv.z), sacc[st][4 * g + 2]);
-            Op::mma(oacc[ds], __uint_as_float(vv.w), sacc[st][4 * g + 3]);
-          }
-        }
-      }
+    for (int i = 0; i < A::LC; ++i) {
+      *reinterpret_cast<uint4*>(&ks[buf ^ 1][c_row[i] * A::PITCH + c_col[i]]) = kr[i];
+      *reinterpret_cast<uint4*>(&vs[buf ^ 1][c_row[i] * A::PITCH + c_col[i]]) = vr[i];
     }
-    if (b + 1 < nkb) store_block(buf ^ 1);
     __syncthreads();
   }
 
-  const float l_tot = l_run + __shfl_xor(l_run, 32);
+  const float l_tot = xhalf_sum(l_run);
   if (q_local < N) {
     const float inv = 1.0f / l_tot;
     T* op = (T*)a.o + (size_t)q * (a.heads * 64) + hd * 64;

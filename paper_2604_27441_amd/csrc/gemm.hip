@@ -57,6 +57,9 @@ __device__ inline float pe_value(float s, int c, int d3) {
 // (j, y, x) is frame j*T + t, pixel (16y + py, 16x + px), channel c with
 // k = ((t*16 + py)*16 + px)*C + c.  Out-of-frame (padding) pixels and lost
 // target pixels read as zero; RGB is scaled by 1/255 and depth by 1/4000 mm.
+// A chunk never straddles a patch row (16*C is a multiple of E), so when
+// the patch row lies inside the frame and rows are 8-pixel aligned it is
+// one contiguous 4..16-byte load.
 template <class Op>
 __device__ uint4 gather_chunk(const ReqDesc& d, int j, int y, int x, int k, int C) {
   typedef typename Op::T T;
@@ -70,21 +73,63 @@ __device__ uint4 gather_chunk(const ReqDesc& d, int j, int y, int x, int k, int 
   const int Y = 16 * y + (rt & 15);
   const bool target = (f == d.nframes - 1);
   const int X0 = 16 * x;
+  float v[E];
+  if (Y < d.H && X0 + 16 <= d.W && (d.W & 7) == 0) {
+    const size_t rowpix = (size_t)Y * d.W + X0;
+    if (C == 3) {
+      const uint8_t* src = (const uint8_t*)d.frames[f] + rowpix * 3 + o;
+      uint32_t w[E / 4];
+      if constexpr (E == 8) {
+        const uint2 t = *reinterpret_cast<const uint2*>(src);
+        w[0] = t.x; w[1] = t.y;
+      } else {
+        w[0] = *reinterpret_cast<const uint32_t*>(src);
+      }
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int oe = o + e;
-    const int X = X0 + oe / C;
-    const int c = oe - (oe / C) * C;
-    float v = 0.0f;
-    if (Y < d.H && X < d.W) {
-      const size_t pix = (size_t)Y * d.W + X;
-      if (!(target && d.mask[pix])) {
-        if (C == 3) v = (float)((const uint8_t*)d.frames[f])[pix * 3 + c] / 255.0f;
-        else v = (float)((const uint16_t*)d.frames[f])[pix] / 4000.0f;
+      for (int e = 0; e < E; ++e) v[e] = (float)((w[e >> 2] >> (8 * (e & 3))) & 0xFF) * (1.0f / 255.0f);
+      if (target) {
+        const uint8_t* m = d.mask + rowpix;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          if (m[(o + e) / 3]) v[e] = 0.0f;
+      }
+    } else {
+      const uint16_t* src = (const uint16_t*)d.frames[f] + rowpix + o;
+      uint32_t w[E / 2];
+      if constexpr (E == 8) {
+        const uint4 t = *reinterpret_cast<const uint4*>(src);
+        w[0] = t.x; w[1] = t.y; w[2] = t.z; w[3] = t.w;
+      } else {
+        const uint2 t = *reinterpret_cast<const uint2*>(src);
+        w[0] = t.x; w[1] = t.y;
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = (float)((w[e >> 1] >> (16 * (e & 1))) & 0xFFFF) * (1.0f / 4000.0f);
+      if (target) {
+        const uint8_t* m = d.mask + rowpix + o;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          if (m[e]) v[e] = 0.0f;
       }
     }
-    r.v[e] = Op::from_float(v);
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int oe = o + e;
+      const int X = X0 + oe / C;
+      const int c = oe - (oe / C) * C;
+      v[e] = 0.0f;
+      if (Y < d.H && X < d.W) {
+        const size_t pix = (size_t)Y * d.W + X;
+        if (!(target && d.mask[pix])) {
+          if (C == 3) v[e] = (float)((const uint8_t*)d.frames[f])[pix * 3 + c] * (1.0f / 255.0f);
+          else v[e] = (float)((const uint16_t*)d.frames[f])[pix] * (1.0f / 4000.0f);
+        }
+      }
+    }
   }
+#pragma unroll
+  for (int e = 0; e < E; ++e) r.v[e] = Op::from_float(v[e]);
   return r.u;
 }
 
@@ -128,51 +173,53 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
     }
   }
 
+  // per-thread chunk coordinates within a stage
+  int c_row[XC > WC ? XC : WC], c_k[XC > WC ? XC : WC];
+#pragma unroll
+  for (int i = 0; i < (XC > WC ? XC : WC); ++i) {
+    c_row[i] = (tid + i * NT) >> 3;
+    c_k[i] = ((tid + i * NT) & 7) * E;
+  }
   uint4 xr[XC], wr[WC];
-  auto load_stage = [&](int kt) {
-    const int k0 = kt * BK;
-#pragma unroll
-    for (int i = 0; i < XC; ++i) {
-      const int c = tid + i * NT, row = c >> 3, kc = c & 7;
-      const int m = m0 + row;
-      if (XM == X_DENSE) {
-        xr[i] = m < a.M ? *reinterpret_cast<const uint4*>(X + (size_t)m * a.K + k0 + kc * E)
-                        : make_uint4(0, 0, 0, 0);
-      } else {
-        xr[i] = g_req[i] >= 0 ? gather_chunk<Op>(a.reqs[g_req[i]], g_j[i], g_y[i], g_x[i], k0 + kc * E, a.channels)
-                              : make_uint4(0, 0, 0, 0);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < WC; ++i) {
-      const int c = tid + i * NT, row = c >> 3, kc = c & 7;
-      wr[i] = *reinterpret_cast<const uint4*>(W + (size_t)(n0 + row) * a.K + k0 + kc * E);
-    }
-  };
-  auto store_stage = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < XC; ++i) {
-      const int c = tid + i * NT, row = c >> 3, kc = c & 7;
-      *reinterpret_cast<uint4*>(&xs[buf][row * PITCH + kc * E]) = xr[i];
-    }
-#pragma unroll
-    for (int i = 0; i < WC; ++i) {
-      const int c = tid + i * NT, row = c >> 3, kc = c & 7;
-      *reinterpret_cast<uint4*>(&ws[buf][row * PITCH + kc * E]) = wr[i];
-    }
-  };
+#define REVO_GEMM_LOAD(kt_)                                                                                  \
+  do {                                                                                                       \
+    const int k0_ = (kt_) * BK;                                                                              \
+    _Pragma("unroll") for (int i = 0; i < XC; ++i) {                                                         \
+      const int m_ = m0 + c_row[i];                                                                          \
+      if (XM == X_DENSE) {                                                                                   \
+        xr[i] = m_ < a.M ? *reinterpret_cast<const uint4*>(X + (size_t)m_ * a.K + k0_ + c_k[i])              \
+                         : make_uint4(0, 0, 0, 0);                                                           \
+      } else {                                                                                               \
+        xr[i] = g_req[i] >= 0                                                                                \
+                    ? gather_chunk<Op>(a.reqs[g_req[i]], g_j[i], g_y[i], g_x[i], k0_ + c_k[i], a.channels)   \
+                    : make_uint4(0, 0, 0, 0);                                                                \
+      }                                                                                                      \
+    }                                                                                                        \
+    _Pragma("unroll") for (int i = 0; i < WC; ++i)                                                           \
+      wr[i] = *reinterpret_cast<const uint4*>(W + (size_t)(n0 + c_row[i]) * a.K + k0_ + c_k[i]);             \
+  } while (0)
+#define REVO_GEMM_STORE(buf_)                                                                                \
+  do {                                                                                                       \
+    _Pragma("unroll") for (int i = 0; i < XC; ++i)                                                           \
+      *reinterpret_cast<uint4*>(&xs[buf_][c_row[i] * PITCH + c_k[i]]) = xr[i];                               \
+    _Pragma("unroll") for (int i = 0; i < WC; ++i)                                                           \
+      *reinterpret_cast<uint4*>(&ws[buf_][c_row[i] * PITCH + c_k[i]]) = wr[i];                               \
+  } while (0)
 
   const int wn = wave >> 1, wm = wave & 1;
   f32x16 acc[NSUB][2];
 #pragma unroll
   for (int i = 0; i < NSUB; ++i) { acc[i][0] = f32x16{}; acc[i][1] = f32x16{}; }
 
-  load_stage(0);
-  store_stage(0);
+  REVO_GEMM_LOAD(0);
+  REVO_GEMM_STORE(0);
   __syncthreads();
   for (int kt = 0; kt < KT; ++kt) {
     const int buf = kt & 1;
-    if (kt + 1 < KT) load_stage(kt + 1);
+    // prefetch the next stage (the last iteration re-reads its own stage into
+    // the idle buffer, which is never read)
+    const int kn = kt + 1 < KT ? kt + 1 : kt;
+    REVO_GEMM_LOAD(kn);
 #pragma unroll
     for (int s = 0; s < STEPS; s += G) {
       const int koff = half * (BK / 2) + s * Op::KPL;
@@ -191,9 +238,11 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
           for (int ms = 0; ms < 2; ++ms)
             Op::mma(acc[ns][ms], frag_of<Op>(wf[ns], g), frag_of<Op>(xf[ms], g));
     }
-    if (kt + 1 < KT) store_stage(buf ^ 1);
+    REVO_GEMM_STORE(buf ^ 1);
     __syncthreads();
   }
+#undef REVO_GEMM_LOAD
+#undef REVO_GEMM_STORE
 
   // ---------------------------------------------------------------- epilogue
 #pragma unroll
