@@ -99,47 +99,56 @@ __device__ __forceinline__ void attn_block(const typename Op::T* __restrict__ kt
     const float alpha = __builtin_amdgcn_exp2f(m_run - m_new);
     m_run = m_new;
     l_run *= alpha;
-#pragma unroll
-    for (int ds = 0; ds < 2; ++ds)
-#pragma unroll
-      for (int i = 0; i < 16; ++i) oacc[ds][i] *= alpha;
+    oacc[0] *= alpha;
+    oacc[1] *= alpha;
+    // keep the rescale inside this (rarely taken) branch instead of letting
+    // it become an unconditional multiply by a selected factor
+    asm volatile("" : "+v"(oacc[0]), "+v"(oacc[1]));
   }
-
-  // probabilities and their row sum (two partial sums per subtile)
-  float ls0 = 0.0f, ls1 = 0.0f, ls2 = 0.0f, ls3 = 0.0f;
-#pragma unroll
-  for (int i = 0; i < 16; i += 2) {
-    sacc[0][i] = __builtin_amdgcn_exp2f(sacc[0][i] - m_run);
-    sacc[0][i + 1] = __builtin_amdgcn_exp2f(sacc[0][i + 1] - m_run);
-    sacc[1][i] = __builtin_amdgcn_exp2f(sacc[1][i] - m_run);
-    sacc[1][i + 1] = __builtin_amdgcn_exp2f(sacc[1][i + 1] - m_run);
-    ls0 += sacc[0][i];
-    ls1 += sacc[0][i + 1];
-    ls2 += sacc[1][i];
-    ls3 += sacc[1][i + 1];
-  }
-  l_run += (ls0 + ls1) + (ls2 + ls3);
 
   // O^T += V^T P^T, contraction over the block's keys
+  if constexpr (sizeof(T) == 2) {
+    // row sum from the bf16-rounded probabilities that also feed the MFMA
+    const bf16x2 one = {(__bf16)1.0f, (__bf16)1.0f};
+    float ls0 = 0.0f, ls1 = 0.0f;
 #pragma unroll
-  for (int st = 0; st < 2; ++st) {
-    if constexpr (sizeof(T) == 2) {
+    for (int st = 0; st < 2; ++st) {
 #pragma unroll
       for (int g = 0; g < 2; ++g) {
-        // registers 8g..8g+7 hold keys st*32 + g*16 + {half*4 + 0..3, 8 + half*4 + 0..3}
+        // registers 8g..8g+7 hold keys st*32 + g*16 + {half*4 + 0..3, 8 + half*4 + 0..3};
+        // V^T rows hold keys with bits 2 and 3 swapped, so those keys are the
+        // 8 contiguous elements at st*32 + g*16 + half*8
         bf16x8 pf;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) pf[e] = (__bf16)sacc[st][8 * g + e];
-        const int key = st * 32 + g * 16 + half * 4;
+        for (int e = 0; e < 8; ++e) pf[e] = (__bf16)__builtin_amdgcn_exp2f(sacc[st][8 * g + e] - m_run);
+        ls0 = __builtin_amdgcn_fdot2_f32_bf16(bf16x2{pf[0], pf[1]}, one, ls0, false);
+        ls1 = __builtin_amdgcn_fdot2_f32_bf16(bf16x2{pf[2], pf[3]}, one, ls1, false);
+        ls0 = __builtin_amdgcn_fdot2_f32_bf16(bf16x2{pf[4], pf[5]}, one, ls0, false);
+        ls1 = __builtin_amdgcn_fdot2_f32_bf16(bf16x2{pf[6], pf[7]}, one, ls1, false);
+        const int pos = st * 32 + g * 16 + half * 8;
 #pragma unroll
         for (int ds = 0; ds < 2; ++ds) {
-          const T* vrow = vt + (ds * 32 + l32) * A::PITCH;
-          const uint2 lo = *reinterpret_cast<const uint2*>(vrow + key);
-          const uint2 hi = *reinterpret_cast<const uint2*>(vrow + key + 8);
-          Op::mma(oacc[ds], __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y)), pf);
+          const uint4 vv = *reinterpret_cast<const uint4*>(vt + (ds * 32 + l32) * A::PITCH + pos);
+          Op::mma(oacc[ds], __builtin_bit_cast(bf16x8, vv), pf);
         }
       }
-    } else {
+    }
+    l_run += ls0 + ls1;
+  } else {
+    float ls0 = 0.0f, ls1 = 0.0f;
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+#pragma unroll
+      for (int i = 0; i < 16; i += 2) {
+        sacc[st][i] = __builtin_amdgcn_exp2f(sacc[st][i] - m_run);
+        sacc[st][i + 1] = __builtin_amdgcn_exp2f(sacc[st][i + 1] - m_run);
+        ls0 += sacc[st][i];
+        ls1 += sacc[st][i + 1];
+      }
+    }
+    l_run += ls0 + ls1;
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
         // registers 4g..4g+3 hold keys st*32 + g*8 + half*4 + 0..3
@@ -158,7 +167,7 @@ __device__ __forceinline__ void attn_block(const typename Op::T* __restrict__ kt
 }
 
 template <class Op>
-__global__ __launch_bounds__(NT, 2) void attn_kernel(const AttnArgs a) {
+__global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 4 : 2) void attn_kernel(const AttnArgs a) {
   typedef typename Op::T T;
   typedef AttnTile<T> A;
   __shared__ __attribute__((aligned(16))) T ks[2][KB * A::PITCH];   // [key][dim]
@@ -187,52 +196,64 @@ __global__ __launch_bounds__(NT, 2) void attn_kernel(const AttnArgs a) {
     for (int i = 0; i < A::QCH; ++i) qf[i] = reinterpret_cast<const uint4*>(qp)[i];
   }
 
-  // per-thread chunk coordinates of a K / V^T tile
-  int c_row[A::LC], c_col[A::LC];
-#pragma unroll
-  for (int i = 0; i < A::LC; ++i) {
-    const int c = tid + i * NT;
-    c_row[i] = c / A::CPR;
-    c_col[i] = (c % A::CPR) * A::E;
+  // per-thread chunk coordinates of a K / V^T tile: chunk i of a thread is
+  // tile element (row c_row + i * R, column c_col), R = NT / CPR rows apart
+  constexpr int R = NT / A::CPR;
+  const int c_row = tid / A::CPR;
+  const int c_col = (tid % A::CPR) * A::E;
+  static_assert(A::LC == 2 || A::LC == 4, "2 or 4 chunks per thread");
+  uint4 kr0, kr1, kr2, kr3, vr0, vr1, vr2, vr3;
+#define REVO_ATTN_LOAD1(kb_, i_, kr_, vr_)                                                            \
+  kr_ = *reinterpret_cast<const uint4*>(Kg + (size_t)((kb_) + c_row + (i_) * R) * 64 + c_col);       \
+  vr_ = *reinterpret_cast<const uint4*>(Vg + (size_t)(c_row + (i_) * R) * a.ldv + (kb_) + c_col);
+#define REVO_ATTN_LOAD(kb_)                                                                           \
+  REVO_ATTN_LOAD1(kb_, 0, kr0, vr0)                                                                   \
+  REVO_ATTN_LOAD1(kb_, 1, kr1, vr1)                                                                   \
+  if constexpr (A::LC == 4) { REVO_ATTN_LOAD1(kb_, 2, kr2, vr2) REVO_ATTN_LOAD1(kb_, 3, kr3, vr3) }
+  // V^T rows are stored with bits 2 and 3 of the key index swapped (bf16):
+  // a chunk of keys c..c+7 lands at c..c+3 and c+8..c+11 (c % 16 == 0) or at
+  // c-4..c-1 and c+4..c+7 (c % 16 == 8)
+#define REVO_ATTN_STORE1(buf_, i_, kr_, vr_)                                                          \
+  {                                                                                                   \
+    *reinterpret_cast<uint4*>(&ks[buf_][(c_row + (i_) * R) * A::PITCH + c_col]) = kr_;                \
+    T* vrow_ = &vs[buf_][(c_row + (i_) * R) * A::PITCH];                                              \
+    if constexpr (sizeof(T) == 2) {                                                                   \
+      const int p0_ = c_col & 8 ? c_col - 4 : c_col;                                                 \
+      *reinterpret_cast<uint2*>(vrow_ + p0_) = make_uint2(vr_.x, vr_.y);                              \
+      *reinterpret_cast<uint2*>(vrow_ + p0_ + 8) = make_uint2(vr_.z, vr_.w);                          \
+    } else {                                                                                          \
+      *reinterpret_cast<uint4*>(vrow_ + c_col) = vr_;                                                 \
+    }                                                                                                 \
   }
-  uint4 kr[A::LC], vr[A::LC];
-#pragma unroll
-  for (int i = 0; i < A::LC; ++i) {
-    kr[i] = *reinterpret_cast<const uint4*>(Kg + (size_t)c_row[i] * 64 + c_col[i]);
-    vr[i] = *reinterpret_cast<const uint4*>(Vg + (size_t)c_row[i] * a.ldv + c_col[i]);
-  }
-#pragma unroll
-  for (int i = 0; i < A::LC; ++i) {
-    *reinterpret_cast<uint4*>(&ks[0][c_row[i] * A::PITCH + c_col[i]]) = kr[i];
-    *reinterpret_cast<uint4*>(&vs[0][c_row[i] * A::PITCH + c_col[i]]) = vr[i];
-  }
+#define REVO_ATTN_STORE(buf_)                                                                         \
+  REVO_ATTN_STORE1(buf_, 0, kr0, vr0)                                                                 \
+  REVO_ATTN_STORE1(buf_, 1, kr1, vr1)                                                                 \
+  if constexpr (A::LC == 4) { REVO_ATTN_STORE1(buf_, 2, kr2, vr2) REVO_ATTN_STORE1(buf_, 3, kr3, vr3) }
+
+  REVO_ATTN_LOAD(0);
+  REVO_ATTN_STORE(0);
   __syncthreads();
 
   f32x16 oacc[2] = {f32x16{}, f32x16{}};
   float m_run = NEG_BIG, l_run = 0.0f;
   const int nkb = (N + KB - 1) / KB;
-  for (int b = 0; b < nkb; ++b) {
+  const int nfull = N / KB;
+  for (int b = 0; b < nfull; ++b) {
     const int buf = b & 1;
-    const int kb = b * KB;
-    // prefetch the next block (the last iteration re-reads its own block,
-    // written to the idle buffer and never read)
-    const int kn = b + 1 < nkb ? kb + KB : kb;
-#pragma unroll
-    for (int i = 0; i < A::LC; ++i) {
-      kr[i] = *reinterpret_cast<const uint4*>(Kg + (size_t)(kn + c_row[i]) * 64 + c_col[i]);
-      vr[i] = *reinterpret_cast<const uint4*>(Vg + (size_t)c_row[i] * a.ldv + kn + c_col[i]);
-    }
-    if (kb + KB <= N)
-      attn_block<Op, false>(ks[buf], vs[buf], qf, oacc, m_run, l_run, lane, KB);
-    else
-      attn_block<Op, true>(ks[buf], vs[buf], qf, oacc, m_run, l_run, lane, N - kb);
-#pragma unroll
-    for (int i = 0; i < A::LC; ++i) {
-      *reinterpret_cast<uint4*>(&ks[buf ^ 1][c_row[i] * A::PITCH + c_col[i]]) = kr[i];
-      *reinterpret_cast<uint4*>(&vs[buf ^ 1][c_row[i] * A::PITCH + c_col[i]]) = vr[i];
-    }
+    // prefetch the next block (the last iteration re-reads its own block
+    // into the idle buffer, which is then never read)
+    const int kn = b + 1 < nkb ? (b + 1) * KB : b * KB;
+    REVO_ATTN_LOAD(kn);
+    attn_block<Op, false>(ks[buf], vs[buf], qf, oacc, m_run, l_run, lane, KB);
+    REVO_ATTN_STORE(buf ^ 1);
     __syncthreads();
   }
+  if (nfull < nkb)  // ragged last block, already in LDS
+    attn_block<Op, true>(ks[nfull & 1], vs[nfull & 1], qf, oacc, m_run, l_run, lane, N - nfull * KB);
+#undef REVO_ATTN_LOAD1
+#undef REVO_ATTN_LOAD
+#undef REVO_ATTN_STORE1
+#undef REVO_ATTN_STORE
 
   const float l_tot = xhalf_sum(l_run);
   if (q_local < N) {
