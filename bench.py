@@ -40,13 +40,13 @@ def model_flop_per_request(N, P, C, T=2, De=384, Dd=192, ne=12, nd=4):
     return f
 
 
-def run_form(precision, reqs, blobs, steps, warmup, log):
+def run_form(precision, reqs, blobs, steps, warmup, log, one_stream=False):
     import torch
     from paper_2604_27441_amd import Recoverer
     from tests.gpu_util import dev, push_refs
 
     rec = Recoverer(blobs[0], blobs[1], precision=precision, device=0, max_batch_tokens=4 * 10800 + 64,
-                    max_batch=8, profile=True)
+                    max_batch=8, profile=True, one_stream=one_stream)
     for s, r in enumerate(reqs):
         push_refs(rec, s, r)
     H, W = reqs[0]["height"], reqs[0]["width"]
@@ -88,6 +88,21 @@ def run_form(precision, reqs, blobs, steps, warmup, log):
     pct = lambda p: lat[min(len(lat) - 1, int(round(p / 100.0 * (len(lat) - 1))))]
     return dict(seconds=dt, pairs=steps * len(reqs), ms_per_step=1e3 * dt / steps,
                 p50_ms=pct(50), p99_ms=pct(99), stats=st)
+
+
+def attention_traffic():
+    """HBM bytes per attention launch from the committed counter record, or
+    None when the kernel source changed since the counters were taken."""
+    import hashlib
+    rec_path = os.path.join(ROOT, "profiles", "attn_bf16_720p_b4_traffic.json")
+    try:
+        rec = json.load(open(rec_path))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec["bytes_per_launch"]
 
 
 def cpu_baseline(req, log):
@@ -138,6 +153,11 @@ def main():
     ap.add_argument("--fp32-steps", type=int, default=3)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="run RGB and depth one after the other on one stream (clean per-kernel times)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one device-to-device copy of MIB MiB (a kernel of known traffic "
+                         "for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the recovery path has no multi-GPU form here "
@@ -147,17 +167,27 @@ def main():
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
+    if args.copy_calibration > 0:
+        import torch
+        n = args.copy_calibration << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {n} bytes read + {n} bytes written")
+        del src, dst
+
     import synth
     t = time.perf_counter()
     reqs = synth.make_batch("c3")
     blobs = synth.make_weights(0)
     log(f"inputs ready ({time.perf_counter() - t:.1f} s)")
 
-    bf = run_form(1, reqs, blobs, args.steps, args.warmup, log)
+    bf = run_form(1, reqs, blobs, args.steps, args.warmup, log, args.one_stream)
     log(f"bf16: {bf['ms_per_step']:.2f} ms/step")
     fp = None
     if not args.no_fp32:
-        fp = run_form(0, reqs, blobs, args.fp32_steps, 1, log)
+        fp = run_form(0, reqs, blobs, args.fp32_steps, 1, log, args.one_stream)
         log(f"fp32: {fp['ms_per_step']:.2f} ms/step")
 
     N, P = 10800, 3600
@@ -184,6 +214,7 @@ def main():
             "encoder": "384x12 (6 heads)", "decoder": "192x4 (3 heads)", "patch": 16,
             "loss": "Gilbert-Elliott, mean 20%, burst 4 slices", "weights": "He-normal, seed 0",
             "parallelism": "single GPU",
+            "streams": 1 if args.one_stream else 2,
         },
         "p50_ms": bf["p50_ms"],
         "p99_ms": bf["p99_ms"],
@@ -198,7 +229,8 @@ def main():
             "peak": BF16_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": attn_tflops / BF16_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": attention_traffic(),
+            "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)",
             "launches": st["attn_launches"],
             "avg_launch_ms": st["attn_ms"] / max(1, st["attn_launches"]),
             "flop_per_launch": st["attn_flop"] / max(1, st["attn_launches"]),

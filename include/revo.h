@@ -67,6 +67,8 @@ enum revo_completion_status {
 /* revo_config.flags */
 #define REVO_CFG_SHED 0x1u    /* shed requests whose deadline cannot be met */
 #define REVO_CFG_PROFILE 0x2u /* time every kernel launch with HIP events (see revo_get_stats) */
+#define REVO_CFG_ONE_STREAM 0x4u /* run the RGB and depth networks one after the other on one stream
+                                   (default: two streams that overlap on the GPU) */
 
 typedef struct revo_config {
   int device;                 /* HIP device ordinal */

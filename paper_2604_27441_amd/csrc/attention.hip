@@ -175,9 +175,16 @@ __global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 4 : 2) void attn_
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5;
-  const int w = a.work[blockIdx.x];
+  // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+  // L2).  Remap so that XCD x runs a contiguous range of (head, q-tile) work:
+  // the q-tiles of one request and head then share its K/V in one L2.
+  const int G = a.nwork * a.heads;
+  const int L = blockIdx.x;
+  const int xcd = L & 7, per = G >> 3, rem = G & 7;
+  const int Lr = xcd * per + (xcd < rem ? xcd : rem) + (L >> 3);
+  const int hd = Lr / a.nwork;
+  const int w = a.work[Lr - hd * a.nwork];
   const int r = w >> 16, qt = w & 0xFFFF;
-  const int hd = blockIdx.y;
   const ReqDesc& d = a.reqs[r];
   const int N = d.J * d.P;
   const int base = d.tok_off;
@@ -281,7 +288,7 @@ __global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 4 : 2) void attn_
 
 int launch_attention(Prec prec, const AttnArgs& a, hipStream_t s) {
   if (a.nwork <= 0) return 0;
-  dim3 grid(a.nwork, a.heads);
+  dim3 grid(a.nwork * a.heads);
   if (prec == P_BF16) attn_kernel<OpBF16><<<grid, NT, 0, s>>>(a);
   else if (prec == P_FP32) attn_kernel<OpF32><<<grid, NT, 0, s>>>(a);
   else return -95;

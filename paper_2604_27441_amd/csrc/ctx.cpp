@@ -485,8 +485,10 @@ int revo_recover_create(const revo_config* cfg_in, revo_ctx** out) {
   c->rings[0].resize(cfg.max_streams);
   c->rings[1].resize(cfg.max_streams);
   int rc = 0;
-  for (int q = 0; q < 2 && !rc; ++q)
+  const int nstreams = (cfg.flags & REVO_CFG_ONE_STREAM) ? 1 : 2;
+  for (int q = 0; q < nstreams && !rc; ++q)
     if (hipStreamCreateWithFlags(&c->stream[q], hipStreamNonBlocking) != hipSuccess) rc = REVO_EDEVICE;
+  if (nstreams == 1) c->stream[1] = c->stream[0];
   if (!rc && hipStreamCreateWithFlags(&c->copy, hipStreamNonBlocking) != hipSuccess) rc = REVO_EDEVICE;
   if (!rc) rc = model_load(c->model[0], 3, T, cfg.enc_depth, cfg.dec_depth, c->prec, cfg.weights_rgb, cfg.n_weights_rgb, c->stream[0]);
   if (!rc) rc = model_load(c->model[1], 1, T, cfg.enc_depth, cfg.dec_depth, c->prec, cfg.weights_depth, cfg.n_weights_depth, c->stream[1]);
@@ -612,8 +614,8 @@ void revo_recover_destroy(revo_ctx* c) {
     model_free(c->model[q]);
   }
   c->pool.clear();
-  for (int q = 0; q < 2; ++q)
-    if (c->stream[q]) (void)hipStreamDestroy(c->stream[q]);
+  if (c->stream[0]) (void)hipStreamDestroy(c->stream[0]);
+  if (c->stream[1] && c->stream[1] != c->stream[0]) (void)hipStreamDestroy(c->stream[1]);
   if (c->copy) (void)hipStreamDestroy(c->copy);
   delete c;
 }

@@ -43,14 +43,31 @@ template <> __device__ inline bf16x8 frag_of<OpBF16>(const uint4& u, int) {
 
 __device__ inline float gelu_erf(float v) { return 0.5f * v * (1.0f + erff(v * 0.70710678118654752f)); }
 
+// sin (odd == 0) or cos (odd == 1) of x for |x| up to a few thousand, without
+// scratch memory: x = n (pi/2) + r with a three-part Cody-Waite reduction,
+// then the single-precision minimax polynomials of the Cephes library
+// (S. L. Moshier) on |r| <= pi/4.
+__device__ inline float sincos_small(float x, int odd) {
+  const float n = rintf(x * 0.636619772367581343f);
+  float r = fmaf(n, -1.5703125f, x);
+  r = fmaf(n, -4.837512969970703125e-4f, r);
+  r = fmaf(n, -7.54978995489188216e-8f, r);
+  const int q = ((int)n + odd) & 3;  // cos(x) = sin(x + pi/2)
+  const float z = r * r;
+  const float sp = fmaf(fmaf(fmaf(-1.9515295891e-4f, z, 8.3321608736e-3f), z, -1.6666654611e-1f), z * r, r);
+  const float cp = fmaf(fmaf(fmaf(2.443315711809948e-5f, z, -1.388731625493765e-3f), z, 4.166664568298827e-2f), z * z,
+                        fmaf(-0.5f, z, 1.0f));
+  const float v = (q & 1) ? cp : sp;
+  return (q & 2) ? -v : v;
+}
+
 // Sinusoid of the three-axis positional embedding: column c of a D-wide
-// embedding for position s (axis c / (D/3)), sin at even, cos at odd columns.
+// embedding for position s (axis c / (D/3)), sin at even, cos at odd columns,
+// frequency 10000^(-2i/(D/3)) for the column pair i.
 __device__ inline float pe_value(float s, int c, int d3) {
   const int i2 = (c % d3) >> 1;
   const float freq = exp2f(-(float)(2 * i2) / (float)d3 * 13.287712379549449f);  // log2(10000)
-  float sn, cs;
-  sincosf(s * freq, &sn, &cs);
-  return (c & 1) ? cs : sn;
+  return sincos_small(s * freq, c & 1);
 }
 
 // One 16-byte chunk (E elements) of a tubelet vector: element k of token

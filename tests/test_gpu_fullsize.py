@@ -1,0 +1,88 @@
+"""Parity at the full 1280x720 size, batch of 4 (the launch configuration
+bench.py times), on sampled outputs of the FP64 oracle precomputed by
+tests/golden/make_golden.py (synth + oracle only), plus properties that hold
+at any size for every request of the batch."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import check_received_and_codes, push_refs, recover
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_720p_samples.json")
+
+
+@pytest.fixture(scope="module")
+def c3():
+    return synth.make_batch("c3"), synth.make_weights(0), json.load(open(GOLDEN))
+
+
+def _run(c3, prec):
+    from paper_2604_27441_amd import Recoverer
+    reqs, blobs, _ = c3
+    with Recoverer(blobs[0], blobs[1], precision=prec, max_batch_tokens=4 * 10800 + 64, max_batch=8) as rec:
+        for s, r in enumerate(reqs):
+            push_refs(rec, s, r)
+        outs = recover(rec, list(enumerate(reqs)))
+    for r, o in zip(reqs, outs):
+        assert o["completion"].status == 0
+        check_received_and_codes(r, o)
+    return outs
+
+
+def _sample_errors(g, out):
+    res = {}
+    for mod, key, scale in (("rgb", "rgb_f", 1.0), ("depth", "depth_f", 1.0)):
+        y, x = np.array(g[mod]["y"]), np.array(g[mod]["x"])
+        ref = np.array(g[mod]["oracle"], np.float64)
+        emu = np.array(g[mod]["oracle_bf16_rounding"], np.float64)
+        got = out[key][y, x].astype(np.float64)
+        lost = slice(0, 1536)  # the first 1536 samples are lost pixels, the rest received
+        res[mod] = dict(err=got - ref, emu=emu - ref, lost=lost)
+    return res
+
+
+def test_fullsize_fp32_samples(c3):
+    g = c3[2]
+    out = _run(c3, 0)[0]
+    e = _sample_errors(g, out)
+    rgb, dep = e["rgb"], e["depth"]
+    print("fp32 720p: rgb max", np.abs(rgb["err"]).max(), "depth max mm", np.abs(dep["err"]).max())
+    # received samples are exact copies
+    assert np.all(rgb["err"][1536:] == 0) and np.all(dep["err"][1536:] == 0)
+    assert np.abs(rgb["err"]).max() <= 2e-4
+    assert np.abs(dep["err"]).max() <= 1.0
+
+
+def test_fullsize_bf16_samples(c3):
+    g = c3[2]
+    out = _run(c3, 1)[0]
+    e = _sample_errors(g, out)
+    for mod in ("rgb", "depth"):
+        err, emu = e[mod]["err"][:1536], e[mod]["emu"][:1536]
+        rms, rms_emu = np.sqrt(np.mean(err ** 2)), np.sqrt(np.mean(emu ** 2))
+        print(f"bf16 720p {mod}: rms {rms:.4g} (rounding oracle {rms_emu:.4g}), max {np.abs(err).max():.4g} "
+              f"(rounding oracle {np.abs(emu).max():.4g})")
+        assert np.all(e[mod]["err"][1536:] == 0)
+        assert rms <= np.sqrt(2.0) * rms_emu, (mod, rms, rms_emu)
+        assert np.abs(err).max() <= 4.0 * max(np.abs(emu).max(), 1e-6), mod
+    rgb_all = e["rgb"]["err"]
+    psnr = 10 * np.log10(1.0 / np.mean(rgb_all[:1536] ** 2))
+    assert psnr >= 45.0, psnr
+
+
+def test_fullsize_batch_members_are_independent(c3):
+    """Every request of the 720p batch equals the same request run alone."""
+    from paper_2604_27441_amd import Recoverer
+    reqs, blobs, _ = c3
+    with Recoverer(blobs[0], blobs[1], precision=1, max_batch_tokens=4 * 10800 + 64, max_batch=8) as rec:
+        for s, r in enumerate(reqs):
+            push_refs(rec, s, r)
+        mixed = recover(rec, list(enumerate(reqs)))
+        alone = recover(rec, [(3, reqs[3])])[0]
+    for key in ("rgb", "depth", "rgb_f", "depth_f"):
+        assert np.array_equal(mixed[3][key], alone[key]), key
