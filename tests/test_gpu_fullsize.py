@@ -52,8 +52,9 @@ def test_fullsize_fp32_samples(c3):
     e = _sample_errors(g, out)
     rgb, dep = e["rgb"], e["depth"]
     print("fp32 720p: rgb max", np.abs(rgb["err"]).max(), "depth max mm", np.abs(dep["err"]).max())
-    # received samples are exact copies
-    assert np.all(rgb["err"][1536:] == 0) and np.all(dep["err"][1536:] == 0)
+    # received samples are copies: depth in whole mm, RGB the float32 u/255
+    # (within half an ulp of 1.0 and the fixture's 9 decimals)
+    assert np.abs(rgb["err"][1536:]).max() <= 6e-8 + 1e-9 and np.all(dep["err"][1536:] == 0)
     assert np.abs(rgb["err"]).max() <= 2e-4
     assert np.abs(dep["err"]).max() <= 1.0
 
@@ -67,7 +68,7 @@ def test_fullsize_bf16_samples(c3):
         rms, rms_emu = np.sqrt(np.mean(err ** 2)), np.sqrt(np.mean(emu ** 2))
         print(f"bf16 720p {mod}: rms {rms:.4g} (rounding oracle {rms_emu:.4g}), max {np.abs(err).max():.4g} "
               f"(rounding oracle {np.abs(emu).max():.4g})")
-        assert np.all(e[mod]["err"][1536:] == 0)
+        assert np.abs(e[mod]["err"][1536:]).max() <= (6e-8 + 1e-9 if mod == "rgb" else 0.0)
         assert rms <= np.sqrt(2.0) * rms_emu, (mod, rms, rms_emu)
         assert np.abs(err).max() <= 4.0 * max(np.abs(emu).max(), 1e-6), mod
     rgb_all = e["rgb"]["err"]

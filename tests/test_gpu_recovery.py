@@ -161,3 +161,20 @@ def test_clean_frame_copy_and_missing_references():
         other = synth.make_request(83, 84, 48, 64, loss=("stripes", 0.5))
         out = recover(rec, [(5, other)])[0]
         assert out["completion"].status == 2 and out["completion"].error == -61
+
+
+@pytest.mark.parametrize("loss", [0.10, 0.30, 0.50])
+def test_c2_640x480_fp32_parity(loss):
+    """640x480, one pair, Gilbert-Elliott slice loss at mean 10/30/50 %, full
+    12 + 4 block model, FP32 form against the FP64 oracle."""
+    req = synth.make_request(1002, 2002, 480, 640, loss=("ge", loss))
+    blobs = synth.make_weights(0)
+    with _rec(blobs, FP32) as rec:
+        push_refs(rec, 0, req)
+        out = recover(rec, [(0, req)])[0]
+    ref = oracle.recover(req, blobs)
+    check_received_and_codes(req, out)
+    e = compare(req, out, ref)
+    print(f"c2 fp32 L={loss}", e)
+    assert e["rgb_psnr"] >= 80.0, e
+    assert e["depth_maxabs"] <= 0.5, e
