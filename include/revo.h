@@ -69,6 +69,8 @@ enum revo_completion_status {
 #define REVO_CFG_PROFILE 0x2u /* time every kernel launch with HIP events (see revo_get_stats) */
 #define REVO_CFG_ONE_STREAM 0x4u /* run the RGB and depth networks one after the other on one stream
                                    (default: two streams that overlap on the GPU) */
+#define REVO_CFG_GRAPHS 0x8u  /* replay each network as a HIP graph captured once per token-capacity
+                                 bucket (cap/8, cap/4, cap/2, cap); ignored with REVO_CFG_PROFILE */
 
 typedef struct revo_config {
   int device;                 /* HIP device ordinal */

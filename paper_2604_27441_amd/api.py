@@ -41,7 +41,8 @@ class Recoverer:
 
     def __init__(self, weights_rgb, weights_depth, precision=REVO_BF16, device=0, k=5, tubelet=2,
                  enc_depth=0, dec_depth=0, composite=1, max_streams=64, max_batch=16, max_batch_tokens=0,
-                 hbm_budget_bytes=0, fps=30.0, shed=False, profile=False, one_stream=False):
+                 hbm_budget_bytes=0, fps=30.0, shed=False, profile=False, one_stream=False,
+                 graphs=False):
         cfg = RevoConfig()
         lib.revo_config_default(C.byref(cfg))
         self._w = [np.ascontiguousarray(weights_rgb, np.float32), np.ascontiguousarray(weights_depth, np.float32)]
@@ -50,7 +51,7 @@ class Recoverer:
         cfg.max_streams, cfg.max_batch, cfg.max_batch_tokens = max_streams, max_batch, max_batch_tokens
         cfg.hbm_budget_bytes, cfg.fps = hbm_budget_bytes, fps
         cfg.flags = ((_lib.REVO_CFG_SHED if shed else 0) | (_lib.REVO_CFG_PROFILE if profile else 0)
-                     | (_lib.REVO_CFG_ONE_STREAM if one_stream else 0))
+                     | (_lib.REVO_CFG_ONE_STREAM if one_stream else 0) | (_lib.REVO_CFG_GRAPHS if graphs else 0))
         cfg.weights_rgb = self._w[0].ctypes.data_as(C.POINTER(C.c_float))
         cfg.n_weights_rgb = self._w[0].size
         cfg.weights_depth = self._w[1].ctypes.data_as(C.POINTER(C.c_float))

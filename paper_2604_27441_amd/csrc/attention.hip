@@ -178,12 +178,14 @@ __global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 4 : 2) void attn_
   // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
   // L2).  Remap so that XCD x runs a contiguous range of (head, q-tile) work:
   // the q-tiles of one request and head then share its K/V in one L2.
-  const int G = a.nwork * a.heads;
+  const int nwork = a.dyn_nwork ? *a.dyn_nwork : a.nwork;
+  const int G = nwork * a.heads;
   const int L = blockIdx.x;
+  if (L >= G) return;  // grid sized for a capacity
   const int xcd = L & 7, per = G >> 3, rem = G & 7;
   const int Lr = xcd * per + (xcd < rem ? xcd : rem) + (L >> 3);
-  const int hd = Lr / a.nwork;
-  const int w = a.work[Lr - hd * a.nwork];
+  const int hd = Lr / nwork;
+  const int w = a.work[Lr - hd * nwork];
   const int r = w >> 16, qt = w & 0xFFFF;
   const ReqDesc& d = a.reqs[r];
   const int N = d.J * d.P;

@@ -129,6 +129,11 @@ struct Job {
 
 }  // namespace
 
+namespace {
+struct InFlight;
+}
+typedef InFlight* InFlightPtr;
+
 struct revo_ctx {
   revo_config cfg;
   int T = 2, k = 5, J = 3, nframes = 6;
@@ -147,7 +152,16 @@ struct revo_ctx {
   std::deque<revo_completion> done;
   bool stop = false;
   std::atomic<unsigned long long> next_ticket{1};
-  std::thread worker;
+  std::thread worker, completer;
+  std::deque<InFlightPtr> inflight;          // batches on the GPU, oldest first
+  std::vector<int> free_slots;               // host descriptor slots not in flight
+  std::condition_variable cv_inflight;
+  bool completer_stop = false;
+  int inflight_max = 2;
+  bool use_graphs = false;
+  hipEvent_t done_ev[WS_SLOTS][2] = {};
+  hipStream_t d2h = nullptr;
+  double busy_until_ns = 0.0;
   int device_error = 0;
   double sec_per_unit = 2e-11;  // cost model for shedding (seconds per work unit)
   std::mutex stats_mu;
@@ -245,10 +259,20 @@ void fill_desc(revo_ctx* c, Job* j, int q, ReqDesc& d) {
   for (int jj = 0; jj < d.J; ++jj) d.tau[jj] = (float)(j->frame - seq[jj * c->T].index);
 }
 
-int run_batch(revo_ctx* c, std::vector<Job*>& batch) {
-  // descriptors: per modality, recoveries first, then clean copies
+// A batch enqueued on the GPU, waiting for its completion events.
+struct InFlight {
+  std::vector<Job*> batch;
+  int slot = 0;
+  int rc = 0;
+  double units = 0.0;
+  long long t_enq = 0;
+};
+
+// Enqueue one batch (descriptors in host slot `slot`) on the modality streams
+// and record its completion events.
+int launch_batch(revo_ctx* c, InFlight* f) {
   std::vector<std::pair<Job*, int>> rec[2], cln[2];
-  for (Job* j : batch) {
+  for (Job* j : f->batch) {
     if (j->status != REVO_DONE) continue;
     for (int q = 0; q < 2; ++q) {
       Mod& m = j->mod[q];
@@ -259,29 +283,90 @@ int run_batch(revo_ctx* c, std::vector<Job*>& batch) {
   int rc = 0;
   for (int q = 0; q < 2; ++q) {
     Workspace& w = c->ws[q];
+    ReqDesc* hr = w.h_reqs_slot[f->slot];
     int n = 0;
-    for (auto& e : rec[q]) fill_desc(c, e.first, q, w.h_reqs[n++]);
+    for (auto& e : rec[q]) fill_desc(c, e.first, q, hr[n++]);
     const int nrec = n;
-    for (auto& e : cln[q]) fill_desc(c, e.first, q, w.h_reqs[n++]);
+    for (auto& e : cln[q]) fill_desc(c, e.first, q, hr[n++]);
     if (n == 0) continue;
-    int e = forward(c->model[q], w, nrec, n, c->cfg.composite, c->stream[q]);
+    const int e = forward(c->model[q], w, f->slot, nrec, n, c->cfg.composite, c->use_graphs, c->stream[q]);
     if (e) rc = e;
   }
   for (int q = 0; q < 2; ++q)
-    if (hipStreamSynchronize(c->stream[q]) != hipSuccess) rc = REVO_EDEVICE;
-  // host outputs
-  for (Job* j : batch) {
-    if (j->status != REVO_DONE) continue;
+    if (hipEventRecord(c->done_ev[f->slot][q], c->stream[q]) != hipSuccess) rc = REVO_EDEVICE;
+  return rc;
+}
+
+// Wait for a batch, copy host outputs, post its completions.
+void complete_batch(revo_ctx* c, InFlight* f) {
+  int rc = f->rc;
+  for (int q = 0; q < 2; ++q)
+    if (hipEventSynchronize(c->done_ev[f->slot][q]) != hipSuccess) rc = REVO_EDEVICE;
+  for (Job* j : f->batch) {
+    if (j->status != REVO_DONE || rc) continue;
     for (int q = 0; q < 2; ++q) {
       Mod& m = j->mod[q];
       if (!m.present || m.error || m.out_dev) continue;
       const size_t px = (size_t)m.H * m.W;
-      if (m.out_i && hipMemcpy(m.out_i, m.out_i_st, m.frame_bytes, hipMemcpyDeviceToHost) != hipSuccess) rc = REVO_EDEVICE;
-      if (m.out_f && hipMemcpy(m.out_f, m.out_f_st, px * (q == 0 ? 3 : 1) * 4, hipMemcpyDeviceToHost) != hipSuccess)
+      if (m.out_i && hipMemcpyAsync(m.out_i, m.out_i_st, m.frame_bytes, hipMemcpyDeviceToHost, c->d2h) != hipSuccess)
+        rc = REVO_EDEVICE;
+      if (m.out_f &&
+          hipMemcpyAsync(m.out_f, m.out_f_st, px * (q == 0 ? 3 : 1) * 4, hipMemcpyDeviceToHost, c->d2h) != hipSuccess)
         rc = REVO_EDEVICE;
     }
   }
-  return rc;
+  if (hipStreamSynchronize(c->d2h) != hipSuccess) rc = REVO_EDEVICE;
+  const double dt = (now_ns() - f->t_enq) * 1e-9;
+  if (f->units > 0.0 && rc == 0 && c->inflight_max == 1) c->sec_per_unit = 0.8 * c->sec_per_unit + 0.2 * (dt / f->units);
+  if (rc) {
+    c->device_error = rc;
+    for (Job* j : f->batch)
+      if (j->status == REVO_DONE) { j->status = REVO_FAILED; j->error = rc; }
+  }
+  {
+    std::lock_guard<std::mutex> lk(c->stats_mu);
+    revo_stats& st = c->stats;
+    st.batches += 1;
+    for (Job* j : f->batch) {
+      if (j->status == REVO_DONE) st.served++;
+      else if (j->status == REVO_SHED) st.shed++;
+      else st.failed++;
+    }
+    for (int q = 0; q < 2; ++q) {
+      Prof& p = c->ws[q].prof;
+      if (!p.on) continue;
+      if (rc == 0) (void)prof_collect(p);
+      p.recs.clear();
+      p.used = 0;
+      st.attn_launches += p.count[PK_ATTN]; st.attn_ms += p.ms[PK_ATTN]; st.attn_flop += p.flop[PK_ATTN];
+      st.gemm_launches += p.count[PK_GEMM]; st.gemm_ms += p.ms[PK_GEMM]; st.gemm_flop += p.flop[PK_GEMM];
+      st.other_launches += p.count[PK_OTHER]; st.other_ms += p.ms[PK_OTHER];
+      st.forward_ms += p.ms[PK_FORWARD];
+      for (int k = 0; k < PK_N; ++k) { p.ms[k] = 0; p.flop[k] = 0; p.count[k] = 0; }
+    }
+  }
+  for (Job* j : f->batch) finish(c, j);
+}
+
+void completer_main(revo_ctx* c) {
+  (void)hipSetDevice(c->cfg.device);
+  for (;;) {
+    InFlight* f = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(c->mu);
+      c->cv_inflight.wait(lk, [&] { return !c->inflight.empty() || c->completer_stop; });
+      if (c->inflight.empty()) return;
+      f = c->inflight.front();
+    }
+    complete_batch(c, f);
+    {
+      std::lock_guard<std::mutex> lk(c->mu);
+      c->inflight.pop_front();
+      c->free_slots.push_back(f->slot);
+    }
+    c->cv_work.notify_all();
+    delete f;
+  }
 }
 
 void worker_main(revo_ctx* c) {
@@ -290,11 +375,12 @@ void worker_main(revo_ctx* c) {
   const int max_batch = c->cfg.max_batch;
   for (;;) {
     std::vector<Job*> batch;
+    int slot = -1;
     {
       std::unique_lock<std::mutex> lk(c->mu);
       for (;;) {
         if (c->stop && c->queue.empty()) return;
-        if (!c->queue.empty()) {
+        if (!c->queue.empty() && !c->free_slots.empty()) {
           bool release = c->stop;
           for (Job* j : c->queue)
             if (!(j->flags & REVO_HOLD)) { release = true; break; }
@@ -305,6 +391,8 @@ void worker_main(revo_ctx* c) {
         }
         c->cv_work.wait(lk);
       }
+      slot = c->free_slots.back();
+      c->free_slots.pop_back();
       // take jobs in order while they fit; stop before a clean frame of a
       // stream that already has a recovery in this batch
       int tokens[2] = {0, 0};
@@ -335,15 +423,17 @@ void worker_main(revo_ctx* c) {
     }
     c->cv_done.notify_all();  // queue space freed
 
-    // shedding, ring updates and reference checks in submission order
+    // shedding, ring updates and reference checks in submission order; the
+    // finish-time estimate starts when the GPU drains what is already queued
     const long long t0 = now_ns();
+    const double start = std::max((double)t0, c->busy_until_ns);
     double units = 0.0;
     for (Job* j : batch) {
       double ju = 0.0;
       for (int q = 0; q < 2; ++q)
         if (j->mod[q].present && !j->mod[q].clean) ju += work_units(request_tokens(j->mod[q].H, j->mod[q].W, c->J));
       if ((c->cfg.flags & REVO_CFG_SHED) && ju > 0.0) {
-        const double finish = (double)t0 + 1e9 * c->sec_per_unit * (units + ju);
+        const double finish = start + 1e9 * c->sec_per_unit * (units + ju);
         if ((double)j->deadline < finish) j->status = REVO_SHED;
       }
       if (j->status == REVO_DONE) units += ju;
@@ -365,37 +455,18 @@ void worker_main(revo_ctx* c) {
         }
       }
     }
-    const int rc = run_batch(c, batch);
-    const double dt = (now_ns() - t0) * 1e-9;
-    if (units > 0.0 && rc == 0) c->sec_per_unit = 0.8 * c->sec_per_unit + 0.2 * (dt / units);
-    if (rc) {
-      c->device_error = rc;
-      for (Job* j : batch)
-        if (j->status == REVO_DONE) { j->status = REVO_FAILED; j->error = rc; }
-    }
+    c->busy_until_ns = start + 1e9 * c->sec_per_unit * units;
+    InFlight* f = new InFlight();
+    f->batch.swap(batch);
+    f->slot = slot;
+    f->units = units;
+    f->t_enq = t0;
+    f->rc = launch_batch(c, f);
     {
-      std::lock_guard<std::mutex> lk(c->stats_mu);
-      revo_stats& st = c->stats;
-      st.batches += 1;
-      for (Job* j : batch) {
-        if (j->status == REVO_DONE) st.served++;
-        else if (j->status == REVO_SHED) st.shed++;
-        else st.failed++;
-      }
-      for (int q = 0; q < 2; ++q) {
-        Prof& p = c->ws[q].prof;
-        if (!p.on) continue;
-        if (rc == 0) (void)prof_collect(p);
-        p.recs.clear();
-        p.used = 0;
-        st.attn_launches += p.count[PK_ATTN]; st.attn_ms += p.ms[PK_ATTN]; st.attn_flop += p.flop[PK_ATTN];
-        st.gemm_launches += p.count[PK_GEMM]; st.gemm_ms += p.ms[PK_GEMM]; st.gemm_flop += p.flop[PK_GEMM];
-        st.other_launches += p.count[PK_OTHER]; st.other_ms += p.ms[PK_OTHER];
-        st.forward_ms += p.ms[PK_FORWARD];
-        for (int k = 0; k < PK_N; ++k) { p.ms[k] = 0; p.flop[k] = 0; p.count[k] = 0; }
-      }
+      std::lock_guard<std::mutex> lk(c->mu);
+      c->inflight.push_back(f);
     }
-    for (Job* j : batch) finish(c, j);
+    c->cv_inflight.notify_all();
   }
 }
 
@@ -490,6 +561,10 @@ int revo_recover_create(const revo_config* cfg_in, revo_ctx** out) {
     if (hipStreamCreateWithFlags(&c->stream[q], hipStreamNonBlocking) != hipSuccess) rc = REVO_EDEVICE;
   if (nstreams == 1) c->stream[1] = c->stream[0];
   if (!rc && hipStreamCreateWithFlags(&c->copy, hipStreamNonBlocking) != hipSuccess) rc = REVO_EDEVICE;
+  if (!rc && hipStreamCreateWithFlags(&c->d2h, hipStreamNonBlocking) != hipSuccess) rc = REVO_EDEVICE;
+  for (int sl = 0; sl < WS_SLOTS && !rc; ++sl)
+    for (int q = 0; q < 2 && !rc; ++q)
+      if (hipEventCreateWithFlags(&c->done_ev[sl][q], hipEventDisableTiming) != hipSuccess) rc = REVO_EDEVICE;
   if (!rc) rc = model_load(c->model[0], 3, T, cfg.enc_depth, cfg.dec_depth, c->prec, cfg.weights_rgb, cfg.n_weights_rgb, c->stream[0]);
   if (!rc) rc = model_load(c->model[1], 1, T, cfg.enc_depth, cfg.dec_depth, c->prec, cfg.weights_depth, cfg.n_weights_depth, c->stream[1]);
   if (!rc) {
@@ -520,7 +595,11 @@ int revo_recover_create(const revo_config* cfg_in, revo_ctx** out) {
     revo_recover_destroy(c);
     return rc < 0 ? rc : REVO_EDEVICE;
   }
+  c->inflight_max = (cfg.flags & REVO_CFG_PROFILE) ? 1 : WS_SLOTS;  // event records are per workspace
+  c->use_graphs = (cfg.flags & REVO_CFG_GRAPHS) != 0;
+  for (int sl = 0; sl < c->inflight_max; ++sl) c->free_slots.push_back(sl);
   c->worker = std::thread(worker_main, c);
+  c->completer = std::thread(completer_main, c);
   *out = c;
   return REVO_OK;
 }
@@ -605,6 +684,12 @@ void revo_recover_destroy(revo_ctx* c) {
   }
   c->cv_work.notify_all();
   if (c->worker.joinable()) c->worker.join();
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->completer_stop = true;
+  }
+  c->cv_inflight.notify_all();
+  if (c->completer.joinable()) c->completer.join();
   (void)hipSetDevice(c->cfg.device);
   for (int q = 0; q < 2; ++q) {
     if (c->stream[q]) (void)hipStreamSynchronize(c->stream[q]);
@@ -617,6 +702,10 @@ void revo_recover_destroy(revo_ctx* c) {
   if (c->stream[0]) (void)hipStreamDestroy(c->stream[0]);
   if (c->stream[1] && c->stream[1] != c->stream[0]) (void)hipStreamDestroy(c->stream[1]);
   if (c->copy) (void)hipStreamDestroy(c->copy);
+  if (c->d2h) (void)hipStreamDestroy(c->d2h);
+  for (int sl = 0; sl < WS_SLOTS; ++sl)
+    for (int q = 0; q < 2; ++q)
+      if (c->done_ev[sl][q]) (void)hipEventDestroy(c->done_ev[sl][q]);
   delete c;
 }
 

@@ -12,9 +12,12 @@ namespace {
 template <class T>
 __global__ __launch_bounds__(256) void layernorm_kernel(const float* __restrict__ x, const float* __restrict__ g,
                                                         const float* __restrict__ b, T* __restrict__ y, int rows,
-                                                        int D, const ReqDesc* reqs, int nreq) {
+                                                        int D, const ReqDesc* reqs, int nreq,
+                                                        const int* dyn_rows, const int* dyn_nreq) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (dyn_rows) rows = *dyn_rows;
+  if (dyn_nreq) nreq = *dyn_nreq;
   if (row >= rows) return;
   int src = row;
   if (reqs) {
@@ -56,11 +59,12 @@ __global__ __launch_bounds__(256) void layernorm_kernel(const float* __restrict_
 // (RGB in [0, 1], depth in [0, 65535] mm) quantised half-to-even, received
 // pixels are copied unchanged.  A request without a mask is a clean frame
 // and is copied; composite == 0 gives every pixel the prediction.
-__global__ __launch_bounds__(256) void composite_kernel(const ReqDesc* __restrict__ reqs, int C, int composite) {
+__global__ __launch_bounds__(256) void composite_kernel(const ReqDesc* __restrict__ reqs, int C, int composite,
+                                                        const int* dyn_nreq) {
+  if (dyn_nreq && (int)blockIdx.y >= *dyn_nreq) return;
   const ReqDesc& d = reqs[blockIdx.y];
   const int npix = d.H * d.W;
-  const int pix = blockIdx.x * 256 + threadIdx.x;
-  if (pix >= npix) return;
+  for (int pix = blockIdx.x * 256 + threadIdx.x; pix < npix; pix += gridDim.x * 256) {
   const bool lost = d.mask != nullptr && (composite == 0 || d.mask[pix] != 0);
   const void* recv = d.frames[d.nframes - 1];
   if (C == 3) {
@@ -93,6 +97,7 @@ __global__ __launch_bounds__(256) void composite_kernel(const ReqDesc* __restric
       if (oi) oi[pix] = u;
     }
   }
+  }
 }
 
 template <class T>
@@ -114,18 +119,22 @@ __global__ void zero_tail_kernel(uint8_t* __restrict__ p, long long n) {
 }  // namespace
 
 int launch_layernorm(Prec out_prec, const float* x, const float* g, const float* b, void* y, int rows, int D,
-                     const ReqDesc* reqs, int nreq, hipStream_t s) {
+                     const ReqDesc* reqs, int nreq, hipStream_t s, const int* dyn_rows, const int* dyn_nreq) {
   if (rows <= 0) return 0;
   if (D > 512) return -22;
   dim3 grid(cdiv(rows, 4));
-  if (out_prec == P_BF16) layernorm_kernel<__bf16><<<grid, 256, 0, s>>>(x, g, b, (__bf16*)y, rows, D, reqs, nreq);
-  else layernorm_kernel<float><<<grid, 256, 0, s>>>(x, g, b, (float*)y, rows, D, reqs, nreq);
+  if (out_prec == P_BF16)
+    layernorm_kernel<__bf16><<<grid, 256, 0, s>>>(x, g, b, (__bf16*)y, rows, D, reqs, nreq, dyn_rows, dyn_nreq);
+  else
+    layernorm_kernel<float><<<grid, 256, 0, s>>>(x, g, b, (float*)y, rows, D, reqs, nreq, dyn_rows, dyn_nreq);
   return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 
-int launch_composite(const ReqDesc* reqs, int nreq, int channels, int max_pixels, int composite, hipStream_t s) {
+int launch_composite(const ReqDesc* reqs, int nreq, int channels, int max_pixels, int composite, hipStream_t s,
+                     const int* dyn_nreq) {
   if (nreq <= 0 || max_pixels <= 0) return 0;
-  composite_kernel<<<dim3(cdiv(max_pixels, 256), nreq), 256, 0, s>>>(reqs, channels, composite);
+  const int bx = cdiv(max_pixels, 256) < 1024 ? cdiv(max_pixels, 256) : 1024;  // grid-stride beyond
+  composite_kernel<<<dim3(bx, nreq), 256, 0, s>>>(reqs, channels, composite, dyn_nreq);
   return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 

@@ -167,6 +167,9 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
   const int m0 = blockIdx.x * BM;
+  const int Mlive = a.dyn_m ? *a.dyn_m : a.M;
+  const int nreq = a.dyn_nreq ? *a.dyn_nreq : a.nreq;
+  if (m0 >= Mlive) return;  // grid sized for a capacity
   const int n0 = blockIdx.y * BN;
   const int KT = a.K / BK;
   const T* __restrict__ W = (const T*)a.W;
@@ -179,8 +182,8 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
     for (int i = 0; i < XC; ++i) {
       const int m = m0 + ((tid + i * NT) >> 3);
       g_req[i] = -1;
-      if (m < a.M) {
-        const int r = find_req_tok(a.reqs, a.nreq, m);
+      if (m < Mlive) {
+        const int r = find_req_tok(a.reqs, nreq, m);
         const ReqDesc& d = a.reqs[r];
         const int t = m - d.tok_off;
         const int j = t / d.P, p = t - (t / d.P) * d.P;
@@ -204,7 +207,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
     _Pragma("unroll") for (int i = 0; i < XC; ++i) {                                                         \
       const int m_ = m0 + c_row[i];                                                                          \
       if (XM == X_DENSE) {                                                                                   \
-        xr[i] = m_ < a.M ? *reinterpret_cast<const uint4*>(X + (size_t)m_ * a.K + k0_ + c_k[i])              \
+        xr[i] = m_ < Mlive ? *reinterpret_cast<const uint4*>(X + (size_t)m_ * a.K + k0_ + c_k[i])            \
                          : make_uint4(0, 0, 0, 0);                                                           \
       } else {                                                                                               \
         xr[i] = g_req[i] >= 0                                                                                \
@@ -265,17 +268,17 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
 #pragma unroll
   for (int ms = 0; ms < 2; ++ms) {
     const int m = m0 + wm * 64 + ms * 32 + l32;
-    if (m >= a.M) continue;
+    if (m >= Mlive) continue;
     int r = 0, tj = 0, ty = 0, tx = 0;
     if (EPI == EPI_PE) {
-      r = find_req_tok(a.reqs, a.nreq, m);
+      r = find_req_tok(a.reqs, nreq, m);
       const ReqDesc& d = a.reqs[r];
       const int t = m - d.tok_off;
       tj = t / d.P;
       const int p = t - tj * d.P;
       ty = p / d.gx; tx = p - ty * d.gx;
     } else if (EPI == EPI_HEAD) {
-      r = find_req_head(a.reqs, a.nreq, m);
+      r = find_req_head(a.reqs, nreq, m);
       const ReqDesc& d = a.reqs[r];
       const int p = m - d.head_off;
       ty = p / d.gx; tx = p - ty * d.gx;

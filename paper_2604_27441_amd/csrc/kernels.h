@@ -41,8 +41,14 @@ enum XMode {
   X_GATHER = 1,      // tubelet vectors gathered from the request's frames
 };
 
+// Batch shape in device memory (read by kernels launched with grids sized
+// for a capacity, e.g. from a captured graph): rows past the live counts exit.
+enum BatchHdr { HDR_M = 0, HDR_MH = 1, HDR_NREC = 2, HDR_NALL = 3, HDR_NWORK = 4, HDR_N = 8 };
+
 struct GemmArgs {
-  int M, N, K;
+  int M, N, K;       // M sizes the grid; the live row count is *dyn_m when set
+  const int* dyn_m;  // nullable
+  const int* dyn_nreq;  // nullable: live request count for the gather / PE / head lookups
   const void* X;     // X_DENSE: [M][K] operand elements
   const void* W;     // [N][K] operand elements
   const float* bias; // [N]
@@ -62,7 +68,9 @@ struct AttnArgs {
   int heads, ldqk, ldv;
   const ReqDesc* reqs; int nreq;
   const int* work;   // per workgroup: (request << 16) | q-tile
-  int nwork;
+  int nwork;         // sizes the grid; the live count is *dyn_nwork when set
+  const int* dyn_nwork;  // nullable
+  const int* dyn_nreq;   // nullable
 };
 
 int launch_gemm(Prec prec, int epi, int xmode, const GemmArgs& a, hipStream_t s);
@@ -70,10 +78,12 @@ int launch_attention(Prec prec, const AttnArgs& a, hipStream_t s);
 // y = LN(x) * g + b over rows of length D.  With reqs set, output row i is
 // the target-tubelet token (i - head_off) of the request owning compact row i.
 int launch_layernorm(Prec out_prec, const float* x, const float* g, const float* b,
-                     void* y, int rows, int D, const ReqDesc* reqs, int nreq, hipStream_t s);
+                     void* y, int rows, int D, const ReqDesc* reqs, int nreq, hipStream_t s,
+                     const int* dyn_rows = nullptr, const int* dyn_nreq = nullptr);
 // Output frames.  Requests with a null mask are clean frames (copied).  With
 // composite == 0 every pixel of a recovered frame takes the prediction.
-int launch_composite(const ReqDesc* reqs, int nreq, int channels, int max_pixels, int composite, hipStream_t s);
+int launch_composite(const ReqDesc* reqs, int nreq, int channels, int max_pixels, int composite, hipStream_t s,
+                     const int* dyn_nreq = nullptr);
 int launch_convert(Prec prec, const float* src, void* dst, long long n, hipStream_t s);
 int launch_fill_zero(void* p, long long bytes, hipStream_t s);
 

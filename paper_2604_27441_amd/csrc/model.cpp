@@ -9,7 +9,7 @@ namespace revo {
 
 namespace {
 
-size_t esize(Prec p) { return p == P_BF16 ? 2 : 4; }
+size_t esize(Prec p) { return p == P_BF16 ? 2 : 4; }  // operand bytes
 
 size_t block_count(int D) { return 2 * D + 3 * D * D + 3 * D + D * D + D + 2 * D + 4 * D * D + 4 * D + 4 * D * D + D; }
 
@@ -139,7 +139,7 @@ size_t workspace_bytes(const ModelW& m, int cap, int max_req) {
   b += (size_t)cap * 4 * De * e;         // hid
   b += (size_t)cap * m.Dd * 4;           // z
   b += (size_t)cap * m.Dd * e;           // ahead (target rows <= cap)
-  b += (size_t)max_req * sizeof(ReqDesc) + (size_t)(cap / 128 + max_req + 1) * 4;
+  b += (size_t)max_req * sizeof(ReqDesc) + (size_t)(cap / 128 + max_req + 1) * 4 + HDR_N * 4;
   return b + 16 * 256;
 }
 
@@ -165,83 +165,74 @@ int workspace_alloc(Workspace& w, const ModelW& m, int cap, int max_req, hipStre
   rc |= get(&w.ahead, (size_t)cap * m.Dd * e);
   rc |= get((void**)&w.d_reqs, (size_t)max_req * sizeof(ReqDesc));
   rc |= get((void**)&w.d_work, (size_t)w.max_work * 4);
+  rc |= get((void**)&w.d_hdr, HDR_N * 4);
   if (rc) return rc < 0 ? rc : -5;
-  REVO_HIP_TRY(hipHostMalloc((void**)&w.h_reqs, (size_t)max_req * sizeof(ReqDesc), hipHostMallocDefault));
-  REVO_HIP_TRY(hipHostMalloc((void**)&w.h_work, (size_t)w.max_work * 4, hipHostMallocDefault));
-  memset(w.h_reqs, 0, (size_t)max_req * sizeof(ReqDesc));
+  for (int sl = 0; sl < WS_SLOTS; ++sl) {
+    REVO_HIP_TRY(hipHostMalloc((void**)&w.h_reqs_slot[sl], (size_t)max_req * sizeof(ReqDesc), hipHostMallocDefault));
+    REVO_HIP_TRY(hipHostMalloc((void**)&w.h_work_slot[sl], (size_t)w.max_work * 4, hipHostMallocDefault));
+    REVO_HIP_TRY(hipHostMalloc((void**)&w.h_hdr_slot[sl], HDR_N * 4, hipHostMallocDefault));
+    memset(w.h_reqs_slot[sl], 0, (size_t)max_req * sizeof(ReqDesc));
+  }
+  w.h_reqs = w.h_reqs_slot[0];
   REVO_HIP_TRY(hipStreamSynchronize(s));
   return 0;
 }
 
 void workspace_free(Workspace& w) {
   prof_free(w.prof);
-  void* dev[] = {w.h, w.a, w.q, w.k, w.vt, w.o, w.hid, w.z, w.ahead, w.d_reqs, w.d_work};
+  for (auto& g : w.graph)
+    if (g) (void)hipGraphExecDestroy(g);
+  void* dev[] = {w.h, w.a, w.q, w.k, w.vt, w.o, w.hid, w.z, w.ahead, w.d_reqs, w.d_work, w.d_hdr};
   for (void* p : dev)
     if (p) (void)hipFree(p);
-  if (w.h_reqs) (void)hipHostFree(w.h_reqs);
-  if (w.h_work) (void)hipHostFree(w.h_work);
+  for (int sl = 0; sl < WS_SLOTS; ++sl) {
+    if (w.h_reqs_slot[sl]) (void)hipHostFree(w.h_reqs_slot[sl]);
+    if (w.h_work_slot[sl]) (void)hipHostFree(w.h_work_slot[sl]);
+    if (w.h_hdr_slot[sl]) (void)hipHostFree(w.h_hdr_slot[sl]);
+  }
   w = Workspace();
 }
 
-int forward(const ModelW& m, Workspace& w, int nrec, int nall, int composite, hipStream_t s) {
-  if (nall <= 0) return 0;
-  if (nall > w.max_req || nrec > nall) return -22;
-  // token and head-row offsets, attention work list
-  int M = 0, Mh = 0, nwork = 0, max_pix = 0;
-  for (int r = 0; r < nall; ++r) {
-    ReqDesc& d = w.h_reqs[r];
-    d.gy = cdiv(d.H, REVO_PATCH);
-    d.gx = cdiv(d.W, REVO_PATCH);
-    d.P = d.gy * d.gx;
-    if (d.H * d.W > max_pix) max_pix = d.H * d.W;
-    if (r >= nrec) { d.tok_off = M; d.head_off = Mh; continue; }
-    M = (M + 7) & ~7;  // 16-byte aligned V^T columns for every request
-    d.tok_off = M;
-    d.head_off = Mh;
-    const int N = d.J * d.P;
-    for (int qt = 0; qt * 128 < N; ++qt) {
-      if (nwork >= w.max_work) return -22;
-      w.h_work[nwork++] = (r << 16) | qt;
-    }
-    M += N;
-    Mh += d.P;
-  }
-  if (M > w.cap) return -22;
-  double Mreal = 0.0, Mh_real = Mh, attn_pairs = 0.0;  // tokens, head rows, sum of N^2
-  for (int r = 0; r < nrec; ++r) {
-    const double N = (double)w.h_reqs[r].J * w.h_reqs[r].P;
-    Mreal += N;
-    attn_pairs += N * N;
-  }
+namespace {
+
+// Launch sequence of the network.  Grid sizes come from the arguments (exact
+// counts when eager, bucket capacities when captured); with dyn set, the
+// kernels read the live counts from the device batch header.
+int enqueue_net(const ModelW& m, Workspace& w, int Mg, int Mhg, int nworkg, int nrec, int nall, int max_pix,
+                int composite, bool dyn, double Mreal, double Mh_real, double attn_pairs, hipStream_t s) {
+  const Prec p = m.prec;
+  const int* H = dyn ? w.d_hdr : nullptr;
   ProfScope whole(w.prof, s, PK_FORWARD, 0.0);
   auto gemm = [&](int epi, int xm, const GemmArgs& ga, double rows) {
     ProfScope ps(w.prof, s, PK_GEMM, 2.0 * rows * ga.N * ga.K);
-    return launch_gemm(m.prec, epi, xm, ga, s);
+    return launch_gemm(p, epi, xm, ga, s);
   };
-  auto ln = [&](const float* x, const float* gg, const float* bb, void* y, int rows, int D, const ReqDesc* rq, int nq) {
+  auto ln = [&](const float* x, const float* gg, const float* bb, void* y, int rows, int D, const ReqDesc* rq,
+                int nq, const int* dyn_rows) {
     ProfScope ps(w.prof, s, PK_OTHER, 0.0);
-    return launch_layernorm(m.prec, x, gg, bb, y, rows, D, rq, nq, s);
+    return launch_layernorm(p, x, gg, bb, y, rows, D, rq, nq, s, dyn_rows, H ? H + HDR_NREC : nullptr);
   };
-  REVO_HIP_TRY(hipMemcpyAsync(w.d_reqs, w.h_reqs, (size_t)nall * sizeof(ReqDesc), hipMemcpyHostToDevice, s));
+  int rc = 0;
   if (nrec > 0) {
-    REVO_HIP_TRY(hipMemcpyAsync(w.d_work, w.h_work, (size_t)nwork * 4, hipMemcpyHostToDevice, s));
-    const Prec p = m.prec;
-    int rc = 0;
     GemmArgs g;
     memset(&g, 0, sizeof(g));
     g.reqs = w.d_reqs; g.nreq = nrec; g.channels = m.C;
+    g.dyn_m = H ? H + HDR_M : nullptr;
+    g.dyn_nreq = H ? H + HDR_NREC : nullptr;
     // tubelet embedding (implicit GEMM over the gathered frames) + PE
-    g.M = M; g.N = m.De; g.K = m.tub_len(); g.W = m.emb_w; g.bias = m.emb_b; g.out = w.h; g.ldo = m.De;
+    g.M = Mg; g.N = m.De; g.K = m.tub_len(); g.W = m.emb_w; g.bias = m.emb_b; g.out = w.h; g.ldo = m.De;
     if ((rc = gemm(EPI_PE, X_GATHER, g, Mreal))) return rc;
 
     AttnArgs at;
     memset(&at, 0, sizeof(at));
     at.q = w.q; at.k = w.k; at.vt = w.vt; at.o = w.o; at.ldqk = w.ld; at.ldv = w.ld;
-    at.reqs = w.d_reqs; at.nreq = nrec; at.work = w.d_work; at.nwork = nwork;
+    at.reqs = w.d_reqs; at.nreq = nrec; at.work = w.d_work; at.nwork = nworkg;
+    at.dyn_nwork = H ? H + HDR_NWORK : nullptr;
+    at.dyn_nreq = H ? H + HDR_NREC : nullptr;
 
     auto run_block = [&](const BlockW& b, float* x, int D, int heads) -> int {
       int e;
-      if ((e = ln(x, b.ln1_g, b.ln1_b, w.a, M, D, nullptr, 0))) return e;
+      if ((e = ln(x, b.ln1_g, b.ln1_b, w.a, Mg, D, nullptr, 0, H ? H + HDR_M : nullptr))) return e;
       GemmArgs q = g;
       q.X = w.a; q.K = D; q.N = 3 * D; q.W = b.qkv_w; q.bias = b.qkv_b;
       q.q = w.q; q.k = w.k; q.vt = w.vt; q.heads = heads; q.ldqk = w.ld; q.ldv = w.ld;
@@ -255,7 +246,7 @@ int forward(const ModelW& m, Workspace& w, int nrec, int nall, int composite, hi
       GemmArgs pr = g;
       pr.X = w.o; pr.K = D; pr.N = D; pr.W = b.proj_w; pr.bias = b.proj_b; pr.out = x; pr.ldo = D;
       if ((e = gemm(EPI_RESIDUAL, X_DENSE, pr, Mreal))) return e;
-      if ((e = ln(x, b.ln2_g, b.ln2_b, w.a, M, D, nullptr, 0))) return e;
+      if ((e = ln(x, b.ln2_g, b.ln2_b, w.a, Mg, D, nullptr, 0, H ? H + HDR_M : nullptr))) return e;
       GemmArgs f1 = g;
       f1.X = w.a; f1.K = D; f1.N = 4 * D; f1.W = b.fc1_w; f1.bias = b.fc1_b; f1.out = w.hid; f1.ldo = 4 * D;
       if ((e = gemm(EPI_GELU, X_DENSE, f1, Mreal))) return e;
@@ -266,23 +257,90 @@ int forward(const ModelW& m, Workspace& w, int nrec, int nall, int composite, hi
     for (const BlockW& b : m.enc)
       if ((rc = run_block(b, w.h, m.De, m.He))) return rc;
     // encoder norm, projection to the decoder width + PE
-    if ((rc = ln(w.h, m.enc_g, m.enc_b, w.a, M, m.De, nullptr, 0))) return rc;
+    if ((rc = ln(w.h, m.enc_g, m.enc_b, w.a, Mg, m.De, nullptr, 0, H ? H + HDR_M : nullptr))) return rc;
     GemmArgs e2 = g;
     e2.X = w.a; e2.K = m.De; e2.N = m.Dd; e2.W = m.e2d_w; e2.bias = m.e2d_b; e2.out = w.z; e2.ldo = m.Dd;
     if ((rc = gemm(EPI_PE, X_DENSE, e2, Mreal))) return rc;
     for (const BlockW& b : m.dec)
       if ((rc = run_block(b, w.z, m.Dd, m.Hd))) return rc;
     // decoder norm and head on the target tubelet only, target time slot only
-    if ((rc = ln(w.z, m.dec_g, m.dec_b, w.ahead, Mh, m.Dd, w.d_reqs, nrec))) return rc;
+    if ((rc = ln(w.z, m.dec_g, m.dec_b, w.ahead, Mhg, m.Dd, w.d_reqs, nrec, H ? H + HDR_MH : nullptr))) return rc;
     const int slot = (m.T - 1) * 256 * m.C;
     GemmArgs hd = g;
-    hd.M = Mh; hd.X = w.ahead; hd.K = m.Dd; hd.N = 256 * m.C;
+    hd.M = Mhg; hd.X = w.ahead; hd.K = m.Dd; hd.N = 256 * m.C;
+    hd.dyn_m = H ? H + HDR_MH : nullptr;
     hd.W = (const char*)m.head_w + (size_t)slot * m.Dd * esize(p);
     hd.bias = m.head_b + slot;
     if ((rc = gemm(EPI_HEAD, X_DENSE, hd, Mh_real))) return rc;
   }
   ProfScope ps(w.prof, s, PK_OTHER, 0.0);
-  return launch_composite(w.d_reqs, nall, m.C, max_pix, composite, s);
+  return launch_composite(w.d_reqs, nall, m.C, max_pix, composite, s, H ? H + HDR_NALL : nullptr);
+}
+
+}  // namespace
+
+int forward(const ModelW& m, Workspace& w, int slot, int nrec, int nall, int composite, bool use_graph,
+            hipStream_t s) {
+  if (nall <= 0) return 0;
+  if (nall > w.max_req || nrec > nall || slot < 0 || slot >= WS_SLOTS) return -22;
+  ReqDesc* reqs = w.h_reqs_slot[slot];
+  int* work = w.h_work_slot[slot];
+  int* hdr = w.h_hdr_slot[slot];
+  // token and head-row offsets, attention work list
+  int M = 0, Mh = 0, nwork = 0, max_pix = 0;
+  double Mreal = 0.0, attn_pairs = 0.0;
+  for (int r = 0; r < nall; ++r) {
+    ReqDesc& d = reqs[r];
+    d.gy = cdiv(d.H, REVO_PATCH);
+    d.gx = cdiv(d.W, REVO_PATCH);
+    d.P = d.gy * d.gx;
+    if (d.H * d.W > max_pix) max_pix = d.H * d.W;
+    if (r >= nrec) { d.tok_off = M; d.head_off = Mh; continue; }
+    M = (M + 7) & ~7;  // 16-byte aligned V^T columns for every request
+    d.tok_off = M;
+    d.head_off = Mh;
+    const int N = d.J * d.P;
+    for (int qt = 0; qt * 128 < N; ++qt) {
+      if (nwork >= w.max_work) return -22;
+      work[nwork++] = (r << 16) | qt;
+    }
+    M += N;
+    Mh += d.P;
+    Mreal += N;
+    attn_pairs += (double)N * N;
+  }
+  if (M > w.cap) return -22;
+  hdr[HDR_M] = M; hdr[HDR_MH] = Mh; hdr[HDR_NREC] = nrec; hdr[HDR_NALL] = nall; hdr[HDR_NWORK] = nwork;
+  REVO_HIP_TRY(hipMemcpyAsync(w.d_reqs, reqs, (size_t)nall * sizeof(ReqDesc), hipMemcpyHostToDevice, s));
+  REVO_HIP_TRY(hipMemcpyAsync(w.d_hdr, hdr, HDR_N * 4, hipMemcpyHostToDevice, s));
+  if (nwork > 0) REVO_HIP_TRY(hipMemcpyAsync(w.d_work, work, (size_t)nwork * 4, hipMemcpyHostToDevice, s));
+
+  if (!use_graph || w.prof.on) {
+    return enqueue_net(m, w, M, Mh, nwork, nrec, nall, max_pix, composite, false, Mreal, Mh, attn_pairs, s);
+  }
+  // smallest capacity bucket holding this batch; capture its graph once
+  int b = 0;
+  while (b + 1 < WS_BUCKETS && (w.cap >> (WS_BUCKETS - 1 - b)) < M) ++b;
+  const int capM = w.cap >> (WS_BUCKETS - 1 - b);
+  if (!w.graph[b]) {
+    const int capW = capM / 128 + w.max_req;
+    const int capPix = 4096 * 4096;
+    hipGraph_t g = nullptr;
+    REVO_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    int rc = enqueue_net(m, w, capM, capM, capW < w.max_work ? capW : w.max_work, w.max_req, w.max_req, capPix,
+                         composite, true, 0.0, 0.0, 0.0, s);
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return -5;
+    e = hipGraphInstantiate(&w.graph[b], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) { w.graph[b] = nullptr; return -5; }
+  }
+  REVO_HIP_TRY(hipGraphLaunch(w.graph[b], s));
+  return 0;
 }
 
 }  // namespace revo

@@ -49,6 +49,9 @@ int prof_collect(Prof& p);
 // Activation buffers for one batch of one modality.  Token rows are the
 // batch's requests one after the other, each starting at a multiple of 8; q/k/vt carry ld >= cap + 64 rows so
 // the last key block of any request stays inside the (zeroed) allocation.
+constexpr int WS_SLOTS = 2;    // batches in flight per workspace (host descriptor copies)
+constexpr int WS_BUCKETS = 4;  // graph capacity buckets: cap/8, cap/4, cap/2, cap tokens
+
 struct Workspace {
   int cap = 0, head_cap = 0, ld = 0, max_req = 0, max_work = 0;
   Prec prec = P_BF16;
@@ -57,8 +60,12 @@ struct Workspace {
   float* z = nullptr;
   ReqDesc* d_reqs = nullptr;
   int* d_work = nullptr;
-  ReqDesc* h_reqs = nullptr;  // pinned host mirror
-  int* h_work = nullptr;      // pinned host mirror
+  int* d_hdr = nullptr;                  // live batch shape (BatchHdr)
+  ReqDesc* h_reqs_slot[WS_SLOTS] = {};   // pinned host descriptors, one set per batch in flight
+  int* h_work_slot[WS_SLOTS] = {};
+  int* h_hdr_slot[WS_SLOTS] = {};
+  ReqDesc* h_reqs = nullptr;             // = h_reqs_slot[0] (single-batch callers)
+  hipGraphExec_t graph[WS_BUCKETS] = {};
   size_t bytes = 0;
   Prof prof;
 };
@@ -70,9 +77,13 @@ void workspace_free(Workspace& w);
 // Tokens of one request at frame size H x W.
 int request_tokens(int H, int W, int J);
 
-// Runs the network for w.h_reqs[0 .. nrec) and the composite for
-// w.h_reqs[0 .. nall) (entries nrec.. are clean frames: copy only).  The
-// caller fills frames/mask/outputs/size fields; offsets are set here.
-int forward(const ModelW& m, Workspace& w, int nrec, int nall, int composite, hipStream_t s);
+// Runs the network for w.h_reqs_slot[slot][0 .. nrec) and the composite for
+// entries [0 .. nall) (entries nrec.. are clean frames: copy only).  The
+// caller fills frames/mask/outputs/size fields; offsets are set here.  The
+// slot's host descriptors must not be reused before this batch completes.
+// With use_graph (and profiling off) the launches replay a graph captured
+// once per capacity bucket; the batch shape then comes from device memory.
+int forward(const ModelW& m, Workspace& w, int slot, int nrec, int nall, int composite, bool use_graph,
+            hipStream_t s);
 
 }  // namespace revo
