@@ -90,6 +90,117 @@ def run_form(precision, reqs, blobs, steps, warmup, log, one_stream=False):
                 p50_ms=pct(50), p99_ms=pct(99), stats=st)
 
 
+SERVE_RES = [(480, 640)] * 16 + [(540, 960)] * 16 + [(720, 1280)] * 32   # 1 : 1 : 2
+
+
+def serve_bench(blobs, streams, seconds, warm_seconds, cap_tokens, log, seed=0):
+    """Serving loop: `streams` conference streams with Poisson arrivals at
+    30 fps each, mixed resolutions, per-stream Gilbert-Elliott loss (mean
+    U[0.05, 0.40], bursts of 4 slices, independent RGB and depth chains), a
+    deadline of arrival + 1/30 s, BF16 graph launches, deadline shedding.
+    A frame of a modality with no lost slice is a clean reference update."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2604_27441_amd import Recoverer
+
+    rng = np.random.default_rng(40000 + seed)
+    res = [SERVE_RES[(i * len(SERVE_RES)) // streams] for i in range(streams)]
+    # shared content per resolution: 5 references + 1 target frame pair
+    content = {}
+    for (H, W) in sorted(set(res)):
+        rgb, dep = synth.scene_frames(20000 + H, H, W, list(range(6)))
+        content[(H, W)] = [(torch.from_numpy(rgb[i]).cuda(), torch.from_numpy(dep[i]).cuda()) for i in range(6)]
+    # per-stream loss chains over 15 frames (cycled), uploaded as device masks
+    F = 15
+    masks = []
+    for i in range(streams):
+        H, W = res[i]
+        L = rng.uniform(0.05, 0.40)
+        mr = synth.gilbert_elliott_masks(30000 + 2 * i, H, W, F, L, 4)
+        md = synth.gilbert_elliott_masks(30001 + 2 * i, H, W, F, L, 4)
+        masks.append([(torch.from_numpy(mr[f]).cuda() if mr[f].any() else None,
+                       torch.from_numpy(md[f]).cuda() if md[f].any() else None) for f in range(F)])
+    outs = {r: (torch.empty((r[0], r[1], 3), dtype=torch.uint8, device="cuda"),
+                torch.empty(r, dtype=torch.int16, device="cuda")) for r in set(res)}
+    rec = Recoverer(blobs[0], blobs[1], precision=1, device=0, max_batch_tokens=cap_tokens, max_batch=16,
+                    max_streams=streams, shed=True, graphs=True, fps=30.0)
+    t_ids = []
+    for i in range(streams):
+        H, W = res[i]
+        for f in range(5):
+            t_ids.append(rec.submit(i, f, W, H, rgb=content[(H, W)][f][0], depth=content[(H, W)][f][1],
+                                    device_ptrs=True))
+    rec.wait(t_ids)
+    # Poisson arrival schedule
+    total = warm_seconds + seconds
+    arrivals = []
+    for i in range(streams):
+        t = rng.exponential(1 / 30.0)
+        while t < total:
+            arrivals.append((t, i))
+            t += rng.exponential(1 / 30.0)
+    arrivals.sort()
+    frame_no = [5] * streams
+    info = {}
+    lat, done = [], []
+    t0 = time.perf_counter()
+    t0_ns = time.clock_gettime_ns(time.CLOCK_MONOTONIC)
+    pending = 0
+
+    def drain(timeout_us):
+        nonlocal pending
+        for c in rec.poll(256, timeout_us):
+            pending -= 1
+            done.append((c, info.pop(c.ticket)))
+
+    for (ta, i) in arrivals:
+        while True:
+            now = time.perf_counter() - t0
+            if now >= ta:
+                break
+            drain(int(min(ta - now, 0.002) * 1e6))
+        H, W = res[i]
+        f = frame_no[i]
+        frame_no[i] += 1
+        mr, md = masks[i][f % F]
+        arr_ns = t0_ns + int(ta * 1e9)
+        t = rec.submit(i, f, W, H, rgb=content[(H, W)][5][0], mask_rgb=mr, depth=content[(H, W)][5][1],
+                       mask_depth=md, rgb_out=outs[(H, W)][0], depth_out=outs[(H, W)][1], device_ptrs=True,
+                       deadline_ns=arr_ns + int(1e9 / 30.0))
+        if t is None:  # queue full: the frame is dropped like a shed one
+            continue
+        pending += 1
+        info[t] = (ta, (H, W), mr is not None or md is not None, arr_ns)
+        drain(0)
+    while pending > 0:
+        drain(1_000_000)
+    rec.close()
+    # measured window: arrivals after the warm-up
+    served = [(c, x) for c, x in done if x[0] >= warm_seconds and x[2]]
+    n_rec = len(served)
+    ok = [(c, x) for c, x in served if c.status == 0]
+    shed = sum(1 for c, _ in served if c.status == 1)
+    lat = sorted((c.done_ns - x[3]) * 1e-6 for c, x in ok)
+    pct = lambda v, p: v[min(len(v) - 1, int(round(p / 100 * (len(v) - 1))))] if v else None
+    per_res = {}
+    for r in sorted(set(res)):
+        lr = sorted((c.done_ns - x[3]) * 1e-6 for c, x in ok if x[1] == r)
+        per_res[f"{r[1]}x{r[0]}"] = {"served_per_s": len(lr) / seconds, "p50_ms": pct(lr, 50), "p99_ms": pct(lr, 99)}
+    out = {
+        "streams": streams, "seconds": seconds, "offered_recoveries_per_s": n_rec / seconds,
+        "served_pairs_per_s": len(ok) / seconds, "shed_fraction": shed / max(1, n_rec),
+        "failed": sum(1 for c, _ in served if c.status == 2),
+        "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+        "deadline_met_fraction": (sum(1 for v in lat if v <= 1000 / 30.0) / len(lat)) if lat else None,
+        "per_resolution": per_res, "batch_token_cap": cap_tokens,
+    }
+    log(f"serving {streams} streams: {out['served_pairs_per_s']:.1f} pairs/s served, shed {100 * out['shed_fraction']:.1f} %,"
+        f" p50 {out['p50_ms']} ms, p99 {out['p99_ms']} ms")
+    return out
+
+
 def attention_traffic():
     """HBM bytes per attention launch from the committed counter record, or
     None when the kernel source changed since the counters were taken."""
@@ -155,6 +266,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--one-stream", action="store_true",
                     help="run RGB and depth one after the other on one stream (clean per-kernel times)")
+    ap.add_argument("--serve-seconds", type=float, default=6.0, help="measured serving window (0 = skip)")
+    ap.add_argument("--serve-warmup", type=float, default=2.0)
+    ap.add_argument("--serve-streams", type=int, default=64)
+    ap.add_argument("--serve-cap", type=int, default=21600, help="tokens per batch per modality when serving")
+    ap.add_argument("--serve-sweep", action="store_true", help="serve 4, 8, 16, 32, 64 streams")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -250,6 +366,12 @@ def main():
             "attn_tflops": fst["attn_flop"] / (fst["attn_ms"] * 1e-3) / 1e12 if fst["attn_ms"] > 0 else 0.0,
             "path_frac_of_fp32_peak": flop_pair * fv / 1e12 / FP32_PEAK_TFLOPS,
         }
+    if args.serve_seconds > 0:
+        out["serving"] = serve_bench(blobs, args.serve_streams, args.serve_seconds, args.serve_warmup,
+                                     args.serve_cap, log)
+        if args.serve_sweep:
+            out["serving_sweep"] = [serve_bench(blobs, n, args.serve_seconds, args.serve_warmup, args.serve_cap, log)
+                                    for n in (4, 8, 16, 32)]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(reqs[0], log)
     print(json.dumps(out), flush=True)

@@ -161,9 +161,10 @@ struct revo_ctx {
   bool use_graphs = false;
   hipEvent_t done_ev[WS_SLOTS][2] = {};
   hipStream_t d2h = nullptr;
-  double busy_until_ns = 0.0;
+  double busy_until_ns = 0.0;  // when the GPU is expected to drain what is enqueued (guarded by mu)
+  long long last_done_ns = 0;
   int device_error = 0;
-  double sec_per_unit = 2e-11;  // cost model for shedding (seconds per work unit)
+  double sec_per_unit = 3e-11;  // cost model for shedding: seconds per work unit (guarded by mu)
   std::mutex stats_mu;
   revo_stats stats;
 };
@@ -266,6 +267,7 @@ struct InFlight {
   int rc = 0;
   double units = 0.0;
   long long t_enq = 0;
+  double predicted_done_ns = 0.0;
 };
 
 // Enqueue one batch (descriptors in host slot `slot`) on the modality streams
@@ -316,8 +318,17 @@ void complete_batch(revo_ctx* c, InFlight* f) {
     }
   }
   if (hipStreamSynchronize(c->d2h) != hipSuccess) rc = REVO_EDEVICE;
-  const double dt = (now_ns() - f->t_enq) * 1e-9;
-  if (f->units > 0.0 && rc == 0 && c->inflight_max == 1) c->sec_per_unit = 0.8 * c->sec_per_unit + 0.2 * (dt / f->units);
+  {
+    // GPU span of this batch: from its enqueue or the previous completion,
+    // whichever is later; it refines the cost model and the drain estimate
+    std::lock_guard<std::mutex> lk(c->mu);
+    const long long t_done = now_ns();
+    const double span = (double)(t_done - std::max(f->t_enq, c->last_done_ns)) * 1e-9;
+    if (f->units > 0.0 && rc == 0 && span > 0.0) c->sec_per_unit = 0.7 * c->sec_per_unit + 0.3 * (span / f->units);
+    c->last_done_ns = t_done;
+    if (c->inflight.size() > 1) c->busy_until_ns += (double)t_done - f->predicted_done_ns;
+    else c->busy_until_ns = (double)t_done;
+  }
   if (rc) {
     c->device_error = rc;
     for (Job* j : f->batch)
@@ -376,6 +387,7 @@ void worker_main(revo_ctx* c) {
   for (;;) {
     std::vector<Job*> batch;
     int slot = -1;
+    double batch_units = 0.0, batch_start = 0.0;
     {
       std::unique_lock<std::mutex> lk(c->mu);
       for (;;) {
@@ -393,14 +405,23 @@ void worker_main(revo_ctx* c) {
       }
       slot = c->free_slots.back();
       c->free_slots.pop_back();
-      // take jobs in order while they fit; stop before a clean frame of a
-      // stream that already has a recovery in this batch
+      // Take jobs in submission order (deadlines follow arrival order) while
+      // they fit the token capacity.  Stop before a clean frame of a stream
+      // that already has a recovery in this batch.  With shedding, a job that
+      // cannot finish by its deadline even alone after the queued work is
+      // shed, and the batch closes before a job whose addition would make
+      // the whole batch (which completes at once) miss a member's deadline.
+      const bool shed = (c->cfg.flags & REVO_CFG_SHED) != 0;
+      const double start = std::max((double)now_ns(), c->busy_until_ns);
+      const double spu = 1e9 * c->sec_per_unit;
+      double min_deadline = 1e300;
       int tokens[2] = {0, 0};
       std::vector<unsigned> rec_streams[2];
       while (!c->queue.empty() && (int)batch.size() < max_batch) {
         Job* j = c->queue.front();
         bool fits = true, conflict = false;
         int add[2] = {0, 0};
+        double ju = 0.0;
         for (int q = 0; q < 2; ++q) {
           const Mod& m = j->mod[q];
           if (!m.present) continue;
@@ -409,33 +430,48 @@ void worker_main(revo_ctx* c) {
               if (s == j->stream) conflict = true;
           } else {
             add[q] = (request_tokens(m.H, m.W, c->J) + 7) & ~7;  // rows start 8-aligned
+            ju += work_units(request_tokens(m.H, m.W, c->J));
             if (tokens[q] + add[q] > cap) fits = false;
           }
         }
-        if (!batch.empty() && (conflict || !fits)) break;
+        bool shed_this = false;
+        if (shed && ju > 0.0) {
+          // plan with a safety margin: 2 ms plus 10 % of the estimate
+          auto late = [&](double units, double deadline) {
+            const double est = spu * units;
+            return start + 1.1 * est + 2.0e6 > deadline;
+          };
+          if (late(ju, (double)j->deadline)) shed_this = true;
+          else if (!batch.empty() && late(batch_units + ju, std::min(min_deadline, (double)j->deadline))) break;
+        }
+        if (!batch.empty() && (conflict || (!fits && !shed_this))) break;
         c->queue.pop_front();
-        for (int q = 0; q < 2; ++q) {
-          tokens[q] += add[q];
-          if (j->mod[q].present && !j->mod[q].clean) rec_streams[q].push_back(j->stream);
+        if (shed_this) {
+          j->status = REVO_SHED;
+        } else {
+          for (int q = 0; q < 2; ++q) {
+            tokens[q] += add[q];
+            if (j->mod[q].present && !j->mod[q].clean) rec_streams[q].push_back(j->stream);
+          }
+          if (ju > 0.0) {
+            batch_units += ju;
+            min_deadline = std::min(min_deadline, (double)j->deadline);
+          }
         }
         batch.push_back(j);
       }
+      batch_start = start;
     }
     c->cv_done.notify_all();  // queue space freed
 
-    // shedding, ring updates and reference checks in submission order; the
-    // finish-time estimate starts when the GPU drains what is already queued
+    // ring updates and reference checks in submission order
     const long long t0 = now_ns();
-    const double start = std::max((double)t0, c->busy_until_ns);
+    const double start = batch_start;
     double units = 0.0;
     for (Job* j : batch) {
       double ju = 0.0;
       for (int q = 0; q < 2; ++q)
         if (j->mod[q].present && !j->mod[q].clean) ju += work_units(request_tokens(j->mod[q].H, j->mod[q].W, c->J));
-      if ((c->cfg.flags & REVO_CFG_SHED) && ju > 0.0) {
-        const double finish = start + 1e9 * c->sec_per_unit * (units + ju);
-        if ((double)j->deadline < finish) j->status = REVO_SHED;
-      }
       if (j->status == REVO_DONE) units += ju;
       for (int q = 0; q < 2; ++q) {
         Mod& m = j->mod[q];
@@ -455,7 +491,6 @@ void worker_main(revo_ctx* c) {
         }
       }
     }
-    c->busy_until_ns = start + 1e9 * c->sec_per_unit * units;
     InFlight* f = new InFlight();
     f->batch.swap(batch);
     f->slot = slot;
@@ -464,6 +499,8 @@ void worker_main(revo_ctx* c) {
     f->rc = launch_batch(c, f);
     {
       std::lock_guard<std::mutex> lk(c->mu);
+      c->busy_until_ns = std::max(start, c->busy_until_ns) + 1e9 * c->sec_per_unit * units;
+      f->predicted_done_ns = c->busy_until_ns;
       c->inflight.push_back(f);
     }
     c->cv_inflight.notify_all();
