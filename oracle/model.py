@@ -121,21 +121,83 @@ def bf16_round(x):
     return u.view(np.float32).astype(np.float64)
 
 
+def e4m3_round(x):
+    """Round to the nearest OCP FP8 E4M3 value (bias 7, 3 mantissa bits,
+    subnormal quantum 2^-9), ties to even, saturating at +-448."""
+    x = np.asarray(x, np.float64)
+    with np.errstate(divide="ignore"):
+        e = np.floor(np.log2(np.abs(x)))
+    q = np.exp2(np.maximum(e, -6.0) - 3.0)
+    return np.clip(np.rint(x / q) * q, -448.0, 448.0)
+
+
 class Rounding:
     """Where a reduced-precision GPU form rounds matrix-multiply operands.
 
-    ``Rounding()`` (the default) is exact FP64.  ``Rounding(bf16_round)``
-    rounds every matrix-product operand (pixel inputs, weights, LayerNorm
-    outputs, Q/K/V, attention probabilities, attention output, GELU output)
-    while sums, normalisation statistics, the residual stream and the
-    composite stay in FP64.  It never reorders any computation.
+    Every matrix product names its call site ("emb", "<blk>.qkv",
+    "<blk>.proj", "<blk>.fc1", "<blk>.fc2", "e2d", "head", and "attn" for
+    Q/K/V and the probabilities); ``act`` rounds the activation operand and
+    ``weight`` the weight operand.  ``Rounding()`` (the default) is exact
+    FP64.  ``Rounding(bf16_round)`` rounds every operand the same way while
+    sums, normalisation statistics, the residual stream and the composite
+    stay in FP64.  It never reorders any computation.
     """
 
     def __init__(self, fn=None):
         self.fn = fn
 
-    def __call__(self, x):
+    def act(self, x, site):
         return x if self.fn is None else self.fn(x)
+
+    def weight(self, w, site):
+        return w if self.fn is None else self.fn(w)
+
+
+class FP8Rounding(Rounding):
+    """The FP8 form: the four block products and the encoder-to-decoder
+    projection take E4M3 operands, activations with a per-tensor scale
+    (absmax over a calibration set / 448) and weights with a per-output-row
+    scale (row absmax / 448); the embedding, head and attention stay BF16."""
+
+    FP8_KINDS = ("qkv", "proj", "fc1", "fc2", "e2d")
+
+    def __init__(self, act_scales):
+        super().__init__(bf16_round)
+        self.scales = dict(act_scales)
+
+    @classmethod
+    def is_fp8(cls, site):
+        return site.rsplit(".", 1)[-1] in cls.FP8_KINDS
+
+    def act(self, x, site):
+        if not self.is_fp8(site):
+            return bf16_round(x)
+        s = self.scales[site]
+        return e4m3_round(np.asarray(x) / s) * s
+
+    def weight(self, w, site):
+        if not self.is_fp8(site):
+            return bf16_round(w)
+        sw = np.abs(w).max(axis=1, keepdims=True) / 448.0
+        sw = np.where(sw > 0, sw, 1.0)
+        return e4m3_round(w / sw) * sw
+
+
+class AbsMaxRecorder(Rounding):
+    """Exact arithmetic that records max |activation operand| per call site
+    (the calibration pass of the FP8 form)."""
+
+    def __init__(self):
+        super().__init__(None)
+        self.absmax = {}
+
+    def act(self, x, site):
+        m = float(np.abs(x).max()) if np.size(x) else 0.0
+        self.absmax[site] = max(self.absmax.get(site, 0.0), m)
+        return x
+
+    def scales(self):
+        return {k: (v / 448.0 if v > 0 else 1.0) for k, v in self.absmax.items()}
 
 
 EXACT = Rounding()
@@ -228,9 +290,9 @@ def token_positions(D, taus, gy, gx):
 # --------------------------------------------------------------------------
 # network layers
 # --------------------------------------------------------------------------
-def linear(x, w, b, rnd=EXACT):
+def linear(x, w, b, rnd=EXACT, site=""):
     """x W^T + b with W stored [out][in]."""
-    return rnd(x) @ rnd(w).T + b
+    return rnd.act(x, site) @ rnd.weight(w, site).T + b
 
 
 def layer_norm(x, g, b, eps=1e-6):
@@ -255,7 +317,7 @@ def attention_head(q, k, v, rnd=EXACT, chunk=2048):
         s -= s.max(axis=1, keepdims=True)
         e = np.exp(s)
         denom = e.sum(axis=1, keepdims=True)
-        out[r0:r0 + chunk] = (rnd(e) @ v) / denom
+        out[r0:r0 + chunk] = (rnd.act(e, "attn") @ v) / denom
     return out
 
 
@@ -264,21 +326,21 @@ def self_attention(a, p, pre, heads, rnd=EXACT):
     head-major with contiguous heads), per-head attention, output projection."""
     N, D = a.shape
     dh = D // heads
-    qkv = linear(a, p[pre + "qkv.w"], p[pre + "qkv.b"], rnd)
-    q, k, v = rnd(qkv[:, :D]), rnd(qkv[:, D:2 * D]), rnd(qkv[:, 2 * D:])
+    qkv = linear(a, p[pre + "qkv.w"], p[pre + "qkv.b"], rnd, pre + "qkv")
+    q, k, v = rnd.act(qkv[:, :D], "attn"), rnd.act(qkv[:, D:2 * D], "attn"), rnd.act(qkv[:, 2 * D:], "attn")
     o = np.empty((N, D))
     for h in range(heads):
         sl = slice(h * dh, (h + 1) * dh)
         o[:, sl] = attention_head(q[:, sl], k[:, sl], v[:, sl], rnd)
-    return linear(o, p[pre + "proj.w"], p[pre + "proj.b"], rnd)
+    return linear(o, p[pre + "proj.w"], p[pre + "proj.b"], rnd, pre + "proj")
 
 
 def transformer_block(h, p, pre, heads, rnd=EXACT):
     """Pre-LN block: h + Attn(LN1(h)), then + FC2(GELU(FC1(LN2(.))))."""
     h = h + self_attention(layer_norm(h, p[pre + "ln1.g"], p[pre + "ln1.b"]), p, pre, heads, rnd)
     a = layer_norm(h, p[pre + "ln2.g"], p[pre + "ln2.b"])
-    z = rnd(gelu(linear(a, p[pre + "fc1.w"], p[pre + "fc1.b"], rnd)))
-    return h + linear(z, p[pre + "fc2.w"], p[pre + "fc2.b"], rnd)
+    z = gelu(linear(a, p[pre + "fc1.w"], p[pre + "fc1.b"], rnd, pre + "fc1"))
+    return h + linear(z, p[pre + "fc2.w"], p[pre + "fc2.b"], rnd, pre + "fc2")
 
 
 # --------------------------------------------------------------------------
@@ -305,18 +367,18 @@ def forward(refs, ref_idx, target, t_target, mask, params, arch, rnd=EXACT):
     J = len(slots) // T
     taus = [t_target - times[j * T] for j in range(J)]
     U = tubelet_vectors(seq, T)
-    h = linear(U, params["emb.w"], params["emb.b"], rnd)
+    h = linear(U, params["emb.w"], params["emb.b"], rnd, "emb")
     h = h + token_positions(arch.enc_dim, taus, gy, gx)
     for i in range(arch.enc_depth):
         h = transformer_block(h, params, f"enc{i}.", arch.enc_heads, rnd)
     a = layer_norm(h, params["enc_norm.g"], params["enc_norm.b"])
-    z = linear(a, params["e2d.w"], params["e2d.b"], rnd)
+    z = linear(a, params["e2d.w"], params["e2d.b"], rnd, "e2d")
     z = z + token_positions(arch.dec_dim, taus, gy, gx)
     for i in range(arch.dec_depth):
         z = transformer_block(z, params, f"dec{i}.", arch.dec_heads, rnd)
     P = gy * gx
     zt = layer_norm(z[(J - 1) * P:], params["dec_norm.g"], params["dec_norm.b"])
-    o = linear(zt, params["head.w"], params["head.b"], rnd)   # [P, T*256*C]
+    o = linear(zt, params["head.w"], params["head.b"], rnd, "head")   # [P, T*256*C]
     slot = o.reshape(P, T, PATCH, PATCH, C)[:, T - 1]          # target time slot
     pred = slot.reshape(gy, gx, PATCH, PATCH, C).transpose(0, 2, 1, 3, 4).reshape(Hp, Wp, C)
     return pred[:H, :W, :]

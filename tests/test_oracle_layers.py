@@ -173,3 +173,42 @@ def test_composite_rules():
     assert list(df[0]) == [0.0, 1000.0, 65535.0] and list(di[0]) == [0, 1000, 65535]
     df, di = oracle.composite(dp, recv_d, np.zeros((1, 3), np.uint8), 1)
     assert list(di[0]) == [7, 8, 9] and list(df[0]) == [7.0, 8.0, 9.0]
+
+
+def test_e4m3_round_matches_torch_and_saturates():
+    x = RNG.standard_normal(200000) * np.exp(RNG.uniform(-12, 6, 200000))
+    x = x[np.abs(x) <= 448]
+    ref = torch.tensor(x, dtype=torch.float64).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    assert np.array_equal(oracle.e4m3_round(x), ref)
+    assert list(oracle.e4m3_round(np.array([448.0, 460.0, 1e6, -1e6]))) == [448.0, 448.0, 448.0, -448.0]
+    sub = 2.0 ** -9
+    assert list(oracle.e4m3_round(np.array([sub, sub / 2, 1.5 * sub, 0.0]))) == [sub, 0.0, 2 * sub, 0.0]
+    assert list(oracle.e4m3_round(np.array([1.0625, 1.1875, -2.5]))) == [1.0, 1.25, -2.5]
+
+
+def test_fp8_rounding_scales():
+    w = RNG.standard_normal((7, 33))
+    r = oracle.FP8Rounding({"enc0.qkv": 0.01})
+    wq = r.weight(w, "enc0.qkv")
+    assert np.allclose(np.abs(wq).max(axis=1), np.abs(w).max(axis=1))      # row max maps to 448 exactly
+    assert np.all(np.abs(wq - w) <= np.abs(w).max(axis=1, keepdims=True) / 448 * 16 + 1e-15)
+    x = RNG.standard_normal((5, 33))
+    assert np.array_equal(r.act(x, "enc0.qkv"), oracle.e4m3_round(x / 0.01) * 0.01)
+    assert np.array_equal(r.act(x, "attn"), oracle.bf16_round(x))           # attention stays bf16
+    assert np.array_equal(r.weight(w, "head"), oracle.bf16_round(w))
+
+
+def test_absmax_recorder_sites():
+    import synth
+    req = synth.make_request(5, 6, 32, 48, loss=("stripes", 0.5))
+    blobs = synth.make_weights(2, enc_depth=2, dec_depth=1)
+    rec = oracle.AbsMaxRecorder()
+    oracle.recover(req, blobs, enc_depth=2, dec_depth=1, rnd=rec, modalities=("rgb",))
+    sites = set(rec.absmax)
+    want = {"emb", "e2d", "head", "attn"} | {f"{b}{i}.{k}" for b, n in (("enc", 2), ("dec", 1))
+                                            for i in range(n) for k in ("qkv", "proj", "fc1", "fc2")}
+    assert sites == want
+    assert all(v > 0 for v in rec.absmax.values())
+    exact = oracle.recover(req, blobs, enc_depth=2, dec_depth=1, modalities=("rgb",))
+    again = oracle.recover(req, blobs, enc_depth=2, dec_depth=1, rnd=oracle.AbsMaxRecorder(), modalities=("rgb",))
+    assert np.array_equal(exact["rgb"][0], again["rgb"][0])                 # recording changes nothing
