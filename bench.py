@@ -201,6 +201,97 @@ def serve_bench(blobs, streams, seconds, warm_seconds, cap_tokens, log, seed=0):
     return out
 
 
+def _time_batches(rec, reqs, base_stream, steps, warmup):
+    """Time `steps` submissions of the whole batch `reqs` (device pointers)."""
+    import torch
+    from tests.gpu_util import dev
+    H, W = reqs[0]["height"], reqs[0]["width"]
+    ins = [(dev(r["rgb"]), dev(r["mask_rgb"]), dev(r["depth"]), dev(r["mask_depth"])) for r in reqs]
+    outs = [(torch.empty((H, W, 3), dtype=torch.uint8, device="cuda"),
+             torch.empty((H, W), dtype=torch.int16, device="cuda")) for _ in reqs]
+
+    def step():
+        ts = [rec.submit(base_stream + i, int(r["t_target"]), W, H, rgb=ins[i][0], mask_rgb=ins[i][1],
+                         depth=ins[i][2], mask_depth=ins[i][3], rgb_out=outs[i][0], depth_out=outs[i][1],
+                         device_ptrs=True, hold=i + 1 < len(reqs)) for i, r in enumerate(reqs)]
+        got = rec.wait(ts)
+        assert all(c.status == 0 for c in got.values()), got
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def fp8_bench(blobs, c3, steps, log):
+    """FP8-E4M3 form at 1280x720, batch 8, Gilbert-Elliott loss 30 %:
+    calibration on 32 seeded frames through the ABI, throughput, error
+    against the BF16 form on the same batch, and against the FP64 oracle on
+    the sampled 1280x720 outputs of tests/golden (request 0 of the batch-4
+    workload)."""
+    import numpy as np
+
+    import synth
+    from paper_2604_27441_amd import Recoverer
+    from tests.gpu_util import psnr, push_refs, recover
+
+    t = time.perf_counter()
+    c4 = synth.make_batch("c4")
+    calib = synth.make_calibration_set(720, 1280, 32, 0.3)
+    log(f"fp8 inputs ready ({time.perf_counter() - t:.1f} s)")
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "c3_720p_samples.json")))
+    res = {}
+    outs = {}
+    for prec, name in ((2, "fp8"), (1, "bf16")):
+        rec = Recoverer(blobs[0], blobs[1], precision=prec, device=0, max_batch_tokens=8 * 10800 + 64,
+                        max_batch=8, max_streams=32, profile=(prec == 2))
+        for s, r in enumerate(c4):
+            push_refs(rec, s, r)
+        for s, r in enumerate(c3):
+            push_refs(rec, 8 + s, r)
+        if prec == 2:
+            for sc in range(4):
+                push_refs(rec, 12 + sc, next(x for x in calib if x["scene"] == sc))
+            t = time.perf_counter()
+            rec.calibrate(1)
+            for i in range(0, len(calib), 8):
+                recover(rec, [(12 + x["scene"], x) for x in calib[i:i + 8]])
+            rec.calibrate(0)
+            res["calibration_seconds"] = time.perf_counter() - t
+            rec.stats(reset=True)
+            dt = _time_batches(rec, c4, 0, steps, 1)
+            st = rec.stats()
+            res.update(value=len(c4) * steps / dt, ms_per_step=1e3 * dt / steps, steps=steps,
+                       linear_tflops=st["gemm_flop"] / (st["gemm_ms"] * 1e-3) / 1e12 if st["gemm_ms"] else None,
+                       attn_tflops=st["attn_flop"] / (st["attn_ms"] * 1e-3) / 1e12 if st["attn_ms"] else None)
+        outs[name] = (recover(rec, list(enumerate(c4))), recover(rec, [(8, c3[0])])[0])
+        rec.close()
+    # FP8 against BF16 on the batch of 8
+    a, b = outs["fp8"][0], outs["bf16"][0]
+    er = np.concatenate([(x["rgb_f"].astype(np.float64) - y["rgb_f"]).ravel() for x, y in zip(a, b)])
+    ed = np.concatenate([(x["depth_f"].astype(np.float64) - y["depth_f"]).ravel() for x, y in zip(a, b)])
+    res["vs_bf16"] = {"rgb_psnr_db": float(10 * np.log10(1.0 / max(np.mean(er ** 2), 1e-30))),
+                      "depth_maxabs_mm": float(np.abs(ed).max()),
+                      "depth_rms_mm": float(np.sqrt(np.mean(ed ** 2)))}
+    # FP8 and BF16 against FP64 on the sampled 1280x720 outputs (lost pixels)
+    for name in ("fp8", "bf16"):
+        o = outs[name][1]
+        g = {}
+        for mod, key in (("rgb", "rgb_f"), ("depth", "depth_f")):
+            y, x = np.array(golden[mod]["y"][:1536]), np.array(golden[mod]["x"][:1536])
+            ref = np.array(golden[mod]["oracle"][:1536], np.float64)
+            g[mod] = o[key][y, x].astype(np.float64) - ref
+        res[f"{name}_vs_fp64_samples"] = {"rgb_psnr_db": psnr(g["rgb"], 0.0),
+                                          "rgb_maxabs": float(np.abs(g["rgb"]).max()),
+                                          "depth_rms_mm": float(np.sqrt(np.mean(g["depth"] ** 2))),
+                                          "depth_maxabs_mm": float(np.abs(g["depth"]).max())}
+    log(f"fp8: {res['value']:.1f} pairs/s at batch 8; vs bf16 {res['vs_bf16']}; vs fp64 {res['fp8_vs_fp64_samples']}")
+    return res
+
+
 def attention_traffic():
     """HBM bytes per attention launch from the committed counter record, or
     None when the kernel source changed since the counters were taken."""
@@ -266,6 +357,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--one-stream", action="store_true",
                     help="run RGB and depth one after the other on one stream (clean per-kernel times)")
+    ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 form (batch 8)")
+    ap.add_argument("--fp8-steps", type=int, default=5)
     ap.add_argument("--serve-seconds", type=float, default=6.0, help="measured serving window (0 = skip)")
     ap.add_argument("--serve-warmup", type=float, default=2.0)
     ap.add_argument("--serve-streams", type=int, default=64)
@@ -366,6 +459,8 @@ def main():
             "attn_tflops": fst["attn_flop"] / (fst["attn_ms"] * 1e-3) / 1e12 if fst["attn_ms"] > 0 else 0.0,
             "path_frac_of_fp32_peak": flop_pair * fv / 1e12 / FP32_PEAK_TFLOPS,
         }
+    if not args.no_fp8:
+        out["fp8"] = fp8_bench(blobs, reqs, args.fp8_steps, log)
     if args.serve_seconds > 0:
         out["serving"] = serve_bench(blobs, args.serve_streams, args.serve_seconds, args.serve_warmup,
                                      args.serve_cap, log)

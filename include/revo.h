@@ -51,7 +51,12 @@ enum revo_status {
 
 enum revo_precision {
   REVO_FP32 = 0,  /* FP32 operands, FP32 MFMA */
-  REVO_BF16 = 1   /* BF16 operands, FP32 accumulation, FP32 residual/LN/softmax/composite */
+  REVO_BF16 = 1,  /* BF16 operands, FP32 accumulation, FP32 residual/LN/softmax/composite */
+  REVO_FP8 = 2    /* OCP FP8 E4M3 operands for the block products (qkv, proj, fc1, fc2) and the
+                     encoder-to-decoder projection, with per-output-row weight scales and
+                     per-tensor activation scales from a calibration pass (revo_calibrate);
+                     embedding, attention and head in BF16; FP32 accumulation, residual, LN
+                     statistics and composite.  Until calibrated it computes as REVO_BF16. */
 };
 
 enum revo_completion_status {
@@ -162,6 +167,14 @@ int revo_recover_poll(revo_ctx *ctx, revo_completion *out, int max, int timeout_
 
 /* Drain queued and in-flight work, stop the worker and free everything. */
 void revo_recover_destroy(revo_ctx *ctx);
+
+/* FP8 calibration (REVO_FP8 contexts only; REVO_ENOTSUP otherwise).
+ * phase = 1: wait for queued work, clear the recorded maxima; recoveries
+ * submitted afterwards run in BF16 and raise the per-tensor maximum of every
+ * FP8 product input over their tokens.  phase = 0: wait for queued work, set
+ * each activation scale to maximum / 448 and run later recoveries in FP8.
+ * Both block the caller until the queue and the GPU are drained. */
+int revo_calibrate(revo_ctx *ctx, int phase);
 
 /* Counters of a context.  The *_ms and *_flop fields are filled only with
  * REVO_CFG_PROFILE: GPU time between HIP events recorded on the stream of

@@ -29,6 +29,16 @@ enum revo_op_epilogue {
 int revo_op_linear(int precision, int epilogue, const void *x, const void *w, const float *bias,
                    void *out, int M, int N, int K, void *stream);
 
+/* FP8 linear layer (the FP8 form's block products): x8 [M][K] and w8 [N][K]
+ * are OCP E4M3 bytes, wscale [N] per-row weight scales, xscale a device
+ * pointer to the activation scale; the product is
+ * sum_k x8[m][k] w8[n][k] * wscale[n] * (*xscale) + bias[n], accumulated in
+ * float.  REVO_EPI_STORE writes bfloat16 out [M][N], REVO_EPI_RESIDUAL adds
+ * into float out, REVO_EPI_GELU writes E4M3 bytes of GELU(.) / (*out_scale).
+ * Requires N % 64 == 0 and K % 64 == 0. */
+int revo_op_linear_fp8(int epilogue, const void *x8, const void *w8, const float *wscale, const float *xscale,
+                       const float *bias, void *out, const float *out_scale, int M, int N, int K, void *stream);
+
 /* LayerNorm over rows of D <= 512 floats: y = (x - mean) / sqrt(var + 1e-6)
  * * g + b with the biased variance; y in the operand type. */
 int revo_op_layernorm(int precision, const float *x, const float *g, const float *b, void *y,
@@ -44,8 +54,9 @@ int revo_op_layernorm(int precision, const float *x, const float *g, const float
 int revo_op_attention(int precision, const void *q, const void *k, const void *vt, void *o,
                       int heads, int ntok, int ld, void *stream);
 
-/* Element-wise float -> operand type conversion of n values
- * (round to nearest even for REVO_BF16). */
+/* Element-wise float -> operand type conversion of n values (round to
+ * nearest even for REVO_BF16; REVO_FP8 gives OCP E4M3 bytes, nearest even,
+ * saturating at +-448). */
 int revo_op_convert(int precision, const float *src, void *dst, long long n, void *stream);
 
 #ifdef __cplusplus

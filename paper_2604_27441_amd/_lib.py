@@ -65,8 +65,11 @@ _sigs = {
     "revo_recover_destroy": (None, [C.c_void_p]),
     "revo_strerror": (C.c_char_p, [C.c_int]),
     "revo_get_stats": (C.c_int, [C.c_void_p, C.POINTER(RevoStats), C.c_int]),
+    "revo_calibrate": (C.c_int, [C.c_void_p, C.c_int]),
     "revo_op_linear": (C.c_int, [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_int, C.c_int, C.c_int, C.c_void_p]),
+    "revo_op_linear_fp8": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p]),
     "revo_op_layernorm": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
                                     C.c_void_p]),
     "revo_op_attention": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,

@@ -7,7 +7,7 @@ import numpy as np
 from . import _lib
 from ._lib import lib, check, RevoConfig, RevoRequest, RevoCompletion
 
-REVO_FP32, REVO_BF16 = 0, 1
+REVO_FP32, REVO_BF16, REVO_FP8 = 0, 1, 2
 
 
 @dataclass
@@ -103,6 +103,11 @@ class Recoverer:
                 got[c.ticket] = c
                 want.discard(c.ticket)
         return got
+
+    def calibrate(self, phase):
+        """FP8 calibration: phase 1 starts recording activation maxima, phase 0
+        turns them into scales and switches the FP8 form on (revo_calibrate)."""
+        check(lib.revo_calibrate(self._h, int(phase)), "revo_calibrate")
 
     def stats(self, reset=False):
         """Counters of the context (revo_get_stats) as a dict."""

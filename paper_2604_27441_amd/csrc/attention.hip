@@ -265,7 +265,19 @@ __global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 4 : 2) void attn_
 #undef REVO_ATTN_STORE
 
   const float l_tot = xhalf_sum(l_run);
-  if (q_local < N) {
+  if (q_local < N && a.o_scale) {
+    // FP8 output for an FP8 output projection
+    const float inv = 1.0f / (l_tot * *a.o_scale);
+    uint8_t* op = (uint8_t*)a.o + (size_t)q * (a.heads * 64) + hd * 64;
+#pragma unroll
+    for (int ds = 0; ds < 2; ++ds)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int dim = ds * 32 + g * 8 + half * 4;
+        *reinterpret_cast<uint32_t*>(op + dim) = e4m3x4(oacc[ds][4 * g] * inv, oacc[ds][4 * g + 1] * inv,
+                                                         oacc[ds][4 * g + 2] * inv, oacc[ds][4 * g + 3] * inv);
+      }
+  } else if (q_local < N) {
     const float inv = 1.0f / l_tot;
     T* op = (T*)a.o + (size_t)q * (a.heads * 64) + hd * 64;
 #pragma unroll
@@ -291,8 +303,8 @@ __global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 4 : 2) void attn_
 int launch_attention(Prec prec, const AttnArgs& a, hipStream_t s) {
   if (a.nwork <= 0) return 0;
   dim3 grid(a.nwork * a.heads);
-  if (prec == P_BF16) attn_kernel<OpBF16><<<grid, NT, 0, s>>>(a);
-  else if (prec == P_FP32) attn_kernel<OpF32><<<grid, NT, 0, s>>>(a);
+  if (prec == P_BF16 || prec == P_FP8) attn_kernel<OpBF16><<<grid, NT, 0, s>>>(a);  // FP8 form: BF16 attention
+  else if (prec == P_FP32 && !a.o_scale) attn_kernel<OpF32><<<grid, NT, 0, s>>>(a);
   else return -95;
   return hipGetLastError() == hipSuccess ? 0 : -5;
 }

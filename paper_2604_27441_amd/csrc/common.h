@@ -23,7 +23,7 @@ typedef __attribute__((ext_vector_type(16))) float f32x16;
 namespace revo {
 
 // Operand precisions of the matrix products.
-enum Prec { P_FP32 = 0, P_BF16 = 1, P_FP8 = 2 };
+enum Prec { P_FP32 = 0, P_BF16 = 1, P_FP8 = 2 };  // P_FP8: FP8 block products, BF16 elsewhere
 
 // ----------------------------------------------------------------------------
 // operand element traits: storage type in HBM/LDS, element size and the
@@ -53,6 +53,33 @@ struct OpBF16 {
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
   }
   __device__ static inline T from_float(float x) { return (__bf16)x; }
+};
+
+typedef __attribute__((ext_vector_type(8))) int i32x8;
+
+// OCP FP8 E4M3 (bias 7, max 448): conversions saturate at +-448.
+__device__ inline uint32_t e4m3x4(float a, float b, float c, float d) {
+  a = fminf(fmaxf(a, -448.0f), 448.0f);
+  b = fminf(fmaxf(b, -448.0f), 448.0f);
+  c = fminf(fmaxf(c, -448.0f), 448.0f);
+  d = fminf(fmaxf(d, -448.0f), 448.0f);
+  int v = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+  v = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, v, true);
+  return (uint32_t)v;
+}
+__device__ inline uint8_t e4m3(float a) { return (uint8_t)(e4m3x4(a, 0.0f, 0.0f, 0.0f) & 0xFF); }
+
+// FP8 operands: 32 E4M3 values per lane per MFMA step (two 16-byte reads),
+// unit block scales (E8M0 exponent 127).
+struct OpFP8 {
+  typedef uint8_t T;
+  static constexpr int KPL = 32;
+  static constexpr int BK = 64;   // one MFMA step per stage (decoder products have K = 192)
+  typedef i32x8 frag;
+  __device__ static inline void mma(f32x16& acc, frag a, frag b) {
+    acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, acc, 0, 0, 0, 127, 0, 127);
+  }
+  __device__ static inline T from_float(float x) { return e4m3(x); }
 };
 
 __device__ inline float to_float(float x) { return x; }

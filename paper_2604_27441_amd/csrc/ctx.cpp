@@ -159,6 +159,8 @@ struct revo_ctx {
   bool completer_stop = false;
   int inflight_max = 2;
   bool use_graphs = false;
+  std::atomic<bool> calibrating{false};
+  std::mutex calib_mu;
   hipEvent_t done_ev[WS_SLOTS][2] = {};
   hipStream_t d2h = nullptr;
   double busy_until_ns = 0.0;  // when the GPU is expected to drain what is enqueued (guarded by mu)
@@ -263,6 +265,7 @@ void fill_desc(revo_ctx* c, Job* j, int q, ReqDesc& d) {
 // A batch enqueued on the GPU, waiting for its completion events.
 struct InFlight {
   std::vector<Job*> batch;
+  bool record = false;  // FP8 calibration batch
   int slot = 0;
   int rc = 0;
   double units = 0.0;
@@ -291,7 +294,7 @@ int launch_batch(revo_ctx* c, InFlight* f) {
     const int nrec = n;
     for (auto& e : cln[q]) fill_desc(c, e.first, q, hr[n++]);
     if (n == 0) continue;
-    const int e = forward(c->model[q], w, f->slot, nrec, n, c->cfg.composite, c->use_graphs, c->stream[q]);
+    const int e = forward(c->model[q], w, f->slot, nrec, n, c->cfg.composite, c->use_graphs, c->stream[q], f->record);
     if (e) rc = e;
   }
   for (int q = 0; q < 2; ++q)
@@ -376,6 +379,7 @@ void completer_main(revo_ctx* c) {
       c->free_slots.push_back(f->slot);
     }
     c->cv_work.notify_all();
+    c->cv_done.notify_all();
     delete f;
   }
 }
@@ -493,6 +497,7 @@ void worker_main(revo_ctx* c) {
     }
     InFlight* f = new InFlight();
     f->batch.swap(batch);
+    f->record = c->calibrating.load();
     f->slot = slot;
     f->units = units;
     f->t_enq = t0;
@@ -568,7 +573,7 @@ int revo_recover_create(const revo_config* cfg_in, revo_ctx** out) {
   if (!cfg_in || !out) return REVO_EINVAL;
   *out = nullptr;
   revo_config cfg = *cfg_in;
-  if (cfg.precision != REVO_FP32 && cfg.precision != REVO_BF16) return REVO_ENOTSUP;
+  if (cfg.precision != REVO_FP32 && cfg.precision != REVO_BF16 && cfg.precision != REVO_FP8) return REVO_ENOTSUP;
   if (cfg.k < 1 || cfg.k > 7 || cfg.tubelet < 1 || cfg.tubelet > 4) return REVO_EINVAL;
   const int T = cfg.tubelet;
   const int nframes = (cfg.k + 1 + T - 1) / T * T;
@@ -589,7 +594,7 @@ int revo_recover_create(const revo_config* cfg_in, revo_ctx** out) {
   memset(&c->stats, 0, sizeof(c->stats));
   c->cfg = cfg;
   c->T = T; c->k = cfg.k; c->nframes = nframes; c->J = nframes / T;
-  c->prec = cfg.precision == REVO_BF16 ? P_BF16 : P_FP32;
+  c->prec = cfg.precision == REVO_BF16 ? P_BF16 : cfg.precision == REVO_FP8 ? P_FP8 : P_FP32;
   c->rings[0].resize(cfg.max_streams);
   c->rings[1].resize(cfg.max_streams);
   int rc = 0;
@@ -703,6 +708,34 @@ int revo_recover_poll(revo_ctx* c, revo_completion* out, int max, int timeout_us
     c->done.pop_front();
   }
   return n;
+}
+
+int revo_calibrate(revo_ctx* c, int phase) {
+  if (!c) return REVO_EINVAL;
+  if (c->prec != P_FP8) return REVO_ENOTSUP;
+  if (phase != 0 && phase != 1) return REVO_EINVAL;
+  std::lock_guard<std::mutex> guard(c->calib_mu);
+  (void)hipSetDevice(c->cfg.device);
+  // let every batch formed so far finish (they ran with the previous mode)
+  {
+    std::unique_lock<std::mutex> lk(c->mu);
+    c->cv_done.wait(lk, [&] { return (c->queue.empty() && c->inflight.empty()) || c->stop; });
+    if (c->stop) return REVO_ESHUTDOWN;
+    // the worker holds no batch now: change the mode before it forms the next
+    int rc = 0;
+    for (int q = 0; q < 2 && !rc; ++q) {
+      rc = phase ? model_reset_calibration(c->model[q], c->stream[q])
+                 : model_finish_calibration(c->model[q], c->stream[q]);
+      // graphs captured before hold the previous mode's launches
+      for (auto& g : c->ws[q].graph)
+        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+    }
+    for (int q = 0; q < 2 && !rc; ++q)
+      if (hipStreamSynchronize(c->stream[q]) != hipSuccess) rc = REVO_EDEVICE;
+    if (rc) return rc < 0 ? rc : REVO_EDEVICE;
+    c->calibrating = phase == 1;
+  }
+  return REVO_OK;
 }
 
 int revo_get_stats(revo_ctx* c, revo_stats* out, int reset) {

@@ -100,10 +100,97 @@ __global__ __launch_bounds__(256) void composite_kernel(const ReqDesc* __restric
   }
 }
 
+// LayerNorm as above, stored as FP8 E4M3 of the result / (*out_scale).
+__global__ __launch_bounds__(256) void layernorm_fp8_kernel(const float* __restrict__ x, const float* __restrict__ g,
+                                                            const float* __restrict__ b, uint8_t* __restrict__ y,
+                                                            const float* __restrict__ out_scale, int rows, int D,
+                                                            const int* dyn_rows) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (dyn_rows) rows = *dyn_rows;
+  if (row >= rows) return;
+  const float* xr = x + (size_t)row * D;
+  float v[8];
+  float s = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int c = lane + 64 * i;
+    v[i] = c < D ? xr[c] : 0.0f;
+    s += v[i];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  const float mean = s / (float)D;
+  float q = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int c = lane + 64 * i;
+    const float t = c < D ? v[i] - mean : 0.0f;
+    q += t * t;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o);
+  const float rstd = 1.0f / sqrtf(q / (float)D + 1e-6f);
+  const float inv = 1.0f / *out_scale;
+  uint8_t* yr = y + (size_t)row * D;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int c = lane + 64 * i;
+    if (c < D) yr[c] = e4m3(((v[i] - mean) * rstd * g[c] + b[c]) * inv);
+  }
+}
+
+// One block per row: row absmax, scale = absmax / 448, E4M3 of w / scale.
+__global__ __launch_bounds__(256) void quantize_rows_kernel(const float* __restrict__ w, int cols,
+                                                            uint8_t* __restrict__ w8, float* __restrict__ scale) {
+  __shared__ float red[4];
+  const float* wr = w + (size_t)blockIdx.x * cols;
+  float m = 0.0f;
+  for (int c = threadIdx.x; c < cols; c += 256) m = fmaxf(m, fabsf(wr[c]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  const float sc = m > 0.0f ? m / 448.0f : 1.0f;
+  if (threadIdx.x == 0) scale[blockIdx.x] = sc;
+  const float inv = 1.0f / sc;
+  for (int c = threadIdx.x; c < cols; c += 256) w8[(size_t)blockIdx.x * cols + c] = e4m3(wr[c] * inv);
+}
+
+__global__ __launch_bounds__(256) void absmax_kernel(const __bf16* __restrict__ x, int rows, int D,
+                                                     const ReqDesc* __restrict__ reqs, int nreq,
+                                                     unsigned* __restrict__ slot) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  const ReqDesc& d = reqs[find_req_tok(reqs, nreq, row)];
+  if (row - d.tok_off >= d.J * d.P) return;  // alignment gap
+  const __bf16* xr = x + (size_t)row * D;
+  float m = 0.0f;
+  for (int c = lane; c < D; c += 64) m = fmaxf(m, fabsf((float)xr[c]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if (lane == 0) atomicMax(slot, __float_as_uint(m));  // non-negative floats order as their bits
+}
+
+__global__ void scales_kernel(const unsigned* __restrict__ absmax, float* __restrict__ scale, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    const float m = __uint_as_float(absmax[i]);
+    scale[i] = m > 0.0f ? m / 448.0f : 1.0f;
+  }
+}
+
 template <class T>
 __global__ void convert_kernel(const float* __restrict__ src, T* __restrict__ dst, long long n) {
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   if (i < n) dst[i] = (T)src[i];
+}
+
+__global__ void convert_fp8_kernel(const float* __restrict__ src, uint8_t* __restrict__ dst, long long n) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = e4m3(src[i]);
 }
 
 __global__ void zero_kernel(uint4* __restrict__ p, long long n16) {
@@ -143,7 +230,34 @@ int launch_convert(Prec prec, const float* src, void* dst, long long n, hipStrea
   const unsigned blocks = (unsigned)cdivll(n, 256);
   if (prec == P_BF16) convert_kernel<__bf16><<<blocks, 256, 0, s>>>(src, (__bf16*)dst, n);
   else if (prec == P_FP32) convert_kernel<float><<<blocks, 256, 0, s>>>(src, (float*)dst, n);
+  else if (prec == P_FP8) convert_fp8_kernel<<<blocks, 256, 0, s>>>(src, (uint8_t*)dst, n);
   else return -95;
+  return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+int launch_layernorm_fp8(const float* x, const float* g, const float* b, uint8_t* y, const float* out_scale,
+                         int rows, int D, hipStream_t s, const int* dyn_rows) {
+  if (rows <= 0) return 0;
+  if (D > 512 || !out_scale) return -22;
+  layernorm_fp8_kernel<<<cdiv(rows, 4), 256, 0, s>>>(x, g, b, y, out_scale, rows, D, dyn_rows);
+  return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+int launch_quantize_rows(const float* w, int rows, int cols, uint8_t* w8, float* scale, hipStream_t s) {
+  if (rows <= 0) return 0;
+  quantize_rows_kernel<<<rows, 256, 0, s>>>(w, cols, w8, scale);
+  return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+int launch_absmax(const __bf16* x, int rows, int D, const ReqDesc* reqs, int nreq, unsigned* slot, hipStream_t s) {
+  if (rows <= 0) return 0;
+  absmax_kernel<<<cdiv(rows, 4), 256, 0, s>>>(x, rows, D, reqs, nreq, slot);
+  return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+int launch_scales_from_absmax(const unsigned* absmax, float* scale, int n, hipStream_t s) {
+  if (n <= 0) return 0;
+  scales_kernel<<<cdiv(n, 256), 256, 0, s>>>(absmax, scale, n);
   return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 

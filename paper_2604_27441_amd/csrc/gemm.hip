@@ -8,8 +8,9 @@
 // its B operand, so each lane ends up owning one token and runs of four
 // consecutive output features: epilogue stores are 8/16-byte row segments.
 //
-// Tile: 128 tokens x BN features x one 128-byte K stage per operand row,
-// 4 waves in a 2 x 2 grid, LDS double-buffered (pitch padded to 144 bytes).
+// Tile: 128 tokens x BN features x one K stage (128 bytes per operand row;
+// 64 for FP8), 4 waves in a 2 x 2 grid, LDS double-buffered, row pitch padded
+// by 16 bytes.
 #include "kernels.h"
 
 namespace revo {
@@ -18,19 +19,28 @@ namespace {
 
 constexpr int BM = 128;
 constexpr int NT = 256;
-constexpr int PITCH_B = 144;
 
+// Four consecutive results of one row; inv = 1 / (output scale) for FP8.
 template <class T> struct Vec4;
 template <> struct Vec4<float> {
-  __device__ static void store(float* p, const float v[4]) {
+  __device__ static void store(float* p, const float v[4], float) {
     *reinterpret_cast<f32x4*>(p) = f32x4{v[0], v[1], v[2], v[3]};
   }
 };
 template <> struct Vec4<__bf16> {
-  __device__ static void store(__bf16* p, const float v[4]) {
+  __device__ static void store(__bf16* p, const float v[4], float) {
     *reinterpret_cast<bf16x4*>(p) = bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
   }
 };
+template <> struct Vec4<uint8_t> {
+  __device__ static void store(uint8_t* p, const float v[4], float inv) {
+    *reinterpret_cast<uint32_t*>(p) = e4m3x4(v[0] * inv, v[1] * inv, v[2] * inv, v[3] * inv);
+  }
+};
+template <class T> __device__ inline T out_cast(float v, float inv);
+template <> __device__ inline float out_cast<float>(float v, float) { return v; }
+template <> __device__ inline __bf16 out_cast<__bf16>(float v, float) { return (__bf16)v; }
+template <> __device__ inline uint8_t out_cast<uint8_t>(float v, float inv) { return e4m3(v * inv); }
 
 template <class Op> __device__ inline typename Op::frag frag_of(const uint4& u, int g);
 template <> __device__ inline float frag_of<OpF32>(const uint4& u, int g) {
@@ -39,6 +49,9 @@ template <> __device__ inline float frag_of<OpF32>(const uint4& u, int g) {
 }
 template <> __device__ inline bf16x8 frag_of<OpBF16>(const uint4& u, int) {
   return __builtin_bit_cast(bf16x8, u);
+}
+__device__ inline i32x8 frag_fp8(const uint4& lo, const uint4& hi) {
+  return i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
 }
 
 __device__ inline float gelu_erf(float v) { return 0.5f * v * (1.0f + erff(v * 0.70710678118654752f)); }
@@ -150,16 +163,18 @@ __device__ uint4 gather_chunk(const ReqDesc& d, int j, int y, int x, int k, int 
   return r.u;
 }
 
-template <class Op, int BN, int EPI, int XM>
+template <class Op, int BN, int EPI, int XM, class OutT>
 __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
   typedef typename Op::T T;
   constexpr int BK = Op::BK;
-  constexpr int E = 16 / sizeof(T);
-  constexpr int PITCH = PITCH_B / sizeof(T);
-  constexpr int XC = BM * 8 / NT;
-  constexpr int WC = BN * 8 / NT;
+  constexpr int E = 16 / sizeof(T);               // elements per 16-byte chunk
+  constexpr int CPR = BK * sizeof(T) / 16;        // chunks per stage row
+  constexpr int PITCH = (BK * sizeof(T) + 16) / sizeof(T);  // LDS row pitch, padded by 16 bytes
+  constexpr int XC = BM * CPR / NT;
+  constexpr int WC = BN * CPR / NT;
   constexpr int NSUB = BN / 64;
-  constexpr int G = 16 / (Op::KPL * sizeof(T));
+  constexpr int FB = Op::KPL * sizeof(T);          // operand bytes per lane per MFMA step
+  constexpr int G = FB >= 16 ? 1 : 16 / FB;        // MFMA steps per 16-byte LDS read
   constexpr int STEPS = BK / (2 * Op::KPL);
   __shared__ __attribute__((aligned(16))) T xs[2][BM * PITCH];
   __shared__ __attribute__((aligned(16))) T ws[2][BN * PITCH];
@@ -180,7 +195,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
   if (XM == X_GATHER) {
 #pragma unroll
     for (int i = 0; i < XC; ++i) {
-      const int m = m0 + ((tid + i * NT) >> 3);
+      const int m = m0 + (tid + i * NT) / CPR;
       g_req[i] = -1;
       if (m < Mlive) {
         const int r = find_req_tok(a.reqs, nreq, m);
@@ -197,8 +212,8 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
   int c_row[XC > WC ? XC : WC], c_k[XC > WC ? XC : WC];
 #pragma unroll
   for (int i = 0; i < (XC > WC ? XC : WC); ++i) {
-    c_row[i] = (tid + i * NT) >> 3;
-    c_k[i] = ((tid + i * NT) & 7) * E;
+    c_row[i] = (tid + i * NT) / CPR;
+    c_k[i] = ((tid + i * NT) % CPR) * E;
   }
   uint4 xr[XC], wr[WC];
 #define REVO_GEMM_LOAD(kt_)                                                                                  \
@@ -243,20 +258,41 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
 #pragma unroll
     for (int s = 0; s < STEPS; s += G) {
       const int koff = half * (BK / 2) + s * Op::KPL;
-      uint4 wf[NSUB], xf[2];
+      if constexpr (FB == 32) {
+        uint4 wf[NSUB][2], xf[2][2];
 #pragma unroll
-      for (int ns = 0; ns < NSUB; ++ns)
-        wf[ns] = *reinterpret_cast<const uint4*>(&ws[buf][(wn * (BN / 2) + ns * 32 + l32) * PITCH + koff]);
+        for (int ns = 0; ns < NSUB; ++ns) {
+          const T* p = &ws[buf][(wn * (BN / 2) + ns * 32 + l32) * PITCH + koff];
+          wf[ns][0] = reinterpret_cast<const uint4*>(p)[0];
+          wf[ns][1] = reinterpret_cast<const uint4*>(p)[1];
+        }
 #pragma unroll
-      for (int ms = 0; ms < 2; ++ms)
-        xf[ms] = *reinterpret_cast<const uint4*>(&xs[buf][(wm * 64 + ms * 32 + l32) * PITCH + koff]);
-#pragma unroll
-      for (int g = 0; g < G; ++g)
+        for (int ms = 0; ms < 2; ++ms) {
+          const T* p = &xs[buf][(wm * 64 + ms * 32 + l32) * PITCH + koff];
+          xf[ms][0] = reinterpret_cast<const uint4*>(p)[0];
+          xf[ms][1] = reinterpret_cast<const uint4*>(p)[1];
+        }
 #pragma unroll
         for (int ns = 0; ns < NSUB; ++ns)
 #pragma unroll
           for (int ms = 0; ms < 2; ++ms)
-            Op::mma(acc[ns][ms], frag_of<Op>(wf[ns], g), frag_of<Op>(xf[ms], g));
+            Op::mma(acc[ns][ms], frag_fp8(wf[ns][0], wf[ns][1]), frag_fp8(xf[ms][0], xf[ms][1]));
+      } else {
+        uint4 wf[NSUB], xf[2];
+#pragma unroll
+        for (int ns = 0; ns < NSUB; ++ns)
+          wf[ns] = *reinterpret_cast<const uint4*>(&ws[buf][(wn * (BN / 2) + ns * 32 + l32) * PITCH + koff]);
+#pragma unroll
+        for (int ms = 0; ms < 2; ++ms)
+          xf[ms] = *reinterpret_cast<const uint4*>(&xs[buf][(wm * 64 + ms * 32 + l32) * PITCH + koff]);
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+          for (int ns = 0; ns < NSUB; ++ns)
+#pragma unroll
+            for (int ms = 0; ms < 2; ++ms)
+              Op::mma(acc[ns][ms], frag_of<Op>(wf[ns], g), frag_of<Op>(xf[ms], g));
+      }
     }
     REVO_GEMM_STORE(buf ^ 1);
     __syncthreads();
@@ -265,6 +301,8 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
 #undef REVO_GEMM_STORE
 
   // ---------------------------------------------------------------- epilogue
+  const float xsc = a.xscale ? *a.xscale : 1.0f;
+  const float oinv = a.out_scale ? 1.0f / *a.out_scale : 1.0f;
 #pragma unroll
   for (int ms = 0; ms < 2; ++ms) {
     const int m = m0 + wm * 64 + ms * 32 + l32;
@@ -289,14 +327,19 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
       for (int g = 0; g < 4; ++g) {
         const int n = n0 + wn * (BN / 2) + ns * 32 + g * 8 + half * 4;
         float v[4];
+        if (a.wscale) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = acc[ns][ms][4 * g + e] + a.bias[n + e];
+          for (int e = 0; e < 4; ++e) v[e] = acc[ns][ms][4 * g + e] * (a.wscale[n + e] * xsc) + a.bias[n + e];
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = acc[ns][ms][4 * g + e] + a.bias[n + e];
+        }
         if (EPI == EPI_STORE) {
-          Vec4<T>::store((T*)a.out + (size_t)m * a.ldo + n, v);
+          Vec4<OutT>::store((OutT*)a.out + (size_t)m * a.ldo + n, v, oinv);
         } else if (EPI == EPI_GELU) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) v[e] = gelu_erf(v[e]);
-          Vec4<T>::store((T*)a.out + (size_t)m * a.ldo + n, v);
+          Vec4<OutT>::store((OutT*)a.out + (size_t)m * a.ldo + n, v, oinv);
         } else if (EPI == EPI_RESIDUAL) {
           float* p = (float*)a.out + (size_t)m * a.ldo + n;
           f32x4 old = *reinterpret_cast<f32x4*>(p);
@@ -316,13 +359,13 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
           if (part == 0) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) v[e] *= a.qscale;
-            Vec4<T>::store((T*)a.q + ((size_t)hd * a.ldqk + m) * 64 + dd, v);
+            Vec4<OutT>::store((OutT*)a.q + ((size_t)hd * a.ldqk + m) * 64 + dd, v, 1.0f);
           } else if (part == 1) {
-            Vec4<T>::store((T*)a.k + ((size_t)hd * a.ldqk + m) * 64 + dd, v);
+            Vec4<OutT>::store((OutT*)a.k + ((size_t)hd * a.ldqk + m) * 64 + dd, v, 1.0f);
           } else {
-            T* vt = (T*)a.vt + ((size_t)hd * 64 + dd) * a.ldv + m;
+            OutT* vt = (OutT*)a.vt + ((size_t)hd * 64 + dd) * a.ldv + m;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) vt[(size_t)e * a.ldv] = Op::from_float(v[e]);
+            for (int e = 0; e < 4; ++e) vt[(size_t)e * a.ldv] = out_cast<OutT>(v[e], 1.0f);
           }
         } else if (EPI == EPI_HEAD) {
           const ReqDesc& d = a.reqs[r];
@@ -342,30 +385,44 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
   }
 }
 
-template <class Op, int EPI, int XM>
+template <class Op, int EPI, int XM, class OutT>
 int launch_t(const GemmArgs& a, hipStream_t s) {
   const int gm = cdiv(a.M, BM);
   if (a.N % 128 == 0) {
-    gemm_kernel<Op, 128, EPI, XM><<<dim3(gm, a.N / 128), NT, 0, s>>>(a);
+    gemm_kernel<Op, 128, EPI, XM, OutT><<<dim3(gm, a.N / 128), NT, 0, s>>>(a);
   } else {
-    gemm_kernel<Op, 64, EPI, XM><<<dim3(gm, a.N / 64), NT, 0, s>>>(a);
+    gemm_kernel<Op, 64, EPI, XM, OutT><<<dim3(gm, a.N / 64), NT, 0, s>>>(a);
   }
   return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 
 template <class Op>
 int launch_op(int epi, int xmode, const GemmArgs& a, hipStream_t s) {
+  typedef typename Op::T T;
   if (xmode == X_GATHER) {
     if (epi != EPI_PE) return -22;
-    return launch_t<Op, EPI_PE, X_GATHER>(a, s);
+    return launch_t<Op, EPI_PE, X_GATHER, float>(a, s);
   }
   switch (epi) {
-    case EPI_STORE: return launch_t<Op, EPI_STORE, X_DENSE>(a, s);
-    case EPI_RESIDUAL: return launch_t<Op, EPI_RESIDUAL, X_DENSE>(a, s);
-    case EPI_GELU: return launch_t<Op, EPI_GELU, X_DENSE>(a, s);
-    case EPI_QKV: return launch_t<Op, EPI_QKV, X_DENSE>(a, s);
-    case EPI_PE: return launch_t<Op, EPI_PE, X_DENSE>(a, s);
-    case EPI_HEAD: return launch_t<Op, EPI_HEAD, X_DENSE>(a, s);
+    case EPI_STORE: return launch_t<Op, EPI_STORE, X_DENSE, T>(a, s);
+    case EPI_RESIDUAL: return launch_t<Op, EPI_RESIDUAL, X_DENSE, float>(a, s);
+    case EPI_GELU: return launch_t<Op, EPI_GELU, X_DENSE, T>(a, s);
+    case EPI_QKV: return launch_t<Op, EPI_QKV, X_DENSE, T>(a, s);
+    case EPI_PE: return launch_t<Op, EPI_PE, X_DENSE, float>(a, s);
+    case EPI_HEAD: return launch_t<Op, EPI_HEAD, X_DENSE, float>(a, s);
+  }
+  return -22;
+}
+
+// FP8 operands: Q/K/V and plain stores come out in BF16 (attention runs in
+// BF16), GELU results in FP8 for the next product, residuals and PE in FP32.
+int launch_fp8(int epi, const GemmArgs& a, hipStream_t s) {
+  switch (epi) {
+    case EPI_STORE: return launch_t<OpFP8, EPI_STORE, X_DENSE, __bf16>(a, s);
+    case EPI_RESIDUAL: return launch_t<OpFP8, EPI_RESIDUAL, X_DENSE, float>(a, s);
+    case EPI_GELU: return launch_t<OpFP8, EPI_GELU, X_DENSE, uint8_t>(a, s);
+    case EPI_QKV: return launch_t<OpFP8, EPI_QKV, X_DENSE, __bf16>(a, s);
+    case EPI_PE: return launch_t<OpFP8, EPI_PE, X_DENSE, float>(a, s);
   }
   return -22;
 }
@@ -382,6 +439,11 @@ int launch_gemm(Prec prec, int epi, int xmode, const GemmArgs& a, hipStream_t s)
   if (prec == P_FP32) {
     if (a.K % OpF32::BK != 0) return -22;
     return launch_op<OpF32>(epi, xmode, a, s);
+  }
+  if (prec == P_FP8) {
+    if (a.K % OpFP8::BK != 0 || xmode != X_DENSE || !a.wscale || !a.xscale) return -22;
+    if (epi == EPI_GELU && !a.out_scale) return -22;
+    return launch_fp8(epi, a, s);
   }
   return -95;
 }

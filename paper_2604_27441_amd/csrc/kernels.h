@@ -56,6 +56,9 @@ struct GemmArgs {
   int ldo;
   // EPI_QKV
   void* q; void* k; void* vt; int heads; int ldqk; int ldv; float qscale;
+  // FP8 operands: acc * wscale[n] * (*xscale) + bias[n]; an FP8 result is
+  // stored as value / (*out_scale)
+  const float* wscale; const float* xscale; const float* out_scale;
   // gather / PE / head
   const ReqDesc* reqs; int nreq; int channels;
 };
@@ -71,6 +74,7 @@ struct AttnArgs {
   int nwork;         // sizes the grid; the live count is *dyn_nwork when set
   const int* dyn_nwork;  // nullable
   const int* dyn_nreq;   // nullable
+  const float* o_scale;  // nullable: store o / (*o_scale) as FP8 E4M3
 };
 
 int launch_gemm(Prec prec, int epi, int xmode, const GemmArgs& a, hipStream_t s);
@@ -82,6 +86,17 @@ int launch_layernorm(Prec out_prec, const float* x, const float* g, const float*
                      const int* dyn_rows = nullptr, const int* dyn_nreq = nullptr);
 // Output frames.  Requests with a null mask are clean frames (copied).  With
 // composite == 0 every pixel of a recovered frame takes the prediction.
+// y = LN(x) * g + b stored as FP8 E4M3 of y / (*out_scale) (FP8 form).
+int launch_layernorm_fp8(const float* x, const float* g, const float* b, uint8_t* y, const float* out_scale,
+                         int rows, int D, hipStream_t s, const int* dyn_rows = nullptr);
+// Per-row FP8 quantisation of a float matrix: scale[r] = max|W[r][:]| / 448
+// (1 for an all-zero row), W8[r][c] = E4M3(W[r][c] / scale[r]).
+int launch_quantize_rows(const float* w, int rows, int cols, uint8_t* w8, float* scale, hipStream_t s);
+// Calibration: atomically raise *slot (float bits) to max |x| over the rows
+// of [rows x D] that hold tokens of the batch's requests (alignment gaps skipped).
+int launch_absmax(const __bf16* x, int rows, int D, const ReqDesc* reqs, int nreq, unsigned* slot, hipStream_t s);
+// scale[i] = absmax[i] / 448 (1 where nothing was recorded).
+int launch_scales_from_absmax(const unsigned* absmax, float* scale, int n, hipStream_t s);
 int launch_composite(const ReqDesc* reqs, int nreq, int channels, int max_pixels, int composite, hipStream_t s,
                      const int* dyn_nreq = nullptr);
 int launch_convert(Prec prec, const float* src, void* dst, long long n, hipStream_t s);

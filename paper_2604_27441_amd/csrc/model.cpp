@@ -9,7 +9,9 @@ namespace revo {
 
 namespace {
 
-size_t esize(Prec p) { return p == P_BF16 ? 2 : 4; }  // operand bytes
+// bytes of a BF16-level operand (the FP8 form keeps BF16 copies and buffers)
+size_t esize(Prec p) { return p == P_FP32 ? 4 : 2; }
+Prec base_prec(Prec p) { return p == P_FP32 ? P_FP32 : P_BF16; }
 
 size_t block_count(int D) { return 2 * D + 3 * D * D + 3 * D + D * D + D + 2 * D + 4 * D * D + 4 * D + 4 * D * D + D; }
 
@@ -29,15 +31,34 @@ int model_load(ModelW& m, int C, int T, int ne, int nd, Prec p, const float* hos
   REVO_HIP_TRY(hipMemcpy(m.master, host_blob, m.count * 4, hipMemcpyHostToDevice));
   REVO_HIP_TRY(hipMalloc(&m.ops, m.count * esize(p)));
   m.bytes = m.count * (4 + esize(p));
-  int rc = launch_convert(p, m.master, m.ops, (long long)m.count, s);
+  int rc = launch_convert(base_prec(p), m.master, m.ops, (long long)m.count, s);
   if (rc) return rc;
+  if (p == P_FP8) {
+    REVO_HIP_TRY(hipMalloc(&m.ops8, m.count));
+    REVO_HIP_TRY(hipMalloc(&m.wscale, m.count / 64 * 4));  // >= rows of all matrices (cols >= 192)
+    m.nact = 4 * (ne + nd) + 1;
+    REVO_HIP_TRY(hipMalloc(&m.act_scale, m.nact * 4));
+    REVO_HIP_TRY(hipMalloc(&m.act_absmax, m.nact * 4));
+    m.bytes += m.count + m.count / 64 * 4 + m.nact * 8;
+    if ((rc = model_reset_calibration(m, s))) return rc;
+  }
   REVO_HIP_TRY(hipStreamSynchronize(s));
 
-  size_t pos = 0;
+  size_t pos = 0, srow = 0;
   auto mat = [&](size_t rows, size_t cols) {
     const void* q = (const char*)m.ops + pos * esize(p);
     pos += rows * cols;
     return q;
+  };
+  // FP8 copy of the matrix just taken by mat() with its row scales
+  auto mat8 = [&](size_t rows, size_t cols, const uint8_t** w8, const float** sc) -> int {
+    if (p != P_FP8) return 0;
+    const size_t off = pos - rows * cols;
+    *w8 = m.ops8 + off;
+    *sc = m.wscale + srow;
+    const int e = launch_quantize_rows(m.master + off, (int)rows, (int)cols, m.ops8 + off, m.wscale + srow, s);
+    srow += rows;
+    return e;
   };
   auto vec = [&](size_t len) {
     const float* q = m.master + pos;
@@ -47,11 +68,11 @@ int model_load(ModelW& m, int C, int T, int ne, int nd, Prec p, const float* hos
   auto block = [&](int D) {
     BlockW b;
     b.ln1_g = vec(D); b.ln1_b = vec(D);
-    b.qkv_w = mat(3 * D, D); b.qkv_b = vec(3 * D);
-    b.proj_w = mat(D, D); b.proj_b = vec(D);
+    b.qkv_w = mat(3 * D, D); rc |= mat8(3 * D, D, &b.qkv_w8, &b.qkv_s); b.qkv_b = vec(3 * D);
+    b.proj_w = mat(D, D); rc |= mat8(D, D, &b.proj_w8, &b.proj_s); b.proj_b = vec(D);
     b.ln2_g = vec(D); b.ln2_b = vec(D);
-    b.fc1_w = mat(4 * D, D); b.fc1_b = vec(4 * D);
-    b.fc2_w = mat(D, 4 * D); b.fc2_b = vec(D);
+    b.fc1_w = mat(4 * D, D); rc |= mat8(4 * D, D, &b.fc1_w8, &b.fc1_s); b.fc1_b = vec(4 * D);
+    b.fc2_w = mat(D, 4 * D); rc |= mat8(D, 4 * D, &b.fc2_w8, &b.fc2_s); b.fc2_b = vec(D);
     return b;
   };
   const int L = m.tub_len();
@@ -59,18 +80,39 @@ int model_load(ModelW& m, int C, int T, int ne, int nd, Prec p, const float* hos
   m.enc.clear();
   for (int i = 0; i < ne; ++i) m.enc.push_back(block(m.De));
   m.enc_g = vec(m.De); m.enc_b = vec(m.De);
-  m.e2d_w = mat(m.Dd, m.De); m.e2d_b = vec(m.Dd);
+  m.e2d_w = mat(m.Dd, m.De); rc |= mat8(m.Dd, m.De, &m.e2d_w8, &m.e2d_s); m.e2d_b = vec(m.Dd);
   m.dec.clear();
   for (int i = 0; i < nd; ++i) m.dec.push_back(block(m.Dd));
   m.dec_g = vec(m.Dd); m.dec_b = vec(m.Dd);
   m.head_w = mat(L, m.Dd); m.head_b = vec(L);
+  if (rc) return -5;
+  if (p == P_FP8) REVO_HIP_TRY(hipStreamSynchronize(s));
   return pos == m.count ? 0 : -22;
 }
 
+int model_reset_calibration(ModelW& m, hipStream_t s) {
+  if (m.prec != P_FP8) return -22;
+  int rc = launch_fill_zero(m.act_absmax, m.nact * 4, s);
+  if (rc) return rc;
+  m.calibrated = false;
+  return launch_scales_from_absmax(m.act_absmax, m.act_scale, m.nact, s);
+}
+
+int model_finish_calibration(ModelW& m, hipStream_t s) {
+  if (m.prec != P_FP8) return -22;
+  const int rc = launch_scales_from_absmax(m.act_absmax, m.act_scale, m.nact, s);
+  if (rc) return rc;
+  REVO_HIP_TRY(hipStreamSynchronize(s));
+  m.calibrated = true;
+  return 0;
+}
+
 void model_free(ModelW& m) {
-  if (m.master) (void)hipFree(m.master);
-  if (m.ops) (void)hipFree(m.ops);
-  m.master = nullptr; m.ops = nullptr;
+  void* p[] = {m.master, m.ops, m.ops8, m.wscale, m.act_scale, m.act_absmax};
+  for (void* q : p)
+    if (q) (void)hipFree(q);
+  m.master = nullptr; m.ops = nullptr; m.ops8 = nullptr; m.wscale = nullptr;
+  m.act_scale = nullptr; m.act_absmax = nullptr;
 }
 
 int prof_init(Prof& p, int events) {
@@ -199,18 +241,27 @@ namespace {
 // counts when eager, bucket capacities when captured); with dyn set, the
 // kernels read the live counts from the device batch header.
 int enqueue_net(const ModelW& m, Workspace& w, int Mg, int Mhg, int nworkg, int nrec, int nall, int max_pix,
-                int composite, bool dyn, double Mreal, double Mh_real, double attn_pairs, hipStream_t s) {
-  const Prec p = m.prec;
+                int composite, bool dyn, double Mreal, double Mh_real, double attn_pairs, bool record, hipStream_t s) {
+  const Prec pb = base_prec(m.prec);                       // embedding, attention, head, LN outputs
+  const bool fp8 = m.prec == P_FP8 && m.calibrated && !record;  // FP8 block products
   const int* H = dyn ? w.d_hdr : nullptr;
   ProfScope whole(w.prof, s, PK_FORWARD, 0.0);
-  auto gemm = [&](int epi, int xm, const GemmArgs& ga, double rows) {
+  auto gemm = [&](Prec p, int epi, int xm, const GemmArgs& ga, double rows) {
     ProfScope ps(w.prof, s, PK_GEMM, 2.0 * rows * ga.N * ga.K);
     return launch_gemm(p, epi, xm, ga, s);
   };
   auto ln = [&](const float* x, const float* gg, const float* bb, void* y, int rows, int D, const ReqDesc* rq,
                 int nq, const int* dyn_rows) {
     ProfScope ps(w.prof, s, PK_OTHER, 0.0);
-    return launch_layernorm(p, x, gg, bb, y, rows, D, rq, nq, s, dyn_rows, H ? H + HDR_NREC : nullptr);
+    return launch_layernorm(pb, x, gg, bb, y, rows, D, rq, nq, s, dyn_rows, H ? H + HDR_NREC : nullptr);
+  };
+  auto ln8 = [&](const float* x, const float* gg, const float* bb, int rows, int D, int act) {
+    ProfScope ps(w.prof, s, PK_OTHER, 0.0);
+    return launch_layernorm_fp8(x, gg, bb, (uint8_t*)w.a, m.act_scale + act, rows, D, s, H ? H + HDR_M : nullptr);
+  };
+  // calibration: raise the maxima of a BF16 activation that an FP8 product will take
+  auto probe = [&](const void* x, int D, int act) {
+    return record ? launch_absmax((const __bf16*)x, Mg, D, w.d_reqs, nrec, m.act_absmax + act, s) : 0;
   };
   int rc = 0;
   if (nrec > 0) {
@@ -221,7 +272,7 @@ int enqueue_net(const ModelW& m, Workspace& w, int Mg, int Mhg, int nworkg, int 
     g.dyn_nreq = H ? H + HDR_NREC : nullptr;
     // tubelet embedding (implicit GEMM over the gathered frames) + PE
     g.M = Mg; g.N = m.De; g.K = m.tub_len(); g.W = m.emb_w; g.bias = m.emb_b; g.out = w.h; g.ldo = m.De;
-    if ((rc = gemm(EPI_PE, X_GATHER, g, Mreal))) return rc;
+    if ((rc = gemm(pb, EPI_PE, X_GATHER, g, Mreal))) return rc;
 
     AttnArgs at;
     memset(&at, 0, sizeof(at));
@@ -230,48 +281,68 @@ int enqueue_net(const ModelW& m, Workspace& w, int Mg, int Mhg, int nworkg, int 
     at.dyn_nwork = H ? H + HDR_NWORK : nullptr;
     at.dyn_nreq = H ? H + HDR_NREC : nullptr;
 
-    auto run_block = [&](const BlockW& b, float* x, int D, int heads) -> int {
+    auto run_block = [&](const BlockW& b, float* x, int D, int heads, bool dec, int bi) -> int {
       int e;
-      if ((e = ln(x, b.ln1_g, b.ln1_b, w.a, Mg, D, nullptr, 0, H ? H + HDR_M : nullptr))) return e;
+      const int sq = m.act_slot(dec, bi, ACT_QKV), sp = m.act_slot(dec, bi, ACT_PROJ);
+      const int s1 = m.act_slot(dec, bi, ACT_FC1), s2 = m.act_slot(dec, bi, ACT_FC2);
+      const Prec pg = fp8 ? P_FP8 : pb;
+      if ((e = fp8 ? ln8(x, b.ln1_g, b.ln1_b, Mg, D, sq) : ln(x, b.ln1_g, b.ln1_b, w.a, Mg, D, nullptr, 0, H ? H + HDR_M : nullptr))) return e;
+      if ((e = probe(w.a, D, sq))) return e;
       GemmArgs q = g;
-      q.X = w.a; q.K = D; q.N = 3 * D; q.W = b.qkv_w; q.bias = b.qkv_b;
+      q.X = w.a; q.K = D; q.N = 3 * D; q.W = fp8 ? (const void*)b.qkv_w8 : b.qkv_w; q.bias = b.qkv_b;
       q.q = w.q; q.k = w.k; q.vt = w.vt; q.heads = heads; q.ldqk = w.ld; q.ldv = w.ld;
       q.qscale = 1.4426950408889634f / 8.0f;  // log2(e) / sqrt(64)
-      if ((e = gemm(EPI_QKV, X_DENSE, q, Mreal))) return e;
+      if (fp8) { q.wscale = b.qkv_s; q.xscale = m.act_scale + sq; }
+      if ((e = gemm(pg, EPI_QKV, X_DENSE, q, Mreal))) return e;
       at.heads = heads;
+      at.o_scale = fp8 ? m.act_scale + sp : nullptr;
       {
         ProfScope ps(w.prof, s, PK_ATTN, 4.0 * 64.0 * heads * attn_pairs);
-        if ((e = launch_attention(p, at, s))) return e;
+        if ((e = launch_attention(fp8 ? P_FP8 : pb, at, s))) return e;
       }
+      if ((e = probe(w.o, D, sp))) return e;
       GemmArgs pr = g;
-      pr.X = w.o; pr.K = D; pr.N = D; pr.W = b.proj_w; pr.bias = b.proj_b; pr.out = x; pr.ldo = D;
-      if ((e = gemm(EPI_RESIDUAL, X_DENSE, pr, Mreal))) return e;
-      if ((e = ln(x, b.ln2_g, b.ln2_b, w.a, Mg, D, nullptr, 0, H ? H + HDR_M : nullptr))) return e;
+      pr.X = w.o; pr.K = D; pr.N = D; pr.W = fp8 ? (const void*)b.proj_w8 : b.proj_w; pr.bias = b.proj_b;
+      pr.out = x; pr.ldo = D;
+      if (fp8) { pr.wscale = b.proj_s; pr.xscale = m.act_scale + sp; }
+      if ((e = gemm(pg, EPI_RESIDUAL, X_DENSE, pr, Mreal))) return e;
+      if ((e = fp8 ? ln8(x, b.ln2_g, b.ln2_b, Mg, D, s1) : ln(x, b.ln2_g, b.ln2_b, w.a, Mg, D, nullptr, 0, H ? H + HDR_M : nullptr))) return e;
+      if ((e = probe(w.a, D, s1))) return e;
       GemmArgs f1 = g;
-      f1.X = w.a; f1.K = D; f1.N = 4 * D; f1.W = b.fc1_w; f1.bias = b.fc1_b; f1.out = w.hid; f1.ldo = 4 * D;
-      if ((e = gemm(EPI_GELU, X_DENSE, f1, Mreal))) return e;
+      f1.X = w.a; f1.K = D; f1.N = 4 * D; f1.W = fp8 ? (const void*)b.fc1_w8 : b.fc1_w; f1.bias = b.fc1_b;
+      f1.out = w.hid; f1.ldo = 4 * D;
+      if (fp8) { f1.wscale = b.fc1_s; f1.xscale = m.act_scale + s1; f1.out_scale = m.act_scale + s2; }
+      if ((e = gemm(pg, EPI_GELU, X_DENSE, f1, Mreal))) return e;
+      if ((e = probe(w.hid, 4 * D, s2))) return e;
       GemmArgs f2 = g;
-      f2.X = w.hid; f2.K = 4 * D; f2.N = D; f2.W = b.fc2_w; f2.bias = b.fc2_b; f2.out = x; f2.ldo = D;
-      return gemm(EPI_RESIDUAL, X_DENSE, f2, Mreal);
+      f2.X = w.hid; f2.K = 4 * D; f2.N = D; f2.W = fp8 ? (const void*)b.fc2_w8 : b.fc2_w; f2.bias = b.fc2_b;
+      f2.out = x; f2.ldo = D;
+      if (fp8) { f2.wscale = b.fc2_s; f2.xscale = m.act_scale + s2; }
+      return gemm(pg, EPI_RESIDUAL, X_DENSE, f2, Mreal);
     };
-    for (const BlockW& b : m.enc)
-      if ((rc = run_block(b, w.h, m.De, m.He))) return rc;
+    for (int i = 0; i < m.ne; ++i)
+      if ((rc = run_block(m.enc[i], w.h, m.De, m.He, false, i))) return rc;
     // encoder norm, projection to the decoder width + PE
-    if ((rc = ln(w.h, m.enc_g, m.enc_b, w.a, Mg, m.De, nullptr, 0, H ? H + HDR_M : nullptr))) return rc;
+    const int se = m.act_e2d();
+    if ((rc = fp8 ? ln8(w.h, m.enc_g, m.enc_b, Mg, m.De, se)
+                  : ln(w.h, m.enc_g, m.enc_b, w.a, Mg, m.De, nullptr, 0, H ? H + HDR_M : nullptr))) return rc;
+    if ((rc = probe(w.a, m.De, se))) return rc;
     GemmArgs e2 = g;
-    e2.X = w.a; e2.K = m.De; e2.N = m.Dd; e2.W = m.e2d_w; e2.bias = m.e2d_b; e2.out = w.z; e2.ldo = m.Dd;
-    if ((rc = gemm(EPI_PE, X_DENSE, e2, Mreal))) return rc;
-    for (const BlockW& b : m.dec)
-      if ((rc = run_block(b, w.z, m.Dd, m.Hd))) return rc;
+    e2.X = w.a; e2.K = m.De; e2.N = m.Dd; e2.W = fp8 ? (const void*)m.e2d_w8 : m.e2d_w; e2.bias = m.e2d_b;
+    e2.out = w.z; e2.ldo = m.Dd;
+    if (fp8) { e2.wscale = m.e2d_s; e2.xscale = m.act_scale + se; }
+    if ((rc = gemm(fp8 ? P_FP8 : pb, EPI_PE, X_DENSE, e2, Mreal))) return rc;
+    for (int i = 0; i < m.nd; ++i)
+      if ((rc = run_block(m.dec[i], w.z, m.Dd, m.Hd, true, i))) return rc;
     // decoder norm and head on the target tubelet only, target time slot only
     if ((rc = ln(w.z, m.dec_g, m.dec_b, w.ahead, Mhg, m.Dd, w.d_reqs, nrec, H ? H + HDR_MH : nullptr))) return rc;
     const int slot = (m.T - 1) * 256 * m.C;
     GemmArgs hd = g;
     hd.M = Mhg; hd.X = w.ahead; hd.K = m.Dd; hd.N = 256 * m.C;
     hd.dyn_m = H ? H + HDR_MH : nullptr;
-    hd.W = (const char*)m.head_w + (size_t)slot * m.Dd * esize(p);
+    hd.W = (const char*)m.head_w + (size_t)slot * m.Dd * esize(m.prec);
     hd.bias = m.head_b + slot;
-    if ((rc = gemm(EPI_HEAD, X_DENSE, hd, Mh_real))) return rc;
+    if ((rc = gemm(pb, EPI_HEAD, X_DENSE, hd, Mh_real))) return rc;
   }
   ProfScope ps(w.prof, s, PK_OTHER, 0.0);
   return launch_composite(w.d_reqs, nall, m.C, max_pix, composite, s, H ? H + HDR_NALL : nullptr);
@@ -280,7 +351,7 @@ int enqueue_net(const ModelW& m, Workspace& w, int Mg, int Mhg, int nworkg, int 
 }  // namespace
 
 int forward(const ModelW& m, Workspace& w, int slot, int nrec, int nall, int composite, bool use_graph,
-            hipStream_t s) {
+            hipStream_t s, bool record) {
   if (nall <= 0) return 0;
   if (nall > w.max_req || nrec > nall || slot < 0 || slot >= WS_SLOTS) return -22;
   ReqDesc* reqs = w.h_reqs_slot[slot];
@@ -315,8 +386,8 @@ int forward(const ModelW& m, Workspace& w, int slot, int nrec, int nall, int com
   REVO_HIP_TRY(hipMemcpyAsync(w.d_hdr, hdr, HDR_N * 4, hipMemcpyHostToDevice, s));
   if (nwork > 0) REVO_HIP_TRY(hipMemcpyAsync(w.d_work, work, (size_t)nwork * 4, hipMemcpyHostToDevice, s));
 
-  if (!use_graph || w.prof.on) {
-    return enqueue_net(m, w, M, Mh, nwork, nrec, nall, max_pix, composite, false, Mreal, Mh, attn_pairs, s);
+  if (!use_graph || w.prof.on || record) {
+    return enqueue_net(m, w, M, Mh, nwork, nrec, nall, max_pix, composite, false, Mreal, Mh, attn_pairs, record, s);
   }
   // smallest capacity bucket holding this batch; capture its graph once
   int b = 0;
@@ -328,7 +399,7 @@ int forward(const ModelW& m, Workspace& w, int slot, int nrec, int nall, int com
     hipGraph_t g = nullptr;
     REVO_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
     int rc = enqueue_net(m, w, capM, capM, capW < w.max_work ? capW : w.max_work, w.max_req, w.max_req, capPix,
-                         composite, true, 0.0, 0.0, 0.0, s);
+                         composite, true, 0.0, 0.0, 0.0, false, s);
     hipError_t e = hipStreamEndCapture(s, &g);
     if (rc) {
       if (g) (void)hipGraphDestroy(g);

@@ -9,7 +9,14 @@ namespace revo {
 struct BlockW {
   const float *ln1_g, *ln1_b, *qkv_b, *proj_b, *ln2_g, *ln2_b, *fc1_b, *fc2_b;
   const void *qkv_w, *proj_w, *fc1_w, *fc2_w;
+  // FP8 form: E4M3 weights and their per-output-row scales
+  const uint8_t *qkv_w8 = nullptr, *proj_w8 = nullptr, *fc1_w8 = nullptr, *fc2_w8 = nullptr;
+  const float *qkv_s = nullptr, *proj_s = nullptr, *fc1_s = nullptr, *fc2_s = nullptr;
 };
+
+// Activation-scale slots of the FP8 form: 4 per block (inputs of qkv, proj,
+// fc1, fc2; encoder blocks first) and one for the encoder-to-decoder input.
+enum { ACT_QKV = 0, ACT_PROJ = 1, ACT_FC1 = 2, ACT_FC2 = 3 };
 
 struct ModelW {
   int C = 3, T = 2, De = 384, Dd = 192, He = 6, Hd = 3, ne = 12, nd = 4;
@@ -22,7 +29,18 @@ struct ModelW {
   const float *enc_g = nullptr, *enc_b = nullptr, *dec_g = nullptr, *dec_b = nullptr;
   std::vector<BlockW> enc, dec;
   size_t bytes = 0;
+  // FP8 form
+  uint8_t* ops8 = nullptr;        // E4M3 copy of the quantised matrices (blob offsets)
+  float* wscale = nullptr;        // per-row weight scales
+  const uint8_t* e2d_w8 = nullptr;
+  const float* e2d_s = nullptr;
+  float* act_scale = nullptr;     // [nact] per-tensor activation scales (device)
+  unsigned* act_absmax = nullptr; // [nact] calibration maxima (float bits, device)
+  int nact = 0;
+  bool calibrated = false;
   int tub_len() const { return T * REVO_PATCH * REVO_PATCH * C; }
+  int act_slot(bool dec, int block, int kind) const { return 4 * ((dec ? ne : 0) + block) + kind; }
+  int act_e2d() const { return 4 * (ne + nd); }
 };
 
 size_t weight_count(int C, int T, int ne, int nd);
@@ -83,7 +101,12 @@ int request_tokens(int H, int W, int J);
 // slot's host descriptors must not be reused before this batch completes.
 // With use_graph (and profiling off) the launches replay a graph captured
 // once per capacity bucket; the batch shape then comes from device memory.
+// record: run the BF16 network and raise the activation maxima of the FP8
+// form's product inputs (calibration); never replayed from a graph.
 int forward(const ModelW& m, Workspace& w, int slot, int nrec, int nall, int composite, bool use_graph,
-            hipStream_t s);
+            hipStream_t s, bool record = false);
+// Turn the recorded maxima into activation scales and switch the FP8 form on.
+int model_finish_calibration(ModelW& m, hipStream_t s);
+int model_reset_calibration(ModelW& m, hipStream_t s);
 
 }  // namespace revo

@@ -18,6 +18,15 @@ bool prec_of(int precision, Prec* p) {
   return false;
 }
 
+int epi_of(int epilogue) {
+  switch (epilogue) {
+    case REVO_EPI_STORE: return EPI_STORE;
+    case REVO_EPI_RESIDUAL: return EPI_RESIDUAL;
+    case REVO_EPI_GELU: return EPI_GELU;
+  }
+  return -1;
+}
+
 }  // namespace
 
 extern "C" {
@@ -39,6 +48,18 @@ int revo_op_linear(int precision, int epilogue, const void* x, const void* w, co
   memset(&a, 0, sizeof(a));
   a.M = M; a.N = N; a.K = K; a.X = x; a.W = w; a.bias = bias; a.out = out; a.ldo = N;
   return launch_gemm(p, epi, X_DENSE, a, (hipStream_t)stream);
+}
+
+int revo_op_linear_fp8(int epilogue, const void* x8, const void* w8, const float* wscale, const float* xscale,
+                       const float* bias, void* out, const float* out_scale, int M, int N, int K, void* stream) {
+  const int epi = epi_of(epilogue);
+  if (epi < 0 || M < 0 || N <= 0 || K <= 0 || !x8 || !w8 || !wscale || !xscale || !bias || !out) return REVO_EINVAL;
+  if (N % 64 || K % 64 || (epi == EPI_GELU && !out_scale)) return REVO_EINVAL;
+  GemmArgs a;
+  memset(&a, 0, sizeof(a));
+  a.M = M; a.N = N; a.K = K; a.X = x8; a.W = w8; a.bias = bias; a.out = out; a.ldo = N;
+  a.wscale = wscale; a.xscale = xscale; a.out_scale = out_scale;
+  return launch_gemm(P_FP8, epi, X_DENSE, a, (hipStream_t)stream);
 }
 
 int revo_op_layernorm(int precision, const float* x, const float* g, const float* b, void* y, int rows, int D,
@@ -88,7 +109,8 @@ int revo_op_attention(int precision, const void* q, const void* k, const void* v
 
 int revo_op_convert(int precision, const float* src, void* dst, long long n, void* stream) {
   Prec p;
-  if (!prec_of(precision, &p)) return REVO_ENOTSUP;
+  if (precision == REVO_FP8) p = P_FP8;
+  else if (!prec_of(precision, &p)) return REVO_ENOTSUP;
   if (n < 0 || !src || !dst) return REVO_EINVAL;
   return launch_convert(p, src, dst, n, (hipStream_t)stream);
 }

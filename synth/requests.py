@@ -71,3 +71,32 @@ def make_batch(config, n=None):
     else:
         raise ValueError(config)
     return reqs if n is None else reqs[:n]
+
+
+def make_calibration_set(height, width, n=32, mean_loss=0.3, scenes=4, k=5, burst=4):
+    """n corrupted frames for FP8 calibration: `scenes` seeded scenes (seeds
+    10000, 10001, ...), each with k clean references and n / scenes
+    consecutive corrupted targets that reuse those references (as the frames
+    of a GoP after a loss do), Gilbert-Elliott loss continuing across them."""
+    H, W = int(height), int(width)
+    per = -(-n // scenes)
+    out = []
+    for sc in range(scenes):
+        ref_idx = np.arange(4, 4 + k, dtype=np.int64)
+        targets = list(range(4 + k, 4 + k + per))
+        rgb, depth = scene_frames(10000 + sc, H, W, list(ref_idx) + targets)
+        mr = gilbert_elliott_masks(10100 + sc, H, W, per, mean_loss, burst)
+        md = gilbert_elliott_masks(10200 + sc, H, W, per, mean_loss, burst)
+        junk = np.random.default_rng(10300 + sc)
+        for i, t in enumerate(targets):
+            if len(out) == n:
+                break
+            rt, dt = rgb[k + i].copy(), depth[k + i].copy()
+            lr, ld = mr[i] != 0, md[i] != 0
+            rt[lr] = junk.integers(0, 256, size=(int(lr.sum()), 3), dtype=np.uint8)
+            dt[ld] = junk.integers(0, 65536, size=int(ld.sum()), dtype=np.uint16)
+            out.append(dict(height=H, width=W, ref_idx=ref_idx, t_target=t, scene=sc,
+                            rgb_refs=np.ascontiguousarray(rgb[:k]), depth_refs=np.ascontiguousarray(depth[:k]),
+                            rgb=rt, depth=dt, mask_rgb=mr[i], mask_depth=md[i],
+                            rgb_clean=rgb[k + i], depth_clean=depth[k + i]))
+    return out

@@ -116,6 +116,7 @@ def scene_frames(seed, height, width, frame_indices):
     side_u = 400.0 * np.minimum(1.0 / np.maximum(-dx, 1e-3), 50.0)
     plane_tu = np.choose(plane_id, [uu, uu, vv])
     plane_tv = np.choose(plane_id, [vv, floor_v, side_u])
+    plane_noise = None
     for fi, t in enumerate(frame_indices):
         z = plane_best.copy()
         obj = plane_id.copy()
@@ -138,7 +139,14 @@ def scene_frames(seed, height, width, frame_indices):
             tu = np.where(closer, uu - su, tu)
             tv = np.where(closer, vv - sv, tv)
         base = p["colors"][obj]
-        noise = _texture(tu, tv, p["tex_seed"])
+        # the planes are static: their texture is computed once per call and
+        # only sphere pixels are textured per frame (same values either way)
+        if plane_noise is None:
+            plane_noise = _texture(plane_tu, plane_tv, p["tex_seed"])
+        noise = plane_noise.copy()
+        on_sphere = obj >= 3
+        if on_sphere.any():
+            noise[on_sphere] = _texture(tu[on_sphere], tv[on_sphere], p["tex_seed"])
         col = np.clip(base + noise[..., None], 0.0, 1.0)
         rgb[fi] = np.rint(col * 255.0).astype(np.uint8)
         depth[fi] = np.rint(np.clip(z, 500.0, 3000.0)).astype(np.uint16)

@@ -135,3 +135,70 @@ def test_convert_bf16_rounding():
     assert _lib().revo_op_convert(BF16, xd.data_ptr(), y.data_ptr(), x.size, None) == 0
     torch.cuda.synchronize()
     assert np.array_equal(y.double().cpu().numpy(), oracle.bf16_round(x))
+
+
+FP8 = 2
+
+
+def _fp8_bytes(v):
+    """E4M3 bytes of values that are already E4M3 numbers (exact in torch)."""
+    return torch.tensor(v, dtype=torch.float32).to(torch.float8_e4m3fn).view(torch.uint8)
+
+
+def test_convert_fp8_rounding():
+    x = (RNG.standard_normal(100003) * np.exp(RNG.uniform(-14, 8, 100003))).astype(np.float32)
+    x[:4] = [448.0, 460.0, 1e6, -3e4]
+    xd = torch.tensor(x).cuda()
+    y = torch.zeros(x.size, dtype=torch.uint8).cuda()
+    assert _lib().revo_op_convert(FP8, xd.data_ptr(), y.data_ptr(), x.size, None) == 0
+    torch.cuda.synchronize()
+    got = y.cpu().view(torch.float8_e4m3fn).to(torch.float64).numpy()
+    assert np.array_equal(got, oracle.e4m3_round(x))
+
+
+@pytest.mark.parametrize("M,N,K", [(1, 64, 64), (300, 576, 192), (1000, 1152, 384), (257, 384, 1536)])
+@pytest.mark.parametrize("epi", [0, 1, 2])
+def test_linear_fp8(M, N, K, epi):
+    x = RNG.standard_normal((M, K)) * 3
+    w = RNG.standard_normal((N, K)) * math.sqrt(2.0 / K)
+    b = 0.1 * RNG.standard_normal(N)
+    rnd = oracle.FP8Rounding({"l.qkv": float(np.abs(x).max() / 448)})
+    xs = rnd.scales["l.qkv"]
+    xq = rnd.act(x, "l.qkv")                       # dequantised operands the kernel sees
+    wq = rnd.weight(w, "l.qkv")
+    ws = np.abs(w).max(axis=1) / 448.0
+    x8 = _fp8_bytes(xq / xs).cuda()
+    w8 = _fp8_bytes(wq / ws[:, None]).cuda()
+    wsd = torch.tensor(ws, dtype=torch.float32).cuda()
+    xsd = torch.tensor([xs], dtype=torch.float32).cuda()
+    bd = torch.tensor(b, dtype=torch.float32).cuda()
+    ref = xq @ wq.T + bd.double().cpu().numpy()
+    # the kernel's scales are float32 copies of the oracle's
+    ref_scale_err = 2 * 2.0 ** -24 * np.abs(xq).sum(1, keepdims=True) @ np.abs(wq).max(1, keepdims=True).T
+    osd = torch.tensor([0.05], dtype=torch.float32).cuda()
+    if epi == 1:
+        res = RNG.standard_normal((M, N)).astype(np.float32)
+        out = torch.tensor(res).cuda()
+        ref = ref + res
+    elif epi == 0:
+        out = torch.zeros((M, N), dtype=torch.bfloat16).cuda()
+    else:
+        out = torch.zeros((M, N), dtype=torch.uint8).cuda()
+    rc = _lib().revo_op_linear_fp8(epi, x8.data_ptr(), w8.data_ptr(), wsd.data_ptr(), xsd.data_ptr(), bd.data_ptr(),
+                                   out.data_ptr(), osd.data_ptr(), M, N, K, None)
+    assert rc == 0
+    torch.cuda.synchronize()
+    if epi == 2:
+        got = out.cpu().view(torch.float8_e4m3fn).to(torch.float64).numpy() * 0.05
+        want = oracle.e4m3_round(oracle.gelu(ref) / 0.05) * 0.05
+        # one E4M3 step where float32 accumulation sits on a rounding boundary
+        step = np.exp2(np.floor(np.log2(np.maximum(np.abs(want), 1e-30))) - 3) * 0.05 + 2.0 ** -9 * 0.05
+        assert np.all(np.abs(got - want) <= step + 1e-12)
+        assert np.mean(got == want) > 0.98
+        return
+    got = out.double().cpu().numpy()
+    scale = np.abs(ref).max() + 1e-30
+    tol = 2e-6 * math.sqrt(K) * scale + ref_scale_err
+    if epi == 0:
+        tol = tol + 4e-3 * np.abs(ref)
+    assert np.all(np.abs(got - ref) <= tol + 1e-7), float(np.abs(got - ref).max())

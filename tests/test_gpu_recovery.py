@@ -232,3 +232,41 @@ def test_many_batches_in_flight():
         for s, o, od in outs:
             assert np.array_equal(o.cpu().numpy(), alone[s]["rgb"])
             assert np.array_equal(od.cpu().numpy().view(np.uint16), alone[s]["depth"])
+
+
+def test_fp8_form_against_rounding_oracle():
+    """FP8 form: after a calibration pass over seeded frames (run by the
+    library and, independently, by the oracle on the same frames), the GPU's
+    error against FP64 stays within the FP8-rounding oracle's error budget
+    (twice its MSE, four times its max error); received pixels stay exact."""
+    FP8 = 2
+    blobs = synth.make_weights(3, perturb_seed=4, **SMALL)
+    target = synth.make_request(111, 112, 96, 128, loss=("stripes", 0.5))
+    calib = [synth.make_request(10000 + i, 10100 + i, 96, 128, loss=("ge", 0.3)) for i in range(4)]
+    scales = {}
+    for mod in ("rgb", "depth"):
+        rec = oracle.AbsMaxRecorder()
+        for r in calib:
+            oracle.recover(r, blobs, rnd=rec, modalities=(mod,), **SMALL)
+        scales[mod] = rec.scales()
+    exact = oracle.recover(target, blobs, **SMALL)
+    emu = {}
+    for mod in ("rgb", "depth"):
+        emu.update(oracle.recover(target, blobs, rnd=oracle.FP8Rounding(scales[mod]), modalities=(mod,), **SMALL))
+    with _rec(blobs, FP8, **SMALL) as rec:
+        for s, r in enumerate(calib):
+            push_refs(rec, s, r)
+        push_refs(rec, 9, target)
+        before = recover(rec, [(9, target)])[0]          # uncalibrated: computes as BF16
+        rec.calibrate(1)
+        recover(rec, list(enumerate(calib)))
+        rec.calibrate(0)
+        out = recover(rec, [(9, target)])[0]
+    check_received_and_codes(target, out)
+    assert not np.array_equal(out["rgb_f"], before["rgb_f"])
+    e = compare(target, out, exact)
+    b = compare(target, {"rgb_f": emu["rgb"][1], "depth_f": emu["depth"][1]}, exact)
+    print("fp8", e, "budget", b)
+    assert e["rgb_psnr"] >= b["rgb_psnr"] - 3.02, (e, b)
+    assert e["depth_rms_lost"] <= np.sqrt(2.0) * b["depth_rms_lost"], (e, b)
+    assert e["depth_maxabs"] <= 4.0 * b["depth_maxabs"], (e, b)
