@@ -195,7 +195,7 @@ def test_linear_fp8(M, N, K, epi):
         # lands on the other side of a rounding midpoint than float64
         step = np.exp2(np.maximum(np.floor(np.log2(np.maximum(np.abs(want) / 0.05, 1e-30))), -6) - 3) * 0.05
         assert np.all(np.abs(got - want) <= step + 1e-12)
-        assert np.mean(got == want) > 0.99
+        assert np.sum(got != want) <= max(2, 0.01 * got.size)   # rounding-midpoint ties only
         return
     got = out.double().cpu().numpy()
     scale = np.abs(ref).max() + 1e-30
