@@ -292,6 +292,38 @@ def fp8_bench(blobs, c3, steps, log):
     return res
 
 
+def sweep_kt(log, reps=5):
+    """Per-frame recovery latency at 1280x720 (one RGB-D pair, BF16) over
+    k in 1..7 clean references and tubelet T in {1, 2, 3}: the shape of the
+    paper's latency-versus-k and k x T ablations (App. B.3), here with
+    seeded weights.  Combinations needing more than 8 input frames are
+    skipped."""
+    import synth
+    from paper_2604_27441_amd import Recoverer
+    from tests.gpu_util import push_refs, recover
+    rows = []
+    for T in (1, 2, 3):
+        blobs = synth.make_weights(0, tubelet=T)
+        for k in range(1, 8):
+            nframes = -(-(k + 1) // T) * T
+            if nframes > 8:
+                continue
+            req = synth.make_request(1003, 2003, 720, 1280, k=k, loss=("ge", 0.2))
+            rec = Recoverer(blobs[0], blobs[1], precision=1, device=0, k=k, tubelet=T,
+                            max_batch_tokens=(nframes // T) * 3600 + 64, max_batch=1)
+            push_refs(rec, 0, req)
+            recover(rec, [(0, req)])
+            lat = []
+            for _ in range(reps):
+                c = recover(rec, [(0, req)])[0]["completion"]
+                lat.append((c.done_ns - c.submit_ns) * 1e-6)
+            rec.close()
+            lat.sort()
+            rows.append({"k": k, "T": T, "tokens": (nframes // T) * 3600, "median_ms": lat[len(lat) // 2]})
+            log(f"k={k} T={T}: {rows[-1]['median_ms']:.2f} ms per RGB-D pair")
+    return rows
+
+
 def attention_traffic():
     """HBM bytes per attention launch from the committed counter record, or
     None when the kernel source changed since the counters were taken."""
@@ -357,6 +389,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--one-stream", action="store_true",
                     help="run RGB and depth one after the other on one stream (clean per-kernel times)")
+    ap.add_argument("--sweep-kt", action="store_true", help="latency over k = 1..7 and T = 1..3 (1280x720)")
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 form (batch 8)")
     ap.add_argument("--fp8-steps", type=int, default=5)
     ap.add_argument("--serve-seconds", type=float, default=6.0, help="measured serving window (0 = skip)")
@@ -461,6 +494,8 @@ def main():
         }
     if not args.no_fp8:
         out["fp8"] = fp8_bench(blobs, reqs, args.fp8_steps, log)
+    if args.sweep_kt:
+        out["k_t_sweep"] = sweep_kt(log)
     if args.serve_seconds > 0:
         out["serving"] = serve_bench(blobs, args.serve_streams, args.serve_seconds, args.serve_warmup,
                                      args.serve_cap, log)
