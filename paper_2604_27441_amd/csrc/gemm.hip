@@ -181,11 +181,20 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
-  const int m0 = blockIdx.x * BM;
+  // Workgroups go round-robin to the 8 XCDs, each with its own L2.  Give
+  // XCD x a contiguous range of tiles, ordered with the N tile fastest, so
+  // the N tiles that reuse one block of activation rows run together on one
+  // XCD and read those rows from its L2 instead of HBM.
+  const int gn = a.N / BN;
+  const int ntiles = gridDim.x;
+  const int L = blockIdx.x;
+  const int xcd = L & 7, per = ntiles >> 3, rem = ntiles & 7;
+  const int tile = xcd * per + (xcd < rem ? xcd : rem) + (L >> 3);
+  const int m0 = (tile / gn) * BM;
+  const int n0 = (tile - (tile / gn) * gn) * BN;
   const int Mlive = a.dyn_m ? *a.dyn_m : a.M;
   const int nreq = a.dyn_nreq ? *a.dyn_nreq : a.nreq;
   if (m0 >= Mlive) return;  // grid sized for a capacity
-  const int n0 = blockIdx.y * BN;
   const int KT = a.K / BK;
   const T* __restrict__ W = (const T*)a.W;
   const T* __restrict__ X = (const T*)a.X;
@@ -389,9 +398,9 @@ template <class Op, int EPI, int XM, class OutT>
 int launch_t(const GemmArgs& a, hipStream_t s) {
   const int gm = cdiv(a.M, BM);
   if (a.N % 128 == 0) {
-    gemm_kernel<Op, 128, EPI, XM, OutT><<<dim3(gm, a.N / 128), NT, 0, s>>>(a);
+    gemm_kernel<Op, 128, EPI, XM, OutT><<<dim3(gm * (a.N / 128)), NT, 0, s>>>(a);
   } else {
-    gemm_kernel<Op, 64, EPI, XM, OutT><<<dim3(gm, a.N / 64), NT, 0, s>>>(a);
+    gemm_kernel<Op, 64, EPI, XM, OutT><<<dim3(gm * (a.N / 64)), NT, 0, s>>>(a);
   }
   return hipGetLastError() == hipSuccess ? 0 : -5;
 }
