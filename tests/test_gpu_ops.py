@@ -97,7 +97,7 @@ def _attn_inputs(heads, ntok, prec, scale=1.0, ld=None):
 
 
 @pytest.mark.parametrize("prec", [FP32, BF16])
-@pytest.mark.parametrize("heads,ntok", [(1, 1), (2, 63), (6, 576), (3, 1000), (1, 4099)])
+@pytest.mark.parametrize("heads,ntok", [(1, 1), (2, 63), (2, 64), (1, 128), (6, 576), (3, 1000), (1, 4099)])
 def test_attention(prec, heads, ntok):
     qd, kd, vt, q64, k64, v64, ld = _attn_inputs(heads, ntok, prec, scale=1.5)
     o = torch.zeros((ntok, heads * 64), dtype=_dt(prec)).cuda()
@@ -114,6 +114,40 @@ def test_attention(prec, heads, ntok):
             err = np.abs(g - ref)
             assert err.max() < 1.5e-2 * np.abs(v64[h]).max(), float(err.max())
             assert np.sqrt(np.mean(err ** 2)) < 4e-3 * np.sqrt(np.mean(ref ** 2)) + 1e-3
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+@pytest.mark.parametrize("direction", [1, -1])
+def test_attention_drifting_max(prec, direction):
+    """Scores that rise (or fall) steadily over the keys, by about 300 in
+    natural-log units end to end: the running max is raised many times (or
+    set by the first block and never again), and the result must still be
+    the softmax average."""
+    heads, ntok = 2, 2000
+    qd, kd, vt, q64, k64, v64, ld = _attn_inputs(heads, ntok, prec, scale=0.3)
+    u = np.zeros(64)
+    u[0] = 1.0
+    ramp = np.linspace(0.0, 1.0, ntok) if direction > 0 else np.linspace(1.0, 0.0, ntok)
+    kk = k64 + 60.0 * ramp[None, :, None] * u
+    qq = q64 + 40.0 * u
+    dt = _dt(prec)
+    k_op = torch.tensor(kk, dtype=torch.float32).to(dt)
+    q_op = torch.tensor(qq * (math.log2(math.e) / 8), dtype=torch.float32).to(dt)
+    kd[:, :ntok] = k_op.cuda()
+    qd[:, :ntok] = q_op.cuda()
+    q64 = q_op.double().numpy() / (math.log2(math.e) / 8)
+    k64 = k_op.double().numpy()
+    o = torch.zeros((ntok, heads * 64), dtype=dt).cuda()
+    assert _lib().revo_op_attention(prec, qd.data_ptr(), kd.data_ptr(), vt.data_ptr(), o.data_ptr(), heads, ntok, ld, None) == 0
+    got = o.double().cpu().numpy()
+    for h in range(heads):
+        ref = oracle.attention_head(q64[h], k64[h], v64[h])
+        err = np.abs(got[:, h * 64:(h + 1) * 64] - ref)
+        # a float32 score s (log2 units) is off by a few ulp(s): each
+        # probability moves by about 2^-23 |s| relative, times a few
+        smax = (np.abs(q64[h]) @ np.abs(k64[h]).T).max() / 8 * math.log2(math.e)
+        bound = 2e-5 + 1e-6 * smax if prec == FP32 else 1.5e-2
+        assert err.max() < bound * np.abs(v64[h]).max(), (float(err.max()), smax)
 
 
 def test_attention_uniform_keys_average_values():
@@ -138,6 +172,25 @@ def test_convert_bf16_rounding():
 
 
 FP8 = 2
+
+
+def _fp8_group_loss(a8, b8):
+    """Bound on what the FP8 MFMA drops when it sums products: it adds each
+    group of 8 consecutive k products after aligning them to the group's
+    largest product, keeping about 14 bits below that product's leading bit
+    (measured on gfx950: 448*448 + 4 gives 448*448, 448*448 + 8 is exact;
+    across groups the sum is FP32).  Per product the loss is below both |p|
+    and 2^(E - 13), E = floor(log2 max |p|) of its group (a factor 2 of
+    margin over the measured window).  a8 [M][K], b8 [N][K] in code units."""
+    # products of two E4M3 values are exact in float32
+    a8, b8 = np.abs(a8).astype(np.float32), np.abs(b8).astype(np.float32)
+    loss = np.zeros((a8.shape[0], b8.shape[0]))
+    for g in range(0, a8.shape[1], 8):
+        p = a8[:, None, g:g + 8] * b8[None, :, g:g + 8]
+        _, e = np.frexp(p.max(axis=2))            # max = f * 2^e, f in [0.5, 1)
+        win = np.ldexp(np.float32(1), e - 14)      # 2^(floor(log2 max) - 13)
+        loss += np.minimum(p, win[..., None]).sum(axis=2)
+    return loss
 
 
 def _fp8_bytes(v):
@@ -175,6 +228,7 @@ def test_linear_fp8(M, N, K, epi):
     ref = xq @ wq.T + bd.double().cpu().numpy()
     # the kernel's scales are float32 copies of the oracle's
     ref_scale_err = 2 * 2.0 ** -24 * np.abs(xq).sum(1, keepdims=True) @ np.abs(wq).max(1, keepdims=True).T
+    ref_scale_err = ref_scale_err + _fp8_group_loss(xq / xs, wq / ws[:, None]) * ws[None, :] * xs
     osd = torch.tensor([0.05], dtype=torch.float32).cuda()
     if epi == 1:
         res = RNG.standard_normal((M, N)).astype(np.float32)
@@ -188,18 +242,22 @@ def test_linear_fp8(M, N, K, epi):
                                    out.data_ptr(), osd.data_ptr(), M, N, K, None)
     assert rc == 0
     torch.cuda.synchronize()
+    scale = np.abs(ref).max() + 1e-30
+    tol = 2e-6 * math.sqrt(K) * scale + ref_scale_err      # on the pre-activation value
     if epi == 2:
         got = out.cpu().view(torch.float8_e4m3fn).to(torch.float64).numpy() * 0.05
         want = oracle.e4m3_round(oracle.gelu(ref) / 0.05) * 0.05
-        # one E4M3 step (quantum of the scaled value) where float32 accumulation
-        # lands on the other side of a rounding midpoint than float64
-        step = np.exp2(np.maximum(np.floor(np.log2(np.maximum(np.abs(want) / 0.05, 1e-30))), -6) - 3) * 0.05
-        assert np.all(np.abs(got - want) <= step + 1e-12)
-        assert np.sum(got != want) <= max(2, 0.01 * got.size)   # rounding-midpoint ties only
+        # |GELU'| <= 1.13, so the pre-activation tolerance moves GELU by at
+        # most 1.13 tol; each side then rounds to E4M3 (half a step each,
+        # bounded by the step at the larger of the two magnitudes)
+        big = np.maximum(np.abs(want), np.abs(got)) / 0.05
+        step = np.exp2(np.maximum(np.floor(np.log2(np.maximum(big, 1e-30))), -6) - 3) * 0.05
+        bad = np.argwhere(np.abs(got - want) > step + 1.13 * tol + 1e-12)
+        assert bad.size == 0, [(tuple(i), float(ref[tuple(i)]), float(got[tuple(i)] / 0.05),
+                                float(want[tuple(i)] / 0.05)) for i in bad[:8]]
+        assert np.sum(got != want) <= max(2, 0.01 * got.size)   # codes away from rounding midpoints agree
         return
     got = out.double().cpu().numpy()
-    scale = np.abs(ref).max() + 1e-30
-    tol = 2e-6 * math.sqrt(K) * scale + ref_scale_err
     if epi == 0:
         tol = tol + 4e-3 * np.abs(ref)
     assert np.all(np.abs(got - ref) <= tol + 1e-7), float(np.abs(got - ref).max())
