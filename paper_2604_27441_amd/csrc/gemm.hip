@@ -235,30 +235,47 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
     c_row[i] = (tid + i * NT) / CPR;
     c_k[i] = ((tid + i * NT) % CPR) * E;
   }
-  uint4 xr[XC], wr[WC];
-#define REVO_GEMM_LOAD(kt_)                                                                                  \
+  // two register sets of stage operands: the loads for stage k+2 are
+  // issued while stage k is multiplied, so two stages of compute cover the
+  // memory latency
+  uint4 xr0[XC], wr0[WC], xr1[XC], wr1[WC];
+  // Dense operands come in through buffer loads: a per-thread byte offset
+  // and a scalar one per stage, and activation rows at or past Mlive fall
+  // outside the descriptor's range and read as zeros, so no lane branches
+  // around a load (the host keeps both operands below 2 GiB).
+  const __amdgpu_buffer_rsrc_t wrs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)W, (short)0, a.N * a.K * (int)sizeof(T), 0x00020000);
+  const __amdgpu_buffer_rsrc_t xrs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, XM == X_DENSE ? Mlive * a.K * (int)sizeof(T) : 0,
+                                        0x00020000);
+  int xoff[XC], woff[WC];
+#pragma unroll
+  for (int i = 0; i < XC; ++i) xoff[i] = ((m0 + c_row[i]) * a.K + c_k[i]) * (int)sizeof(T);
+#pragma unroll
+  for (int i = 0; i < WC; ++i) woff[i] = ((n0 + c_row[i]) * a.K + c_k[i]) * (int)sizeof(T);
+#define REVO_GEMM_LOAD(kt_, XR, WR)                                                                          \
   do {                                                                                                       \
     const int k0_ = (kt_) * BK;                                                                              \
     _Pragma("unroll") for (int i = 0; i < XC; ++i) {                                                         \
-      const int m_ = m0 + c_row[i];                                                                          \
       if (XM == X_DENSE) {                                                                                   \
-        xr[i] = m_ < Mlive ? *reinterpret_cast<const uint4*>(X + (size_t)m_ * a.K + k0_ + c_k[i])            \
-                         : make_uint4(0, 0, 0, 0);                                                           \
+        XR[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(                             \
+                                              xrs, xoff[i], k0_ * (int)sizeof(T), 0));                       \
       } else {                                                                                               \
-        xr[i] = g_req[i] >= 0                                                                                \
+        XR[i] = g_req[i] >= 0                                                                                \
                     ? gather_chunk<Op>(a.reqs[g_req[i]], g_j[i], g_y[i], g_x[i], k0_ + c_k[i], a.channels)   \
                     : make_uint4(0, 0, 0, 0);                                                                \
       }                                                                                                      \
     }                                                                                                        \
     _Pragma("unroll") for (int i = 0; i < WC; ++i)                                                           \
-      wr[i] = *reinterpret_cast<const uint4*>(W + (size_t)(n0 + c_row[i]) * a.K + k0_ + c_k[i]);             \
+      WR[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(                               \
+                                            wrs, woff[i], k0_ * (int)sizeof(T), 0));                         \
   } while (0)
-#define REVO_GEMM_STORE(buf_)                                                                                \
+#define REVO_GEMM_STORE(buf_, XR, WR)                                                                        \
   do {                                                                                                       \
     _Pragma("unroll") for (int i = 0; i < XC; ++i)                                                           \
-      *reinterpret_cast<uint4*>(&xs[buf_][c_row[i] * PITCH + c_k[i]]) = xr[i];                               \
+      *reinterpret_cast<uint4*>(&xs[buf_][c_row[i] * PITCH + c_k[i]]) = XR[i];                               \
     _Pragma("unroll") for (int i = 0; i < WC; ++i)                                                           \
-      *reinterpret_cast<uint4*>(&ws[buf_][c_row[i] * PITCH + c_k[i]]) = wr[i];                               \
+      *reinterpret_cast<uint4*>(&ws[buf_][c_row[i] * PITCH + c_k[i]]) = WR[i];                               \
   } while (0)
 
   const int wn = wave >> 1, wm = wave & 1;
@@ -266,59 +283,64 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
 #pragma unroll
   for (int i = 0; i < NSUB; ++i) { acc[i][0] = f32x16{}; acc[i][1] = f32x16{}; }
 
-  REVO_GEMM_LOAD(0);
-  REVO_GEMM_STORE(0);
+  // one K stage from LDS buffer buf_ into the accumulators
+#define REVO_GEMM_COMPUTE(buf_)                                                                              \
+  _Pragma("unroll") for (int s = 0; s < STEPS; s += G) {                                                     \
+    const int koff = half * (BK / 2) + s * Op::KPL;                                                          \
+    if constexpr (FB == 32) {                                                                                \
+      uint4 wf[NSUB][2], xf[2][2];                                                                           \
+      _Pragma("unroll") for (int ns = 0; ns < NSUB; ++ns) {                                                  \
+        const T* p = &ws[buf_][(wn * (BN / 2) + ns * 32 + l32) * PITCH + koff];                              \
+        wf[ns][0] = reinterpret_cast<const uint4*>(p)[0];                                                    \
+        wf[ns][1] = reinterpret_cast<const uint4*>(p)[1];                                                    \
+      }                                                                                                      \
+      _Pragma("unroll") for (int ms = 0; ms < 2; ++ms) {                                                     \
+        const T* p = &xs[buf_][(wm * 64 + ms * 32 + l32) * PITCH + koff];                                    \
+        xf[ms][0] = reinterpret_cast<const uint4*>(p)[0];                                                    \
+        xf[ms][1] = reinterpret_cast<const uint4*>(p)[1];                                                    \
+      }                                                                                                      \
+      _Pragma("unroll") for (int ns = 0; ns < NSUB; ++ns)                                                    \
+        _Pragma("unroll") for (int ms = 0; ms < 2; ++ms)                                                     \
+          Op::mma(acc[ns][ms], frag_fp8(wf[ns][0], wf[ns][1]), frag_fp8(xf[ms][0], xf[ms][1]));              \
+    } else {                                                                                                 \
+      uint4 wf[NSUB], xf[2];                                                                                 \
+      _Pragma("unroll") for (int ns = 0; ns < NSUB; ++ns)                                                    \
+        wf[ns] = *reinterpret_cast<const uint4*>(&ws[buf_][(wn * (BN / 2) + ns * 32 + l32) * PITCH + koff]); \
+      _Pragma("unroll") for (int ms = 0; ms < 2; ++ms)                                                       \
+        xf[ms] = *reinterpret_cast<const uint4*>(&xs[buf_][(wm * 64 + ms * 32 + l32) * PITCH + koff]);       \
+      _Pragma("unroll") for (int g = 0; g < G; ++g)                                                          \
+        _Pragma("unroll") for (int ns = 0; ns < NSUB; ++ns)                                                  \
+          _Pragma("unroll") for (int ms = 0; ms < 2; ++ms)                                                   \
+            Op::mma(acc[ns][ms], frag_of<Op>(wf[ns], g), frag_of<Op>(xf[ms], g));                            \
+    }                                                                                                        \
+  }
+
+  // stage k sits in LDS buffer k % 2 and, before that, in register set k % 2
+  // (prefetches past the last stage re-read the last stage; those copies
+  // are never stored)
+  REVO_GEMM_LOAD(0, xr0, wr0);
+  REVO_GEMM_LOAD(KT > 1 ? 1 : 0, xr1, wr1);
+  REVO_GEMM_STORE(0, xr0, wr0);
   __syncthreads();
-  for (int kt = 0; kt < KT; ++kt) {
-    const int buf = kt & 1;
-    // prefetch the next stage (the last iteration re-reads its own stage into
-    // the idle buffer, which is never read)
-    const int kn = kt + 1 < KT ? kt + 1 : kt;
-    REVO_GEMM_LOAD(kn);
-#pragma unroll
-    for (int s = 0; s < STEPS; s += G) {
-      const int koff = half * (BK / 2) + s * Op::KPL;
-      if constexpr (FB == 32) {
-        uint4 wf[NSUB][2], xf[2][2];
-#pragma unroll
-        for (int ns = 0; ns < NSUB; ++ns) {
-          const T* p = &ws[buf][(wn * (BN / 2) + ns * 32 + l32) * PITCH + koff];
-          wf[ns][0] = reinterpret_cast<const uint4*>(p)[0];
-          wf[ns][1] = reinterpret_cast<const uint4*>(p)[1];
-        }
-#pragma unroll
-        for (int ms = 0; ms < 2; ++ms) {
-          const T* p = &xs[buf][(wm * 64 + ms * 32 + l32) * PITCH + koff];
-          xf[ms][0] = reinterpret_cast<const uint4*>(p)[0];
-          xf[ms][1] = reinterpret_cast<const uint4*>(p)[1];
-        }
-#pragma unroll
-        for (int ns = 0; ns < NSUB; ++ns)
-#pragma unroll
-          for (int ms = 0; ms < 2; ++ms)
-            Op::mma(acc[ns][ms], frag_fp8(wf[ns][0], wf[ns][1]), frag_fp8(xf[ms][0], xf[ms][1]));
-      } else {
-        uint4 wf[NSUB], xf[2];
-#pragma unroll
-        for (int ns = 0; ns < NSUB; ++ns)
-          wf[ns] = *reinterpret_cast<const uint4*>(&ws[buf][(wn * (BN / 2) + ns * 32 + l32) * PITCH + koff]);
-#pragma unroll
-        for (int ms = 0; ms < 2; ++ms)
-          xf[ms] = *reinterpret_cast<const uint4*>(&xs[buf][(wm * 64 + ms * 32 + l32) * PITCH + koff]);
-#pragma unroll
-        for (int g = 0; g < G; ++g)
-#pragma unroll
-          for (int ns = 0; ns < NSUB; ++ns)
-#pragma unroll
-            for (int ms = 0; ms < 2; ++ms)
-              Op::mma(acc[ns][ms], frag_of<Op>(wf[ns], g), frag_of<Op>(xf[ms], g));
-      }
-    }
-    REVO_GEMM_STORE(buf ^ 1);
+  // (the scheduling barriers keep each prefetch ahead of the multiplies
+  // it is meant to overlap)
+  for (int kt = 0; kt < KT; kt += 2) {
+    REVO_GEMM_LOAD(kt + 2 < KT ? kt + 2 : KT - 1, xr0, wr0);
+    __builtin_amdgcn_sched_barrier(0);
+    REVO_GEMM_COMPUTE(0)
+    if (kt + 1 >= KT) break;
+    REVO_GEMM_STORE(1, xr1, wr1);
+    __syncthreads();
+    REVO_GEMM_LOAD(kt + 3 < KT ? kt + 3 : KT - 1, xr1, wr1);
+    __builtin_amdgcn_sched_barrier(0);
+    REVO_GEMM_COMPUTE(1)
+    if (kt + 2 >= KT) break;
+    REVO_GEMM_STORE(0, xr0, wr0);
     __syncthreads();
   }
 #undef REVO_GEMM_LOAD
 #undef REVO_GEMM_STORE
+#undef REVO_GEMM_COMPUTE
 
   // ---------------------------------------------------------------- epilogue
   const float xsc = a.xscale ? *a.xscale : 1.0f;
@@ -408,11 +430,19 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
 template <class Op, int EPI, int XM, class OutT>
 int launch_t(const GemmArgs& a, hipStream_t s) {
   const int gm = cdiv(a.M, BM);
-  if (a.N % 128 == 0) {
-    gemm_kernel<Op, 128, EPI, XM, OutT><<<dim3(gm * (a.N / 128)), NT, 0, s>>>(a);
-  } else {
-    gemm_kernel<Op, 64, EPI, XM, OutT><<<dim3(gm * (a.N / 64)), NT, 0, s>>>(a);
+  // buffer-load byte offsets are 32-bit: both operands, with X padded to
+  // whole row tiles, stay below 2 GiB
+  const long long esz = sizeof(typename Op::T);
+  if ((long long)gm * BM * a.K * esz >= (1LL << 31) || (long long)a.N * a.K * esz >= (1LL << 31)) return -22;
+  // the gather loader's per-row token coordinates leave no registers for a
+  // 128-wide tile with two prefetched stages
+  if constexpr (XM == X_DENSE) {
+    if (a.N % 128 == 0) {
+      gemm_kernel<Op, 128, EPI, XM, OutT><<<dim3(gm * (a.N / 128)), NT, 0, s>>>(a);
+      return hipGetLastError() == hipSuccess ? 0 : -5;
+    }
   }
+  gemm_kernel<Op, 64, EPI, XM, OutT><<<dim3(gm * (a.N / 64)), NT, 0, s>>>(a);
   return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 
