@@ -16,8 +16,13 @@
 // scores exceed it by more than 8 (in log2 units), so probabilities stay
 // below 2^8 and the output rescale is skipped for almost every block; the
 // final division by the row sum makes the result independent of the max
-// used.  Only the last key block of a request checks key bounds.
-// K and V^T blocks of 64 keys are double-buffered in LDS.
+// used.  The first block sets the max; after it (BF16) the score products
+// accumulate onto a register block holding -max, so they come out already
+// shifted and the softmax is a bare exp2 per score.  Only the last key
+// block of a request checks key bounds.
+// K and V^T blocks of 64 keys are double-buffered in LDS; they come in
+// through buffer loads with scalar per-block offsets, and the block loop
+// runs two blocks per trip so both LDS buffers have fixed addresses.
 #include "kernels.h"
 
 namespace revo {
@@ -50,16 +55,26 @@ struct AttnTile {
 };
 
 // One 64-key block for one wave: scores, online softmax, P V accumulation.
-template <class Op, bool MASK>
+template <class Op, bool MASK, bool FIRST>
 __device__ __forceinline__ void attn_block(const typename Op::T* __restrict__ kt, const typename Op::T* __restrict__ vt,
                                            const uint4 (&qf)[AttnTile<typename Op::T>::QCH], f32x16 (&oacc)[2],
-                                           float& m_run, float& l_run, int lane, int kvalid) {
+                                           f32x16& negm, float& m_run, float& l_run, int lane, int kvalid) {
   typedef typename Op::T T;
   typedef AttnTile<T> A;
   const int half = lane >> 5, l32 = lane & 31;
+  // BF16: after the first block the score products start from -m_run (all
+  // 16 registers of negm), so they come out already shifted by the max
+  constexpr bool SHIFTED = sizeof(T) == 2 && !FIRST;
 
   // S^T = K Q^T for two 32-key subtiles
-  f32x16 sacc[2] = {f32x16{}, f32x16{}};
+  f32x16 sacc[2];
+  if constexpr (SHIFTED) {
+    sacc[0] = negm;
+    sacc[1] = negm;
+  } else {
+    sacc[0] = f32x16{};
+    sacc[1] = f32x16{};
+  }
 #pragma unroll
   for (int kc = 0; kc < A::QCH; ++kc) {
 #pragma unroll
@@ -93,24 +108,55 @@ __device__ __forceinline__ void attn_block(const typename Op::T* __restrict__ kt
   }
   float mloc = fmaxf(fmaxf(m0, sacc[0][15]), fmaxf(m1, sacc[1][15]));
   mloc = xhalf_max(mloc);
-  const bool grow = mloc > m_run + LAZY;
-  if (__any(grow)) {
-    const float m_new = grow ? mloc : m_run;
-    const float alpha = __builtin_amdgcn_exp2f(m_run - m_new);
-    m_run = m_new;
-    l_run *= alpha;
-    oacc[0] *= alpha;
-    oacc[1] *= alpha;
-    // keep the rescale inside this (rarely taken) branch instead of letting
-    // it become an unconditional multiply by a selected factor
-    asm volatile("" : "+v"(oacc[0]), "+v"(oacc[1]));
+  if constexpr (FIRST) {
+    // nothing accumulated yet: take this block's max as it is
+    m_run = mloc;
+    if constexpr (sizeof(T) == 2) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) negm[i] = -mloc;
+#pragma unroll
+      for (int st = 0; st < 2; ++st)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) sacc[st][i] -= mloc;
+    }
+  } else if constexpr (SHIFTED) {
+    // mloc is relative to m_run here
+    const bool grow = mloc > LAZY;
+    if (__any(grow)) {
+      const float d = grow ? mloc : 0.0f;
+      const float alpha = __builtin_amdgcn_exp2f(-d);
+      m_run += d;
+      l_run *= alpha;
+      oacc[0] *= alpha;
+      oacc[1] *= alpha;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) negm[i] = -m_run;
+#pragma unroll
+      for (int st = 0; st < 2; ++st)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) sacc[st][i] -= d;
+      // keep the rescale inside this (rarely taken) branch instead of letting
+      // it become unconditional work with a selected factor
+      asm volatile("" : "+v"(oacc[0]), "+v"(oacc[1]), "+v"(sacc[0]), "+v"(sacc[1]), "+v"(negm));
+    }
+  } else {
+    const bool grow = mloc > m_run + LAZY;
+    if (__any(grow)) {
+      const float m_new = grow ? mloc : m_run;
+      const float alpha = __builtin_amdgcn_exp2f(m_run - m_new);
+      m_run = m_new;
+      l_run *= alpha;
+      oacc[0] *= alpha;
+      oacc[1] *= alpha;
+      asm volatile("" : "+v"(oacc[0]), "+v"(oacc[1]));
+    }
   }
 
   // O^T += V^T P^T, contraction over the block's keys
   if constexpr (sizeof(T) == 2) {
     // row sum from the bf16-rounded probabilities that also feed the MFMA
     const bf16x2 one = {(__bf16)1.0f, (__bf16)1.0f};
-    float ls0 = 0.0f, ls1 = 0.0f;
+    float ls0 = l_run, ls1 = 0.0f;
 #pragma unroll
     for (int st = 0; st < 2; ++st) {
 #pragma unroll
@@ -120,7 +166,7 @@ __device__ __forceinline__ void attn_block(const typename Op::T* __restrict__ kt
         // 8 contiguous elements at st*32 + g*16 + half*8
         bf16x8 pf;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) pf[e] = (__bf16)__builtin_amdgcn_exp2f(sacc[st][8 * g + e] - m_run);
+        for (int e = 0; e < 8; ++e) pf[e] = (__bf16)__builtin_amdgcn_exp2f(sacc[st][8 * g + e]);
         ls0 = __builtin_amdgcn_fdot2_f32_bf16(bf16x2{pf[0], pf[1]}, one, ls0, false);
         ls1 = __builtin_amdgcn_fdot2_f32_bf16(bf16x2{pf[2], pf[3]}, one, ls1, false);
         ls0 = __builtin_amdgcn_fdot2_f32_bf16(bf16x2{pf[4], pf[5]}, one, ls0, false);
@@ -133,7 +179,7 @@ __device__ __forceinline__ void attn_block(const typename Op::T* __restrict__ kt
         }
       }
     }
-    l_run += ls0 + ls1;
+    l_run = ls0 + ls1;
   } else {
     float ls0 = 0.0f, ls1 = 0.0f;
 #pragma unroll
@@ -167,7 +213,7 @@ __device__ __forceinline__ void attn_block(const typename Op::T* __restrict__ kt
 }
 
 template <class Op>
-__global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 4 : 2) void attn_kernel(const AttnArgs a) {
+__global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 3 : 2) void attn_kernel(const AttnArgs a) {
   typedef typename Op::T T;
   typedef AttnTile<T> A;
   __shared__ __attribute__((aligned(16))) T ks[2][KB * A::PITCH];   // [key][dim]
@@ -212,9 +258,19 @@ __global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 4 : 2) void attn_
   const int c_col = (tid % A::CPR) * A::E;
   static_assert(A::LC == 2 || A::LC == 4, "2 or 4 chunks per thread");
   uint4 kr0, kr1, kr2, kr3, vr0, vr1, vr2, vr3;
-#define REVO_ATTN_LOAD1(kb_, i_, kr_, vr_)                                                            \
-  kr_ = *reinterpret_cast<const uint4*>(Kg + (size_t)((kb_) + c_row + (i_) * R) * 64 + c_col);       \
-  vr_ = *reinterpret_cast<const uint4*>(Vg + (size_t)(c_row + (i_) * R) * a.ldv + (kb_) + c_col);
+  const __amdgpu_buffer_rsrc_t krs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)Kg, (short)0, (a.ldqk - base) * 64 * (int)sizeof(T), 0x00020000);
+  const __amdgpu_buffer_rsrc_t vrs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)Vg, (short)0, (64 * a.ldv - base) * (int)sizeof(T), 0x00020000);
+  const int kvo = (c_row * 64 + c_col) * (int)sizeof(T);
+  const int vvo = (c_row * a.ldv + c_col) * (int)sizeof(T);
+#define REVO_ATTN_LOAD1(kb_, i_, kr_, vr_)                                                                     \
+  {                                                                                                            \
+    auto k_ = __builtin_amdgcn_raw_buffer_load_b128(krs, kvo, ((kb_) + (i_) * R) * 64 * (int)sizeof(T), 0);   \
+    auto v_ = __builtin_amdgcn_raw_buffer_load_b128(vrs, vvo, ((i_) * R * a.ldv + (kb_)) * (int)sizeof(T), 0); \
+    kr_ = make_uint4(k_[0], k_[1], k_[2], k_[3]);                                                              \
+    vr_ = make_uint4(v_[0], v_[1], v_[2], v_[3]);                                                              \
+  }
 #define REVO_ATTN_LOAD(kb_)                                                                           \
   REVO_ATTN_LOAD1(kb_, 0, kr0, vr0)                                                                   \
   REVO_ATTN_LOAD1(kb_, 1, kr1, vr1)                                                                   \
@@ -244,21 +300,39 @@ __global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 4 : 2) void attn_
   __syncthreads();
 
   f32x16 oacc[2] = {f32x16{}, f32x16{}};
-  float m_run = NEG_BIG, l_run = 0.0f;
+  f32x16 negm;
+  float m_run = 0.0f, l_run = 0.0f;
   const int nkb = (N + KB - 1) / KB;
   const int nfull = N / KB;
-  for (int b = 0; b < nfull; ++b) {
-    const int buf = b & 1;
-    // prefetch the next block (the last iteration re-reads its own block
-    // into the idle buffer, which is then never read)
-    const int kn = b + 1 < nkb ? (b + 1) * KB : b * KB;
-    REVO_ATTN_LOAD(kn);
-    attn_block<Op, false>(ks[buf], vs[buf], qf, oacc, m_run, l_run, lane, KB);
-    REVO_ATTN_STORE(buf ^ 1);
+  if (nfull == 0) {
+    // a single, ragged block
+    attn_block<Op, true, true>(ks[0], vs[0], qf, oacc, negm, m_run, l_run, lane, N);
+  } else {
+    // the first block sets the max; the prefetch of the next block (or, at
+    // the end, a re-read of its own block into the idle buffer, which is
+    // then never read) overlaps it
+    REVO_ATTN_LOAD(nkb > 1 ? KB : 0);
+    attn_block<Op, false, true>(ks[0], vs[0], qf, oacc, negm, m_run, l_run, lane, KB);
+    REVO_ATTN_STORE(1);
     __syncthreads();
+#define REVO_ATTN_STEP(b_, buf_)                                                                      \
+  {                                                                                                   \
+    const int kn_ = (b_) + 1 < nkb ? ((b_) + 1) * KB : (b_) * KB;                                     \
+    REVO_ATTN_LOAD(kn_);                                                                              \
+    attn_block<Op, false, false>(ks[buf_], vs[buf_], qf, oacc, negm, m_run, l_run, lane, KB);         \
+    REVO_ATTN_STORE(buf_ ^ 1);                                                                        \
+    __syncthreads();                                                                                  \
   }
-  if (nfull < nkb)  // ragged last block, already in LDS
-    attn_block<Op, true>(ks[nfull & 1], vs[nfull & 1], qf, oacc, m_run, l_run, lane, N - nfull * KB);
+    int b = 1;
+    for (; b + 1 < nfull; b += 2) {
+      REVO_ATTN_STEP(b, 1)
+      REVO_ATTN_STEP(b + 1, 0)
+    }
+    if (b < nfull) REVO_ATTN_STEP(b, 1)
+#undef REVO_ATTN_STEP
+    if (nfull < nkb)  // ragged last block, already in LDS
+      attn_block<Op, true, false>(ks[nfull & 1], vs[nfull & 1], qf, oacc, negm, m_run, l_run, lane, N - nfull * KB);
+  }
 #undef REVO_ATTN_LOAD1
 #undef REVO_ATTN_LOAD
 #undef REVO_ATTN_STORE1
