@@ -174,6 +174,32 @@ __device__ uint4 gather_chunk(const ReqDesc& d, int j, int y, int x, int k, int 
   return r.u;
 }
 
+// Tubelet vectors written out once as a dense [M][K] operand (K = T*16*16*C),
+// so the embedding product runs as a plain dense GEMM instead of gathering
+// the same pixels again for every N tile.  One thread per 16-byte chunk;
+// rows in the alignment gaps between requests are zeros.
+template <class Op>
+__global__ void tubelet_pack_kernel(const ReqDesc* __restrict__ reqs, int nreq_, const int* dyn_nreq, int M_,
+                                    const int* dyn_m, int K, int C, typename Op::T* __restrict__ out) {
+  constexpr int E = 16 / sizeof(typename Op::T);
+  const int M = dyn_m ? *dyn_m : M_;
+  const int nreq = dyn_nreq ? *dyn_nreq : nreq_;
+  const int cpr = K / E;
+  const long long total = (long long)M * cpr;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int m = (int)(i / cpr);
+    const int k = (int)(i - (long long)m * cpr) * E;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    const int r = find_req_tok(reqs, nreq, m);
+    const ReqDesc& d = reqs[r];
+    const int t = m - d.tok_off;
+    const int j = t / d.P, p = t - (t / d.P) * d.P;
+    if (t >= 0 && j < d.J) v = gather_chunk<Op>(d, j, p / d.gx, p - (p / d.gx) * d.gx, k, C);
+    *reinterpret_cast<uint4*>(out + (size_t)m * K + k) = v;
+  }
+}
+
 template <class Op, int BN, int EPI, int XM, class OutT>
 __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
   typedef typename Op::T T;
@@ -478,6 +504,21 @@ int launch_fp8(int epi, const GemmArgs& a, hipStream_t s) {
 }
 
 }  // namespace
+
+int launch_tubelet_pack(Prec prec, const GemmArgs& a, void* out, hipStream_t s) {
+  if (a.M <= 0) return 0;
+  const int E = prec == P_FP32 ? 4 : 8;
+  if (a.K % E || !out) return -22;
+  const long long chunks = (long long)a.M * (a.K / E);
+  const int grid = (int)(chunks / 256 + 1 < 65536 ? chunks / 256 + 1 : 65536);
+  if (prec == P_FP32)
+    tubelet_pack_kernel<OpF32><<<grid, 256, 0, s>>>(a.reqs, a.nreq, a.dyn_nreq, a.M, a.dyn_m, a.K, a.channels,
+                                                    (float*)out);
+  else
+    tubelet_pack_kernel<OpBF16><<<grid, 256, 0, s>>>(a.reqs, a.nreq, a.dyn_nreq, a.M, a.dyn_m, a.K, a.channels,
+                                                     (__bf16*)out);
+  return hipGetLastError() == hipSuccess ? 0 : -5;
+}
 
 int launch_gemm(Prec prec, int epi, int xmode, const GemmArgs& a, hipStream_t s) {
   if (a.M <= 0) return 0;

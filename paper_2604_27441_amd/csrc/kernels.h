@@ -78,6 +78,10 @@ struct AttnArgs {
 };
 
 int launch_gemm(Prec prec, int epi, int xmode, const GemmArgs& a, hipStream_t s);
+// Tubelet vectors of the requests in a (reqs, nreq, M, K = tubelet length,
+// channels, dyn_m / dyn_nreq) written to out as a dense [M][K] operand
+// (float for P_FP32, bfloat16 otherwise).
+int launch_tubelet_pack(Prec prec, const GemmArgs& a, void* out, hipStream_t s);
 int launch_attention(Prec prec, const AttnArgs& a, hipStream_t s);
 // y = LN(x) * g + b over rows of length D.  With reqs set, output row i is
 // the target-tubelet token (i - head_off) of the request owning compact row i.

@@ -270,9 +270,21 @@ int enqueue_net(const ModelW& m, Workspace& w, int Mg, int Mhg, int nworkg, int 
     g.reqs = w.d_reqs; g.nreq = nrec; g.channels = m.C;
     g.dyn_m = H ? H + HDR_M : nullptr;
     g.dyn_nreq = H ? H + HDR_NREC : nullptr;
-    // tubelet embedding (implicit GEMM over the gathered frames) + PE
+    // tubelet embedding + PE: the tubelet vectors are packed into the MLP
+    // hidden buffer (free at this point) when they fit, then multiplied as a
+    // dense operand; longer tubelets gather inside the product
     g.M = Mg; g.N = m.De; g.K = m.tub_len(); g.W = m.emb_w; g.bias = m.emb_b; g.out = w.h; g.ldo = m.De;
-    if ((rc = gemm(pb, EPI_PE, X_GATHER, g, Mreal))) return rc;
+    if (m.tub_len() <= 4 * m.De) {
+      {
+        ProfScope ps(w.prof, s, PK_OTHER, 0.0);
+        if ((rc = launch_tubelet_pack(pb, g, w.hid, s))) return rc;
+      }
+      GemmArgs ge = g;
+      ge.X = w.hid;
+      if ((rc = gemm(pb, EPI_PE, X_DENSE, ge, Mreal))) return rc;
+    } else if ((rc = gemm(pb, EPI_PE, X_GATHER, g, Mreal))) {
+      return rc;
+    }
 
     AttnArgs at;
     memset(&at, 0, sizeof(at));
