@@ -12,13 +12,13 @@ float64 unless a rounding emulation is requested for error budgeting.
 from .model import (
     Arch, unpack_weights, normalise, zero_fill, sequence_frames, tubelet_vectors,
     sinusoid, positional_embedding, linear, layer_norm, gelu, attention_head,
-    self_attention, transformer_block, forward, recover, composite, Rounding,
+    self_attention, transformer_block, forward, place_target_slot, recover, composite, Rounding,
     bf16_round, e4m3_round, FP8Rounding, AbsMaxRecorder,
 )
 
 __all__ = [
     "Arch", "unpack_weights", "normalise", "zero_fill", "sequence_frames", "tubelet_vectors",
     "sinusoid", "positional_embedding", "linear", "layer_norm", "gelu", "attention_head",
-    "self_attention", "transformer_block", "forward", "recover", "composite", "Rounding",
+    "self_attention", "transformer_block", "forward", "place_target_slot", "recover", "composite", "Rounding",
     "bf16_round", "e4m3_round", "FP8Rounding", "AbsMaxRecorder",
 ]

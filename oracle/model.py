@@ -379,9 +379,18 @@ def forward(refs, ref_idx, target, t_target, mask, params, arch, rnd=EXACT):
     P = gy * gx
     zt = layer_norm(z[(J - 1) * P:], params["dec_norm.g"], params["dec_norm.b"])
     o = linear(zt, params["head.w"], params["head.b"], rnd, "head")   # [P, T*256*C]
-    slot = o.reshape(P, T, PATCH, PATCH, C)[:, T - 1]          # target time slot
-    pred = slot.reshape(gy, gx, PATCH, PATCH, C).transpose(0, 2, 1, 3, 4).reshape(Hp, Wp, C)
-    return pred[:H, :W, :]
+    return place_target_slot(o, gy, gx, T, C)[:H, :W, :]
+
+
+def place_target_slot(o, gy, gx, T, C):
+    """Frame [16 gy, 16 gx, C] from the head outputs of the target tubelet's
+    tokens (§3.4.1: the module outputs the reconstructed frame).  Token
+    p = y*gx + x holds T*16*16*C values ordered (t, py, px, c), as its input
+    tubelet vector; the target frame is time slot t = T-1, and value
+    (py, px, c) goes to pixel (16y + py, 16x + px), channel c."""
+    P = gy * gx
+    slot = np.asarray(o).reshape(P, T, PATCH, PATCH, C)[:, T - 1]
+    return slot.reshape(gy, gx, PATCH, PATCH, C).transpose(0, 2, 1, 3, 4).reshape(gy * PATCH, gx * PATCH, C)
 
 
 def composite(pred, received, mask, channels):

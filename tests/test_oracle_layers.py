@@ -212,3 +212,23 @@ def test_absmax_recorder_sites():
     exact = oracle.recover(req, blobs, enc_depth=2, dec_depth=1, modalities=("rgb",))
     again = oracle.recover(req, blobs, enc_depth=2, dec_depth=1, rnd=oracle.AbsMaxRecorder(), modalities=("rgb",))
     assert np.array_equal(exact["rgb"][0], again["rgb"][0])                 # recording changes nothing
+
+
+@pytest.mark.parametrize("gy,gx,T,C", [(2, 3, 2, 3), (3, 2, 2, 1), (1, 4, 3, 3), (2, 2, 1, 1)])
+def test_head_placement_is_the_index_bijection(gy, gx, T, C):
+    """Head outputs tagged (token id, output index) land pixel by pixel where
+    the tubelet layout puts them: token y*gx + x, slot T-1, (py, px, c)."""
+    P, L = gy * gx, T * 256 * C
+    o = np.arange(P)[:, None] * 100000.0 + np.arange(L)[None, :]
+    frame = oracle.place_target_slot(o, gy, gx, T, C)
+    assert frame.shape == (16 * gy, 16 * gx, C)
+    for Y in range(16 * gy):
+        for X in range(16 * gx):
+            for c in range(C):
+                tok = (Y // 16) * gx + (X // 16)
+                idx = (((T - 1) * 16 + Y % 16) * 16 + X % 16) * C + c
+                assert frame[Y, X, c] == tok * 100000.0 + idx
+    # a bijection onto the target slot's outputs
+    used = np.sort(frame.ravel())
+    want = np.sort((np.arange(P)[:, None] * 100000.0 + ((T - 1) * 256 * C + np.arange(256 * C))[None, :]).ravel())
+    assert np.array_equal(used, want)
