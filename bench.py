@@ -30,12 +30,16 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 matrix
 
 def model_flop_per_request(N, P, C, T=2, De=384, Dd=192, ne=12, nd=4):
     """Algorithmic FLOPs of one request: embedding, blocks (linear + attention),
-    encoder-to-decoder projection, head on the target time slot."""
+    encoder-to-decoder projection, head on the target time slot.  The last
+    decoder block only needs the target tubelet's P queries (K and V of all
+    N tokens, Q, projection and MLP of P rows, attention P x N): the path
+    prunes that block's attention to them, and counts only what is needed."""
     L = T * 256 * C
     f = 2.0 * N * L * De
     f += ne * (24.0 * N * De * De + 4.0 * N * N * De)
     f += 2.0 * N * De * Dd
-    f += nd * (24.0 * N * Dd * Dd + 4.0 * N * N * Dd)
+    f += (nd - 1) * (24.0 * N * Dd * Dd + 4.0 * N * N * Dd)
+    f += 4.0 * N * Dd * Dd + 20.0 * P * Dd * Dd + 4.0 * N * P * Dd
     f += 2.0 * P * Dd * 256 * C
     return f
 

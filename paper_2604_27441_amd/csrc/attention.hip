@@ -232,11 +232,13 @@ __global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 3 : 2) void attn_
   const int Lr = xcd * per + (xcd < rem ? xcd : rem) + (L >> 3);
   const int hd = Lr / nwork;
   const int w = a.work[Lr - hd * nwork];
-  const int r = w >> 16, qt = w & 0xFFFF;
+  const int r = w >> 16, qt = w & (ATTN_TARGET_TILE - 1);
   const ReqDesc& d = a.reqs[r];
   const int N = d.J * d.P;
   const int base = d.tok_off;
-  const int q_local = qt * QT + wave * 32 + (lane & 31);
+  // target-tubelet tiles (the last block, whose other queries feed nothing)
+  const int q0 = (w & ATTN_TARGET_TILE) ? (d.J - 1) * d.P : 0;
+  const int q_local = q0 + qt * QT + wave * 32 + (lane & 31);
   const int q = base + q_local;
 
   const T* __restrict__ Kg = (const T*)a.k + ((size_t)hd * a.ldqk + base) * 64;

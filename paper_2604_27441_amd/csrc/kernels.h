@@ -43,7 +43,7 @@ enum XMode {
 
 // Batch shape in device memory (read by kernels launched with grids sized
 // for a capacity, e.g. from a captured graph): rows past the live counts exit.
-enum BatchHdr { HDR_M = 0, HDR_MH = 1, HDR_NREC = 2, HDR_NALL = 3, HDR_NWORK = 4, HDR_N = 8 };
+enum BatchHdr { HDR_M = 0, HDR_MH = 1, HDR_NREC = 2, HDR_NALL = 3, HDR_NWORK = 4, HDR_NWORK_LAST = 5, HDR_N = 8 };
 
 struct GemmArgs {
   int M, N, K;       // M sizes the grid; the live row count is *dyn_m when set
@@ -63,6 +63,8 @@ struct GemmArgs {
   const ReqDesc* reqs; int nreq; int channels;
 };
 
+constexpr int ATTN_TARGET_TILE = 0x8000;
+
 struct AttnArgs {
   const void* q;     // [heads][ldqk rows][64], pre-scaled by log2(e)/sqrt(64)
   const void* k;     // [heads][ldqk rows][64]
@@ -70,7 +72,9 @@ struct AttnArgs {
   void* o;           // [M][heads * 64]
   int heads, ldqk, ldv;
   const ReqDesc* reqs; int nreq;
-  const int* work;   // per workgroup: (request << 16) | q-tile
+  // per workgroup: (request << 16) | q-tile, with ATTN_TARGET_TILE set for a
+  // q-tile of the request's target tubelet only (queries from (J-1)*P on)
+  const int* work;
   int nwork;         // sizes the grid; the live count is *dyn_nwork when set
   const int* dyn_nwork;  // nullable
   const int* dyn_nreq;   // nullable

@@ -181,7 +181,7 @@ size_t workspace_bytes(const ModelW& m, int cap, int max_req) {
   b += (size_t)cap * 4 * De * e;         // hid
   b += (size_t)cap * m.Dd * 4;           // z
   b += (size_t)cap * m.Dd * e;           // ahead (target rows <= cap)
-  b += (size_t)max_req * sizeof(ReqDesc) + (size_t)(cap / 128 + max_req + 1) * 4 + HDR_N * 4;
+  b += (size_t)max_req * sizeof(ReqDesc) + 2 * (size_t)(cap / 128 + max_req + 1) * 4 + HDR_N * 4;
   return b + 16 * 256;
 }
 
@@ -206,12 +206,12 @@ int workspace_alloc(Workspace& w, const ModelW& m, int cap, int max_req, hipStre
   rc |= get((void**)&w.z, (size_t)cap * m.Dd * 4);
   rc |= get(&w.ahead, (size_t)cap * m.Dd * e);
   rc |= get((void**)&w.d_reqs, (size_t)max_req * sizeof(ReqDesc));
-  rc |= get((void**)&w.d_work, (size_t)w.max_work * 4);
+  rc |= get((void**)&w.d_work, 2 * (size_t)w.max_work * 4);  // all q-tiles, then target-tubelet q-tiles
   rc |= get((void**)&w.d_hdr, HDR_N * 4);
   if (rc) return rc < 0 ? rc : -5;
   for (int sl = 0; sl < WS_SLOTS; ++sl) {
     REVO_HIP_TRY(hipHostMalloc((void**)&w.h_reqs_slot[sl], (size_t)max_req * sizeof(ReqDesc), hipHostMallocDefault));
-    REVO_HIP_TRY(hipHostMalloc((void**)&w.h_work_slot[sl], (size_t)w.max_work * 4, hipHostMallocDefault));
+    REVO_HIP_TRY(hipHostMalloc((void**)&w.h_work_slot[sl], 2 * (size_t)w.max_work * 4, hipHostMallocDefault));
     REVO_HIP_TRY(hipHostMalloc((void**)&w.h_hdr_slot[sl], HDR_N * 4, hipHostMallocDefault));
     memset(w.h_reqs_slot[sl], 0, (size_t)max_req * sizeof(ReqDesc));
   }
@@ -240,8 +240,9 @@ namespace {
 // Launch sequence of the network.  Grid sizes come from the arguments (exact
 // counts when eager, bucket capacities when captured); with dyn set, the
 // kernels read the live counts from the device batch header.
-int enqueue_net(const ModelW& m, Workspace& w, int Mg, int Mhg, int nworkg, int nrec, int nall, int max_pix,
-                int composite, bool dyn, double Mreal, double Mh_real, double attn_pairs, bool record, hipStream_t s) {
+int enqueue_net(const ModelW& m, Workspace& w, int Mg, int Mhg, int nworkg, int nworkg_last, int nrec, int nall,
+                int max_pix, int composite, bool dyn, double Mreal, double Mh_real, double attn_pairs,
+                double attn_pairs_last, bool record, hipStream_t s) {
   const Prec pb = base_prec(m.prec);                       // embedding, attention, head, LN outputs
   const bool fp8 = m.prec == P_FP8 && m.calibrated && !record;  // FP8 block products
   const int* H = dyn ? w.d_hdr : nullptr;
@@ -306,11 +307,20 @@ int enqueue_net(const ModelW& m, Workspace& w, int Mg, int Mhg, int nworkg, int 
       q.qscale = 1.4426950408889634f / 8.0f;  // log2(e) / sqrt(64)
       if (fp8) { q.wscale = b.qkv_s; q.xscale = m.act_scale + sq; }
       if ((e = gemm(pg, EPI_QKV, X_DENSE, q, Mreal))) return e;
-      at.heads = heads;
-      at.o_scale = fp8 ? m.act_scale + sp : nullptr;
+      // the last decoder block only needs the queries of the target tubelet:
+      // its other tokens feed nothing after it (the head reads the target rows)
+      const bool last = dec && bi == m.nd - 1;
+      AttnArgs ab = at;
+      ab.heads = heads;
+      ab.o_scale = fp8 ? m.act_scale + sp : nullptr;
+      if (last) {
+        ab.work = w.d_work + w.max_work;
+        ab.nwork = nworkg_last;
+        ab.dyn_nwork = H ? H + HDR_NWORK_LAST : nullptr;
+      }
       {
-        ProfScope ps(w.prof, s, PK_ATTN, 4.0 * 64.0 * heads * attn_pairs);
-        if ((e = launch_attention(fp8 ? P_FP8 : pb, at, s))) return e;
+        ProfScope ps(w.prof, s, PK_ATTN, 4.0 * 64.0 * heads * (last ? attn_pairs_last : attn_pairs));
+        if ((e = launch_attention(fp8 ? P_FP8 : pb, ab, s))) return e;
       }
       if ((e = probe(w.o, D, sp))) return e;
       GemmArgs pr = g;
@@ -371,7 +381,9 @@ int forward(const ModelW& m, Workspace& w, int slot, int nrec, int nall, int com
   int* hdr = w.h_hdr_slot[slot];
   // token and head-row offsets, attention work list
   int M = 0, Mh = 0, nwork = 0, max_pix = 0;
-  double Mreal = 0.0, attn_pairs = 0.0;
+  double Mreal = 0.0, attn_pairs = 0.0, attn_pairs_last = 0.0;
+  int nwork_last = 0;
+  int* work_last = work + w.max_work;
   for (int r = 0; r < nall; ++r) {
     ReqDesc& d = reqs[r];
     d.gy = cdiv(d.H, REVO_PATCH);
@@ -387,19 +399,28 @@ int forward(const ModelW& m, Workspace& w, int slot, int nrec, int nall, int com
       if (nwork >= w.max_work) return -22;
       work[nwork++] = (r << 16) | qt;
     }
+    for (int qt = 0; qt * 128 < d.P; ++qt) {
+      if (nwork_last >= w.max_work) return -22;
+      work_last[nwork_last++] = (r << 16) | ATTN_TARGET_TILE | qt;
+    }
     M += N;
     Mh += d.P;
     Mreal += N;
     attn_pairs += (double)N * N;
+    attn_pairs_last += (double)N * d.P;
   }
   if (M > w.cap) return -22;
   hdr[HDR_M] = M; hdr[HDR_MH] = Mh; hdr[HDR_NREC] = nrec; hdr[HDR_NALL] = nall; hdr[HDR_NWORK] = nwork;
+  hdr[HDR_NWORK_LAST] = nwork_last;
   REVO_HIP_TRY(hipMemcpyAsync(w.d_reqs, reqs, (size_t)nall * sizeof(ReqDesc), hipMemcpyHostToDevice, s));
   REVO_HIP_TRY(hipMemcpyAsync(w.d_hdr, hdr, HDR_N * 4, hipMemcpyHostToDevice, s));
   if (nwork > 0) REVO_HIP_TRY(hipMemcpyAsync(w.d_work, work, (size_t)nwork * 4, hipMemcpyHostToDevice, s));
+  if (nwork_last > 0)
+    REVO_HIP_TRY(hipMemcpyAsync(w.d_work + w.max_work, work_last, (size_t)nwork_last * 4, hipMemcpyHostToDevice, s));
 
   if (!use_graph || w.prof.on || record) {
-    return enqueue_net(m, w, M, Mh, nwork, nrec, nall, max_pix, composite, false, Mreal, Mh, attn_pairs, record, s);
+    return enqueue_net(m, w, M, Mh, nwork, nwork_last, nrec, nall, max_pix, composite, false, Mreal, Mh, attn_pairs,
+                       attn_pairs_last, record, s);
   }
   // smallest capacity bucket holding this batch; capture its graph once
   int b = 0;
@@ -410,8 +431,9 @@ int forward(const ModelW& m, Workspace& w, int slot, int nrec, int nall, int com
     const int capPix = 4096 * 4096;
     hipGraph_t g = nullptr;
     REVO_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
-    int rc = enqueue_net(m, w, capM, capM, capW < w.max_work ? capW : w.max_work, w.max_req, w.max_req, capPix,
-                         composite, true, 0.0, 0.0, 0.0, false, s);
+    const int capWn = capW < w.max_work ? capW : w.max_work;
+    int rc = enqueue_net(m, w, capM, capM, capWn, capWn, w.max_req, w.max_req, capPix, composite, true, 0.0, 0.0, 0.0,
+                         0.0, false, s);
     hipError_t e = hipStreamEndCapture(s, &g);
     if (rc) {
       if (g) (void)hipGraphDestroy(g);

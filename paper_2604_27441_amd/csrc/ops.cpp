@@ -77,7 +77,7 @@ int revo_op_attention(int precision, const void* q, const void* k, const void* v
   if (heads <= 0 || ntok <= 0 || ld < ntok + 64 || !q || !k || !vt || !o) return REVO_EINVAL;
   if (ld % 8) return REVO_EINVAL;  // 16-byte aligned vt rows
   const int ntile = (ntok + 127) / 128;
-  if (ntile > 0xFFFF) return REVO_EINVAL;
+  if (ntile >= ATTN_TARGET_TILE) return REVO_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   // one request covering all tokens; descriptor and work list in device memory
   ReqDesc h;
