@@ -75,7 +75,11 @@ enum revo_completion_status {
 #define REVO_CFG_ONE_STREAM 0x4u /* run the RGB and depth networks one after the other on one stream
                                    (default: two streams that overlap on the GPU) */
 #define REVO_CFG_GRAPHS 0x8u  /* replay each network as a HIP graph captured once per token-capacity
-                                 bucket (cap/8, cap/4, cap/2, cap); ignored with REVO_CFG_PROFILE */
+                                 bucket (cap/8, cap/4, cap/2, cap); ignored with REVO_CFG_PROFILE or
+                                 REVO_CFG_PROFILE_ATTN */
+#define REVO_CFG_PROFILE_ATTN 0x10u /* time only the attention launches and whole network passes
+                                       with HIP events: about 34 events per pass instead of one pair
+                                       per kernel, so the timing barely perturbs throughput */
 
 typedef struct revo_config {
   int device;                 /* HIP device ordinal */

@@ -14,6 +14,7 @@ lib = C.CDLL(LIB_PATH)
 REVO_OK, REVO_EAGAIN = 0, 1
 REVO_DEVICE_PTRS, REVO_HOLD = 0x1, 0x2
 REVO_CFG_SHED, REVO_CFG_PROFILE, REVO_CFG_ONE_STREAM, REVO_CFG_GRAPHS = 0x1, 0x2, 0x4, 0x8
+REVO_CFG_PROFILE_ATTN = 0x10
 REVO_DONE, REVO_SHED, REVO_FAILED = 0, 1, 2
 
 

@@ -50,7 +50,10 @@ class Recoverer:
         cfg.enc_depth, cfg.dec_depth, cfg.composite = enc_depth, dec_depth, composite
         cfg.max_streams, cfg.max_batch, cfg.max_batch_tokens = max_streams, max_batch, max_batch_tokens
         cfg.hbm_budget_bytes, cfg.fps = hbm_budget_bytes, fps
-        cfg.flags = ((_lib.REVO_CFG_SHED if shed else 0) | (_lib.REVO_CFG_PROFILE if profile else 0)
+        # profile: False, True (every kernel) or "attention" (attention launches
+        # and whole passes only, which barely perturbs throughput)
+        prof_flag = _lib.REVO_CFG_PROFILE_ATTN if profile == "attention" else (_lib.REVO_CFG_PROFILE if profile else 0)
+        cfg.flags = ((_lib.REVO_CFG_SHED if shed else 0) | prof_flag
                      | (_lib.REVO_CFG_ONE_STREAM if one_stream else 0) | (_lib.REVO_CFG_GRAPHS if graphs else 0))
         cfg.weights_rgb = self._w[0].ctypes.data_as(C.POINTER(C.c_float))
         cfg.n_weights_rgb = self._w[0].size

@@ -626,8 +626,11 @@ int revo_recover_create(const revo_config* cfg_in, revo_ctx** out) {
     c->cfg.max_batch_tokens = cap;
     if (!rc) rc = workspace_alloc(c->ws[0], c->model[0], cap, cfg.max_batch, c->stream[0]);
     if (!rc) rc = workspace_alloc(c->ws[1], c->model[1], cap, cfg.max_batch, c->stream[1]);
-    if (!rc && (cfg.flags & REVO_CFG_PROFILE))
-      for (int q = 0; q < 2 && !rc; ++q) rc = prof_init(c->ws[q].prof, 1024);
+    if (!rc && (cfg.flags & (REVO_CFG_PROFILE | REVO_CFG_PROFILE_ATTN)))
+      for (int q = 0; q < 2 && !rc; ++q) {
+        rc = prof_init(c->ws[q].prof, 1024);
+        c->ws[q].prof.attn_only = !(cfg.flags & REVO_CFG_PROFILE);
+      }
     fixed += c->ws[0].bytes + c->ws[1].bytes;
     c->pool.fixed = fixed;
     c->pool.budget = cfg.hbm_budget_bytes;
@@ -637,7 +640,8 @@ int revo_recover_create(const revo_config* cfg_in, revo_ctx** out) {
     revo_recover_destroy(c);
     return rc < 0 ? rc : REVO_EDEVICE;
   }
-  c->inflight_max = (cfg.flags & REVO_CFG_PROFILE) ? 1 : WS_SLOTS;  // event records are per workspace
+  // event records are per workspace
+  c->inflight_max = (cfg.flags & (REVO_CFG_PROFILE | REVO_CFG_PROFILE_ATTN)) ? 1 : WS_SLOTS;
   c->use_graphs = (cfg.flags & REVO_CFG_GRAPHS) != 0;
   for (int sl = 0; sl < c->inflight_max; ++sl) c->free_slots.push_back(sl);
   c->worker = std::thread(worker_main, c);

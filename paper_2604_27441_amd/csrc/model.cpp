@@ -150,7 +150,7 @@ struct ProfScope {
   int a = -1, kind;
   double flop;
   ProfScope(Prof& p_, hipStream_t s_, int kind_, double flop_) : p(p_), s(s_), kind(kind_), flop(flop_) {
-    if (p.on && p.used + 2 <= (int)p.pool.size()) {
+    if (p.on && (!p.attn_only || kind == PK_ATTN || kind == PK_FORWARD) && p.used + 2 <= (int)p.pool.size()) {
       a = p.used;
       p.used += 2;
       (void)hipEventRecord(p.pool[a], s);

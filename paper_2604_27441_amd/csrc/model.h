@@ -51,6 +51,7 @@ void model_free(ModelW& m);
 enum ProfKind { PK_ATTN = 0, PK_GEMM = 1, PK_OTHER = 2, PK_FORWARD = 3, PK_N = 4 };
 struct Prof {
   bool on = false;
+  bool attn_only = false;  // only attention launches and whole passes
   std::vector<hipEvent_t> pool;
   struct Rec { int a, b, kind; double flop; };
   std::vector<Rec> recs;
