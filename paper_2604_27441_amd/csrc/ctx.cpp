@@ -440,10 +440,11 @@ void worker_main(revo_ctx* c) {
         }
         bool shed_this = false;
         if (shed && ju > 0.0) {
-          // plan with a safety margin: 2 ms plus 10 % of the estimate
+          // plan with a safety margin: 3 ms (completion hand-off and output
+          // copies after the GPU span) plus 10 % of the estimate
           auto late = [&](double units, double deadline) {
             const double est = spu * units;
-            return start + 1.1 * est + 2.0e6 > deadline;
+            return start + 1.1 * est + 3.0e6 > deadline;
           };
           if (late(ju, (double)j->deadline)) shed_this = true;
           else if (!batch.empty() && late(batch_units + ju, std::min(min_deadline, (double)j->deadline))) break;
