@@ -270,3 +270,76 @@ def test_fp8_form_against_rounding_oracle():
     assert e["rgb_psnr"] >= b["rgb_psnr"] - 3.02, (e, b)
     assert e["depth_rms_lost"] <= np.sqrt(2.0) * b["depth_rms_lost"], (e, b)
     assert e["depth_maxabs"] <= 4.0 * b["depth_maxabs"], (e, b)
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+def test_mask_without_lost_pixels_returns_the_input(prec):
+    """A frame that goes through recovery but lost nothing comes back as it
+    arrived, byte for byte (every pixel is a received pixel)."""
+    req = synth.make_request(91, 92, 40, 56, loss=("none", 0))
+    assert not req["mask_rgb"].any() and not req["mask_depth"].any()
+    out, _ = _small(prec, req)
+    assert out["completion"].status == 0
+    check_received_and_codes(req, out)
+    assert np.array_equal(out["rgb"], req["rgb"]) and np.array_equal(out["depth"], req["depth"])
+
+
+def test_everything_lost_fp32():
+    """A frame with every slice lost: the network sees the references and an
+    all-zero target, and every output pixel is the clamped prediction."""
+    req = synth.make_request(93, 94, 40, 56, loss=("all", 0))
+    assert req["mask_rgb"].all() and req["mask_depth"].all()
+    out, ref = _small(FP32, req)
+    check_received_and_codes(req, out)
+    e = compare(req, out, ref)
+    assert e["rgb_maxabs"] <= 1e-4 and e["depth_maxabs"] <= 0.5, e
+
+
+def test_modalities_keep_separate_rings():
+    """RGB lost while the depth of the same frame arrived intact: the RGB is
+    recovered, the depth is copied and becomes the newest depth reference.
+    The next frame's depth recovery then uses it, while the RGB references
+    stay as they were (Sec. 3.4.2: separate models and losses per modality)."""
+    import torch
+    from tests.gpu_util import dev
+    blobs = synth.make_weights(3, perturb_seed=4, **SMALL)
+    H, W = 40, 56
+    req = synth.make_request(95, 98, H, W, loss=("stripes", 0.5))
+    nxt = synth.make_request(95, 97, H, W, t_target=req["t_target"] + 1, loss=("stripes", 0.5))
+    assert req["mask_rgb"].any() and nxt["mask_depth"].any()
+
+    def outs():
+        return dict(rgb=torch.zeros((H, W, 3), dtype=torch.uint8, device="cuda"),
+                    depth=torch.zeros((H, W), dtype=torch.int16, device="cuda"),
+                    rgb_f=torch.zeros((H, W, 3), dtype=torch.float32, device="cuda"),
+                    depth_f=torch.zeros((H, W), dtype=torch.float32, device="cuda"))
+
+    def run(rec, r, rgb_lost):
+        o = outs()
+        ins = [dev(r["rgb"]), dev(r["mask_rgb"]), dev(r["depth"]), dev(r["mask_depth"])]
+        t = rec.submit(0, int(r["t_target"]), W, H, rgb=ins[0], mask_rgb=ins[1] if rgb_lost else None,
+                       depth=ins[2], mask_depth=None if rgb_lost else ins[3], rgb_out=o["rgb"], depth_out=o["depth"],
+                       rgb_out_f32=o["rgb_f"], depth_out_f32=o["depth_f"], device_ptrs=True)
+        c = rec.wait([t])[t]
+        assert c.status == 0, c
+        got = {k: v.cpu().numpy() for k, v in o.items()}
+        got["depth"] = got["depth"].view(np.uint16)
+        return got
+
+    with _rec(blobs, FP32, **SMALL) as rec:
+        push_refs(rec, 0, req)
+        a = run(rec, req, rgb_lost=True)
+        b = run(rec, nxt, rgb_lost=False)
+    ra = oracle.recover(req, blobs, modalities=("rgb",), **SMALL)["rgb"]
+    assert np.abs(a["rgb_f"] - ra[1]).max() <= 1e-4
+    assert np.array_equal(a["depth"], req["depth"])                      # copied as received
+    r2 = dict(nxt)
+    r2["depth_refs"] = list(req["depth_refs"][1:]) + [req["depth"]]        # newest depth reference
+    r2["ref_idx"] = list(req["ref_idx"][1:]) + [req["t_target"]]
+    rb = oracle.recover(r2, blobs, modalities=("depth",), **SMALL)["depth"]
+    assert np.abs(b["depth_f"] - rb[1]).max() <= 0.5
+    assert np.array_equal(b["rgb"], nxt["rgb"])
+    # the same depth with the old references differs: the ring really moved
+    r_old = oracle.recover(nxt, blobs, modalities=("depth",), **SMALL)["depth"]
+    lost = nxt["mask_depth"] != 0
+    assert np.abs(r_old[1] - rb[1])[lost].max() > 1.0
