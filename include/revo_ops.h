@@ -39,7 +39,7 @@ int revo_op_linear(int precision, int epilogue, const void *x, const void *w, co
 int revo_op_linear_fp8(int epilogue, const void *x8, const void *w8, const float *wscale, const float *xscale,
                        const float *bias, void *out, const float *out_scale, int M, int N, int K, void *stream);
 
-/* LayerNorm over rows of D <= 512 floats: y = (x - mean) / sqrt(var + 1e-6)
+/* LayerNorm over rows of D <= 512 floats, D even: y = (x - mean) / sqrt(var + 1e-6)
  * * g + b with the biased variance; y in the operand type. */
 int revo_op_layernorm(int precision, const float *x, const float *g, const float *b, void *y,
                       int rows, int D, void *stream);

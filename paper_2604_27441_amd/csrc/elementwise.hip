@@ -5,7 +5,7 @@ namespace revo {
 
 namespace {
 
-// One wave per row: FP32 mean and biased variance over D features (D <= 512),
+// One wave per row: FP32 mean and biased variance over D features (D <= 512, even),
 // then (x - mean) / sqrt(var + 1e-6) * g + b, stored as the next product's
 // operand type.  With reqs set, output row i is request r's target-tubelet
 // token i - head_off (rows of the last tubelet only, for the head).
@@ -25,33 +25,48 @@ __global__ __launch_bounds__(256) void layernorm_kernel(const float* __restrict_
     const ReqDesc& d = reqs[r];
     src = d.tok_off + (d.J - 1) * d.P + (row - d.head_off);
   }
-  const float* xr = x + (size_t)src * D;
-  float v[8];
+  // float2 chunks (D is even): 512-byte loads per wave instruction
+  const float2* xr = reinterpret_cast<const float2*>(x + (size_t)src * D);
+  const int D2 = D >> 1;
+  float2 v[4];
   float s = 0.0f;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < 4; ++i) {
     const int c = lane + 64 * i;
-    v[i] = c < D ? xr[c] : 0.0f;
-    s += v[i];
+    v[i] = c < D2 ? xr[c] : make_float2(0.0f, 0.0f);
+    s += v[i].x + v[i].y;
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
   const float mean = s / (float)D;
   float q = 0.0f;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < 4; ++i) {
     const int c = lane + 64 * i;
-    const float t = c < D ? v[i] - mean : 0.0f;
-    q += t * t;
+    if (c < D2) {
+      const float t0 = v[i].x - mean, t1 = v[i].y - mean;
+      q += t0 * t0 + t1 * t1;
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o);
   const float rstd = 1.0f / sqrtf(q / (float)D + 1e-6f);
   T* yr = y + (size_t)row * D;
+  const float2* g2 = reinterpret_cast<const float2*>(g);
+  const float2* b2 = reinterpret_cast<const float2*>(b);
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < 4; ++i) {
     const int c = lane + 64 * i;
-    if (c < D) yr[c] = (T)((v[i] - mean) * rstd * g[c] + b[c]);
+    if (c < D2) {
+      const float2 gg = g2[c], bb = b2[c];
+      const float y0 = (v[i].x - mean) * rstd * gg.x + bb.x;
+      const float y1 = (v[i].y - mean) * rstd * gg.y + bb.y;
+      if constexpr (sizeof(T) == 2) {
+        *reinterpret_cast<bf16x2*>(yr + 2 * c) = bf16x2{(__bf16)y0, (__bf16)y1};
+      } else {
+        *reinterpret_cast<float2*>(yr + 2 * c) = make_float2(y0, y1);
+      }
+    }
   }
 }
 
@@ -208,7 +223,7 @@ __global__ void zero_tail_kernel(uint8_t* __restrict__ p, long long n) {
 int launch_layernorm(Prec out_prec, const float* x, const float* g, const float* b, void* y, int rows, int D,
                      const ReqDesc* reqs, int nreq, hipStream_t s, const int* dyn_rows, const int* dyn_nreq) {
   if (rows <= 0) return 0;
-  if (D > 512) return -22;
+  if (D > 512 || (D & 1)) return -22;
   dim3 grid(cdiv(rows, 4));
   if (out_prec == P_BF16)
     layernorm_kernel<__bf16><<<grid, 256, 0, s>>>(x, g, b, (__bf16*)y, rows, D, reqs, nreq, dyn_rows, dyn_nreq);
