@@ -623,6 +623,7 @@ int revo_recover_create(const revo_config* cfg_in, revo_ctx** out) {
         cap = avail > 0 ? (int)std::min(avail / per_tok, 1.0e6) : 0;
       }
     }
+    cap &= ~7;  // requests start on 8-row boundaries; V^T rows stay 16-byte aligned
     if (cap < 64) rc = REVO_ENOMEM;
     c->cfg.max_batch_tokens = cap;
     if (!rc) rc = workspace_alloc(c->ws[0], c->model[0], cap, cfg.max_batch, c->stream[0]);

@@ -200,6 +200,218 @@ __global__ void tubelet_pack_kernel(const ReqDesc* __restrict__ reqs, int nreq_,
   }
 }
 
+// Epilogue of one 128 x BN tile straight from the accumulators (the head's
+// unpatchify scatter), for the tile's rows below Mlive.
+template <class Op, int BN, int EPI, class OutT>
+__device__ __forceinline__ void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[BN / 64][2], int m0, int n0,
+                                              int Mlive, int nreq, int lane, int wave) {
+  constexpr int NSUB = BN / 64;
+  const int half = lane >> 5, l32 = lane & 31;
+  const int wn = wave >> 1, wm = wave & 1;
+  const float xsc = a.xscale ? *a.xscale : 1.0f;
+  const float oinv = a.out_scale ? 1.0f / *a.out_scale : 1.0f;
+#pragma unroll
+  for (int ms = 0; ms < 2; ++ms) {
+    const int m = m0 + wm * 64 + ms * 32 + l32;
+    if (m >= Mlive) continue;
+    int r = 0, tj = 0, ty = 0, tx = 0;
+    if (EPI == EPI_PE) {
+      r = find_req_tok(a.reqs, nreq, m);
+      const ReqDesc& d = a.reqs[r];
+      const int t = m - d.tok_off;
+      tj = t / d.P;
+      const int p = t - tj * d.P;
+      ty = p / d.gx; tx = p - ty * d.gx;
+    } else if (EPI == EPI_HEAD) {
+      r = find_req_head(a.reqs, nreq, m);
+      const ReqDesc& d = a.reqs[r];
+      const int p = m - d.head_off;
+      ty = p / d.gx; tx = p - ty * d.gx;
+    }
+#pragma unroll
+    for (int ns = 0; ns < NSUB; ++ns) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int n = n0 + wn * (BN / 2) + ns * 32 + g * 8 + half * 4;
+        float v[4];
+        if (a.wscale) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = acc[ns][ms][4 * g + e] * (a.wscale[n + e] * xsc) + a.bias[n + e];
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = acc[ns][ms][4 * g + e] + a.bias[n + e];
+        }
+        if (EPI == EPI_STORE) {
+          Vec4<OutT>::store((OutT*)a.out + (size_t)m * a.ldo + n, v, oinv);
+        } else if (EPI == EPI_GELU) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = gelu_erf(v[e]);
+          Vec4<OutT>::store((OutT*)a.out + (size_t)m * a.ldo + n, v, oinv);
+        } else if (EPI == EPI_RESIDUAL) {
+          float* p = (float*)a.out + (size_t)m * a.ldo + n;
+          f32x4 old = *reinterpret_cast<f32x4*>(p);
+          *reinterpret_cast<f32x4*>(p) = f32x4{old[0] + v[0], old[1] + v[1], old[2] + v[2], old[3] + v[3]};
+        } else if (EPI == EPI_PE) {
+          const ReqDesc& d = a.reqs[r];
+          const int d3 = a.N / 3;
+          const int axis = n / d3;
+          const float s = axis == 0 ? (tj < d.J ? d.tau[tj] : 0.0f) : axis == 1 ? (float)ty : (float)tx;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] += pe_value(s, n + e, d3);
+          float* p = (float*)a.out + (size_t)m * a.ldo + n;
+          *reinterpret_cast<f32x4*>(p) = f32x4{v[0], v[1], v[2], v[3]};
+        } else if (EPI == EPI_QKV) {
+          const int D = a.heads * 64;
+          const int part = n / D, hd = (n % D) >> 6, dd = n & 63;
+          if (part == 0) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] *= a.qscale;
+            Vec4<OutT>::store((OutT*)a.q + ((size_t)hd * a.ldqk + m) * 64 + dd, v, 1.0f);
+          } else if (part == 1) {
+            Vec4<OutT>::store((OutT*)a.k + ((size_t)hd * a.ldqk + m) * 64 + dd, v, 1.0f);
+          } else {
+            OutT* vt = (OutT*)a.vt + ((size_t)hd * 64 + dd) * a.ldv + m;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) vt[(size_t)e * a.ldv] = out_cast<OutT>(v[e], 1.0f);
+          }
+        } else if (EPI == EPI_HEAD) {
+          const ReqDesc& d = a.reqs[r];
+          const int C = a.channels;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int c = n + e;
+            const int py = c / (16 * C);
+            const int px = (c / C) & 15;
+            const int ch = c - (c / C) * C;
+            const int Y = 16 * ty + py, Xp = 16 * tx + px;
+            if (Y < d.H && Xp < d.W) d.pred[((size_t)Y * d.W + Xp) * C + ch] = v[e];
+          }
+        }
+      }
+    }
+  }
+}
+
+// LDS bytes of the staged epilogue: a row-major [BM][BN] tile of the output
+// type, or for the V part of the QKV product a transposed [BN][BM] tile
+// (rows padded by 16 bytes).
+template <int BN, class OutT>
+constexpr int epi_stage_bytes() {
+  return BM * (BN * (int)sizeof(OutT) + 16) > BN * (BM * (int)sizeof(OutT) + 16) ? BM * (BN * (int)sizeof(OutT) + 16)
+                                                                                  : BN * (BM * (int)sizeof(OutT) + 16);
+}
+
+// Epilogue through LDS: the accumulators (lane = token, runs of four
+// features) go into a tile after the scale / bias / fused step, and the
+// workgroup then writes whole output rows in 16-byte chunks, so every store
+// instruction covers contiguous row segments instead of one short piece per
+// token.  The V part of the QKV product is staged transposed and written as
+// contiguous token runs of V^T.  smem must hold epi_stage_bytes<BN, OutT>().
+template <class Op, int BN, int EPI, class OutT>
+__device__ __forceinline__ void gemm_epilogue_staged(const GemmArgs& a, f32x16 (&acc)[BN / 64][2], int m0, int n0,
+                                                     int Mlive, int nreq, int tid, uint8_t* smem) {
+  constexpr int NSUB = BN / 64;
+  constexpr int TPB = BN * (int)sizeof(OutT) + 16;  // row pitch (bytes), row-major tile
+  constexpr int TPV = BM * (int)sizeof(OutT) + 16;  // row pitch (bytes), transposed V tile
+  constexpr int EO = 16 / (int)sizeof(OutT);         // output elements per 16-byte chunk
+  const int lane = tid & 63, wave = tid >> 6;
+  const int half = lane >> 5, l32 = lane & 31;
+  const int wn = wave >> 1, wm = wave & 1;
+  const float xsc = a.xscale ? *a.xscale : 1.0f;
+  const float oinv = a.out_scale ? 1.0f / *a.out_scale : 1.0f;
+  const int D = EPI == EPI_QKV ? a.heads * 64 : 1;
+  const int part = EPI == EPI_QKV ? n0 / D : 0;  // tiles never straddle Q | K | V
+  const bool vtile = EPI == EPI_QKV && part == 2;
+  __syncthreads();  // every wave is done with the operand tiles
+#pragma unroll
+  for (int ms = 0; ms < 2; ++ms) {
+    const int ml = wm * 64 + ms * 32 + l32;
+    const int m = m0 + ml;
+    int r = 0, tj = 0, ty = 0, tx = 0;
+    if (EPI == EPI_PE) {
+      r = find_req_tok(a.reqs, nreq, m);
+      const ReqDesc& d = a.reqs[r];
+      const int t = m - d.tok_off;
+      tj = t / d.P;
+      const int p = t - tj * d.P;
+      ty = p / d.gx; tx = p - ty * d.gx;
+    }
+#pragma unroll
+    for (int ns = 0; ns < NSUB; ++ns) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int nl = wn * (BN / 2) + ns * 32 + g * 8 + half * 4;
+        const int n = n0 + nl;
+        float v[4];
+        if (a.wscale) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = acc[ns][ms][4 * g + e] * (a.wscale[n + e] * xsc) + a.bias[n + e];
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = acc[ns][ms][4 * g + e] + a.bias[n + e];
+        }
+        if (EPI == EPI_GELU) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = gelu_erf(v[e]);
+        } else if (EPI == EPI_PE) {
+          const ReqDesc& d = a.reqs[r];
+          const int d3 = a.N / 3;
+          const int axis = n / d3;
+          const float s = axis == 0 ? (tj < d.J ? d.tau[tj] : 0.0f) : axis == 1 ? (float)ty : (float)tx;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] += pe_value(s, n + e, d3);
+        } else if (EPI == EPI_QKV && part == 0) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] *= a.qscale;
+        }
+        if (vtile) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) reinterpret_cast<OutT*>(smem + (nl + e) * TPV)[ml] = out_cast<OutT>(v[e], 1.0f);
+        } else {
+          Vec4<OutT>::store(reinterpret_cast<OutT*>(smem + ml * TPB) + nl, v, oinv);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (vtile) {
+    // V^T rows: EO consecutive tokens per 16-byte chunk
+    for (int i = tid; i < BN * (BM / EO); i += NT) {
+      const int nl = i / (BM / EO), c = (i - nl * (BM / EO)) * EO;
+      const int m = m0 + c;
+      if (m >= Mlive) continue;
+      const int n = n0 + nl;
+      const int hd = (n - 2 * D) >> 6, dd = n & 63;
+      OutT* dst = (OutT*)a.vt + ((size_t)hd * 64 + dd) * a.ldv + m;
+      const OutT* src = reinterpret_cast<const OutT*>(smem + nl * TPV) + c;
+      if (m + EO <= Mlive) {
+        *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(src);
+      } else {
+        for (int e = 0; m + e < Mlive; ++e) dst[e] = src[e];
+      }
+    }
+    return;
+  }
+  constexpr int CPRO = BN / EO;
+  for (int i = tid; i < BM * CPRO; i += NT) {
+    const int rl = i / CPRO, c = (i - rl * CPRO) * EO;
+    const int m = m0 + rl;
+    if (m >= Mlive) continue;
+    const int n = n0 + c;
+    const uint4 val = *reinterpret_cast<const uint4*>(smem + rl * TPB + c * (int)sizeof(OutT));
+    if (EPI == EPI_RESIDUAL) {
+      f32x4* p = reinterpret_cast<f32x4*>((float*)a.out + (size_t)m * a.ldo + n);
+      *p = *p + __builtin_bit_cast(f32x4, val);
+    } else if (EPI == EPI_QKV) {
+      const int hd = (n - part * D) >> 6, dd = n & 63;
+      OutT* dst = (OutT*)(part == 0 ? a.q : a.k) + ((size_t)hd * a.ldqk + m) * 64 + dd;
+      *reinterpret_cast<uint4*>(dst) = val;
+    } else {
+      *reinterpret_cast<uint4*>((OutT*)a.out + (size_t)m * a.ldo + n) = val;
+    }
+  }
+}
+
 template <class Op, int BN, int EPI, int XM, class OutT>
 __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
   typedef typename Op::T T;
@@ -213,8 +425,12 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
   constexpr int FB = Op::KPL * sizeof(T);          // operand bytes per lane per MFMA step
   constexpr int G = FB >= 16 ? 1 : 16 / FB;        // MFMA steps per 16-byte LDS read
   constexpr int STEPS = BK / (2 * Op::KPL);
-  __shared__ __attribute__((aligned(16))) T xs[2][BM * PITCH];
-  __shared__ __attribute__((aligned(16))) T ws[2][BN * PITCH];
+  // operand stages, reused by the staged epilogue once the K loop is done
+  constexpr int OPB = (2 * BM * PITCH + 2 * BN * PITCH) * (int)sizeof(T);
+  constexpr int EPB = EPI == EPI_HEAD ? 0 : epi_stage_bytes<BN, OutT>();
+  __shared__ __attribute__((aligned(16))) uint8_t smem[OPB > EPB ? OPB : EPB];
+  T(*xs)[BM * PITCH] = reinterpret_cast<T(*)[BM * PITCH]>(smem);
+  T(*ws)[BN * PITCH] = reinterpret_cast<T(*)[BN * PITCH]>(smem + 2 * BM * PITCH * sizeof(T));
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
@@ -368,89 +584,10 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
 #undef REVO_GEMM_STORE
 #undef REVO_GEMM_COMPUTE
 
-  // ---------------------------------------------------------------- epilogue
-  const float xsc = a.xscale ? *a.xscale : 1.0f;
-  const float oinv = a.out_scale ? 1.0f / *a.out_scale : 1.0f;
-#pragma unroll
-  for (int ms = 0; ms < 2; ++ms) {
-    const int m = m0 + wm * 64 + ms * 32 + l32;
-    if (m >= Mlive) continue;
-    int r = 0, tj = 0, ty = 0, tx = 0;
-    if (EPI == EPI_PE) {
-      r = find_req_tok(a.reqs, nreq, m);
-      const ReqDesc& d = a.reqs[r];
-      const int t = m - d.tok_off;
-      tj = t / d.P;
-      const int p = t - tj * d.P;
-      ty = p / d.gx; tx = p - ty * d.gx;
-    } else if (EPI == EPI_HEAD) {
-      r = find_req_head(a.reqs, nreq, m);
-      const ReqDesc& d = a.reqs[r];
-      const int p = m - d.head_off;
-      ty = p / d.gx; tx = p - ty * d.gx;
-    }
-#pragma unroll
-    for (int ns = 0; ns < NSUB; ++ns) {
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int n = n0 + wn * (BN / 2) + ns * 32 + g * 8 + half * 4;
-        float v[4];
-        if (a.wscale) {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = acc[ns][ms][4 * g + e] * (a.wscale[n + e] * xsc) + a.bias[n + e];
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = acc[ns][ms][4 * g + e] + a.bias[n + e];
-        }
-        if (EPI == EPI_STORE) {
-          Vec4<OutT>::store((OutT*)a.out + (size_t)m * a.ldo + n, v, oinv);
-        } else if (EPI == EPI_GELU) {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = gelu_erf(v[e]);
-          Vec4<OutT>::store((OutT*)a.out + (size_t)m * a.ldo + n, v, oinv);
-        } else if (EPI == EPI_RESIDUAL) {
-          float* p = (float*)a.out + (size_t)m * a.ldo + n;
-          f32x4 old = *reinterpret_cast<f32x4*>(p);
-          *reinterpret_cast<f32x4*>(p) = f32x4{old[0] + v[0], old[1] + v[1], old[2] + v[2], old[3] + v[3]};
-        } else if (EPI == EPI_PE) {
-          const ReqDesc& d = a.reqs[r];
-          const int d3 = a.N / 3;
-          const int axis = n / d3;
-          const float s = axis == 0 ? (tj < d.J ? d.tau[tj] : 0.0f) : axis == 1 ? (float)ty : (float)tx;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] += pe_value(s, n + e, d3);
-          float* p = (float*)a.out + (size_t)m * a.ldo + n;
-          *reinterpret_cast<f32x4*>(p) = f32x4{v[0], v[1], v[2], v[3]};
-        } else if (EPI == EPI_QKV) {
-          const int D = a.heads * 64;
-          const int part = n / D, hd = (n % D) >> 6, dd = n & 63;
-          if (part == 0) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] *= a.qscale;
-            Vec4<OutT>::store((OutT*)a.q + ((size_t)hd * a.ldqk + m) * 64 + dd, v, 1.0f);
-          } else if (part == 1) {
-            Vec4<OutT>::store((OutT*)a.k + ((size_t)hd * a.ldqk + m) * 64 + dd, v, 1.0f);
-          } else {
-            OutT* vt = (OutT*)a.vt + ((size_t)hd * 64 + dd) * a.ldv + m;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) vt[(size_t)e * a.ldv] = out_cast<OutT>(v[e], 1.0f);
-          }
-        } else if (EPI == EPI_HEAD) {
-          const ReqDesc& d = a.reqs[r];
-          const int C = a.channels;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int c = n + e;
-            const int py = c / (16 * C);
-            const int px = (c / C) & 15;
-            const int ch = c - (c / C) * C;
-            const int Y = 16 * ty + py, Xp = 16 * tx + px;
-            if (Y < d.H && Xp < d.W) d.pred[((size_t)Y * d.W + Xp) * C + ch] = v[e];
-          }
-        }
-      }
-    }
-  }
+  if constexpr (EPI == EPI_HEAD)
+    gemm_epilogue<Op, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, lane, wave);
+  else
+    gemm_epilogue_staged<Op, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, tid, smem);
 }
 
 template <class Op, int EPI, int XM, class OutT>
