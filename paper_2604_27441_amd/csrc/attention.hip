@@ -340,37 +340,61 @@ __global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 3 : 2) void attn_
 #undef REVO_ATTN_STORE1
 #undef REVO_ATTN_STORE
 
+  // The output goes through LDS (the K stages are free once every wave is
+  // past its last block) so that whole 64-dim query rows are written in
+  // 16-byte chunks rather than one short piece per query row.
   const float l_tot = xhalf_sum(l_run);
-  if (q_local < N && a.o_scale) {
+  const int ql = wave * 32 + (lane & 31);  // this lane's query within the tile
+  uint8_t* st = reinterpret_cast<uint8_t*>(&ks[0][0]);
+  __syncthreads();
+  if (a.o_scale) {
     // FP8 output for an FP8 output projection
+    constexpr int RB = 64 + 16;  // bytes per staged row
     const float inv = 1.0f / (l_tot * *a.o_scale);
-    uint8_t* op = (uint8_t*)a.o + (size_t)q * (a.heads * 64) + hd * 64;
 #pragma unroll
     for (int ds = 0; ds < 2; ++ds)
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
         const int dim = ds * 32 + g * 8 + half * 4;
-        *reinterpret_cast<uint32_t*>(op + dim) = e4m3x4(oacc[ds][4 * g] * inv, oacc[ds][4 * g + 1] * inv,
-                                                         oacc[ds][4 * g + 2] * inv, oacc[ds][4 * g + 3] * inv);
+        *reinterpret_cast<uint32_t*>(st + ql * RB + dim) = e4m3x4(oacc[ds][4 * g] * inv, oacc[ds][4 * g + 1] * inv,
+                                                                  oacc[ds][4 * g + 2] * inv, oacc[ds][4 * g + 3] * inv);
       }
-  } else if (q_local < N) {
+    __syncthreads();
+    for (int i = tid; i < QT * 4; i += NT) {
+      const int row = i >> 2, c = (i & 3) * 16;
+      const int qr = q0 + qt * QT + row;
+      if (qr < N)
+        *reinterpret_cast<uint4*>((uint8_t*)a.o + (size_t)(base + qr) * (a.heads * 64) + hd * 64 + c) =
+            *reinterpret_cast<const uint4*>(st + row * RB + c);
+    }
+  } else {
+    constexpr int RB = 64 * (int)sizeof(T) + 16;
+    constexpr int EC = 16 / (int)sizeof(T);  // elements per 16-byte chunk
+    static_assert(QT * RB <= (int)sizeof(ks), "output tile fits the K stages");
     const float inv = 1.0f / l_tot;
-    T* op = (T*)a.o + (size_t)q * (a.heads * 64) + hd * 64;
 #pragma unroll
     for (int ds = 0; ds < 2; ++ds)
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
         const int dim = ds * 32 + g * 8 + half * 4;
+        T* sp = reinterpret_cast<T*>(st + ql * RB) + dim;
         if constexpr (sizeof(T) == 2) {
-          *reinterpret_cast<bf16x4*>(op + dim) =
+          *reinterpret_cast<bf16x4*>(sp) =
               bf16x4{(__bf16)(oacc[ds][4 * g] * inv), (__bf16)(oacc[ds][4 * g + 1] * inv),
                      (__bf16)(oacc[ds][4 * g + 2] * inv), (__bf16)(oacc[ds][4 * g + 3] * inv)};
         } else {
-          *reinterpret_cast<f32x4*>(op + dim) =
-              f32x4{oacc[ds][4 * g] * inv, oacc[ds][4 * g + 1] * inv, oacc[ds][4 * g + 2] * inv,
-                    oacc[ds][4 * g + 3] * inv};
+          *reinterpret_cast<f32x4*>(sp) = f32x4{oacc[ds][4 * g] * inv, oacc[ds][4 * g + 1] * inv,
+                                                oacc[ds][4 * g + 2] * inv, oacc[ds][4 * g + 3] * inv};
         }
       }
+    __syncthreads();
+    for (int i = tid; i < QT * (64 / EC); i += NT) {
+      const int row = i / (64 / EC), c = (i - row * (64 / EC)) * EC;
+      const int qr = q0 + qt * QT + row;
+      if (qr < N)
+        *reinterpret_cast<uint4*>((T*)a.o + (size_t)(base + qr) * (a.heads * 64) + hd * 64 + c) =
+            *reinterpret_cast<const uint4*>(st + row * RB + c * (int)sizeof(T));
+    }
   }
 }
 
