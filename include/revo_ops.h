@@ -48,9 +48,12 @@ int revo_op_layernorm(int precision, const float *x, const float *g, const float
  * `heads` heads of 64 (the attention inside each Transformer block,
  * App. B.1): o[t][h*64 + d] = sum_j softmax_j(q_h[t] . k_h[j] / 8) v_h[j][d].
  * Layouts (operand type): q and k [heads][ld][64] with q already
- * multiplied by log2(e) / 8; vt [heads][64][ld] (V transposed);
- * o [ntok][heads * 64].  ld >= ntok + 64 and rows ntok .. ld-1 of q, k
- * and columns ntok .. ld-1 of vt must hold finite values (zeros). */
+ * multiplied by log2(e) / 8; vt [heads][64][ld] (V transposed), where for
+ * REVO_BF16 column c holds token c with bits 2 and 3 of c swapped
+ * (c ^ ((c ^ (c >> 1)) & 4) * 3, a permutation inside each group of 16);
+ * o [ntok][heads * 64].  ld >= ntok + 64, ld % 16 == 0, and rows ntok ..
+ * ld-1 of q, k and columns ntok .. ld-1 of vt must hold finite values
+ * (zeros). */
 int revo_op_attention(int precision, const void *q, const void *k, const void *vt, void *o,
                       int heads, int ntok, int ld, void *stream);
 

@@ -20,9 +20,11 @@
 // accumulate onto a register block holding -max, so they come out already
 // shifted and the softmax is a bare exp2 per score.  Only the last key
 // block of a request checks key bounds.
-// K and V^T blocks of 64 keys are double-buffered in LDS; they come in
-// through buffer loads with scalar per-block offsets, and the block loop
-// runs two blocks per trip so both LDS buffers have fixed addresses.
+// K and V^T blocks of 64 keys are double-buffered in LDS.  BF16 blocks go
+// from HBM straight into LDS (buffer loads with an LDS destination, no
+// registers in between) with swizzled, unpadded rows; FP32 blocks pass
+// through registers.  Loads take scalar per-block offsets, and the block
+// loop runs two blocks per trip so both LDS buffers have fixed addresses.
 #include "kernels.h"
 
 namespace revo {
@@ -48,11 +50,18 @@ __device__ __forceinline__ float xhalf_sum(float x) {
 template <class T>
 struct AttnTile {
   static constexpr int E = 16 / sizeof(T);   // elements per 16-byte chunk
-  static constexpr int PITCH = 64 + E;       // padded LDS row pitch (elements)
+  // BF16 tiles arrive by DMA (whole 128-byte rows, unpadded, chunks
+  // swizzled); FP32 rows are padded by one chunk
+  static constexpr int PITCH = sizeof(T) == 2 ? 64 : 64 + E;  // LDS row pitch (elements)
   static constexpr int CPR = 64 / E;         // 16-byte chunks per 64-element row
-  static constexpr int LC = KB * CPR / NT;   // chunks per thread per tile
+  static constexpr int LC = KB * CPR / NT;   // chunks per thread per tile (FP32)
   static constexpr int QCH = 32 / E;         // Q chunks per lane
 };
+
+// BF16 K and V^T tiles: row r (a key of K, a dimension of V^T) holds its
+// eight 16-byte chunks with chunk c at slot c ^ ((r >> 1) & 7), so the 16
+// rows read by one 16-lane phase of a b128 read cover all 64 banks.
+__device__ __forceinline__ int swz(int row, int chunk) { return row * 64 + ((chunk ^ ((row >> 1) & 7)) << 3); }
 
 // One 64-key block for one wave: scores, online softmax, P V accumulation.
 template <class Op, bool MASK, bool FIRST>
@@ -79,7 +88,9 @@ __device__ __forceinline__ void attn_block(const typename Op::T* __restrict__ kt
   for (int kc = 0; kc < A::QCH; ++kc) {
 #pragma unroll
     for (int st = 0; st < 2; ++st) {
-      const uint4 kf = *reinterpret_cast<const uint4*>(kt + (st * 32 + l32) * A::PITCH + half * 32 + kc * A::E);
+      const uint4 kf = sizeof(T) == 2
+                           ? *reinterpret_cast<const uint4*>(kt + swz(st * 32 + l32, half * 4 + kc))
+                           : *reinterpret_cast<const uint4*>(kt + (st * 32 + l32) * A::PITCH + half * 32 + kc * A::E);
       if constexpr (sizeof(T) == 2) {
         Op::mma(sacc[st], __builtin_bit_cast(bf16x8, kf), __builtin_bit_cast(bf16x8, qf[kc]));
       } else {
@@ -174,7 +185,7 @@ __device__ __forceinline__ void attn_block(const typename Op::T* __restrict__ kt
         const int pos = st * 32 + g * 16 + half * 8;
 #pragma unroll
         for (int ds = 0; ds < 2; ++ds) {
-          const uint4 vv = *reinterpret_cast<const uint4*>(vt + (ds * 32 + l32) * A::PITCH + pos);
+          const uint4 vv = *reinterpret_cast<const uint4*>(vt + swz(ds * 32 + l32, pos >> 3));
           Op::mma(oacc[ds], __builtin_bit_cast(bf16x8, vv), pf);
         }
       }
@@ -216,8 +227,10 @@ template <class Op>
 __global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 3 : 2) void attn_kernel(const AttnArgs a) {
   typedef typename Op::T T;
   typedef AttnTile<T> A;
-  __shared__ __attribute__((aligned(16))) T ks[2][KB * A::PITCH];   // [key][dim]
-  __shared__ __attribute__((aligned(16))) T vs[2][64 * A::PITCH];   // [dim][key]
+  // two K stages [key][dim] then two V^T stages [dim][key]
+  __shared__ __attribute__((aligned(16))) T kv[4][KB * A::PITCH];
+  T(*ks)[KB * A::PITCH] = kv;
+  T(*vs)[KB * A::PITCH] = kv + 2;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5;
@@ -253,52 +266,76 @@ __global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 3 : 2) void attn_
     for (int i = 0; i < A::QCH; ++i) qf[i] = reinterpret_cast<const uint4*>(qp)[i];
   }
 
-  // per-thread chunk coordinates of a K / V^T tile: chunk i of a thread is
-  // tile element (row c_row + i * R, column c_col), R = NT / CPR rows apart
-  constexpr int R = NT / A::CPR;
-  const int c_row = tid / A::CPR;
-  const int c_col = (tid % A::CPR) * A::E;
-  static_assert(A::LC == 2 || A::LC == 4, "2 or 4 chunks per thread");
-  uint4 kr0, kr1, kr2, kr3, vr0, vr1, vr2, vr3;
   const __amdgpu_buffer_rsrc_t krs =
       __builtin_amdgcn_make_buffer_rsrc((void*)Kg, (short)0, (a.ldqk - base) * 64 * (int)sizeof(T), 0x00020000);
   const __amdgpu_buffer_rsrc_t vrs =
       __builtin_amdgcn_make_buffer_rsrc((void*)Vg, (short)0, (64 * a.ldv - base) * (int)sizeof(T), 0x00020000);
-  const int kvo = (c_row * 64 + c_col) * (int)sizeof(T);
-  const int vvo = (c_row * a.ldv + c_col) * (int)sizeof(T);
-#define REVO_ATTN_LOAD1(kb_, i_, kr_, vr_)                                                                     \
-  {                                                                                                            \
-    auto k_ = __builtin_amdgcn_raw_buffer_load_b128(krs, kvo, ((kb_) + (i_) * R) * 64 * (int)sizeof(T), 0);   \
-    auto v_ = __builtin_amdgcn_raw_buffer_load_b128(vrs, vvo, ((i_) * R * a.ldv + (kb_)) * (int)sizeof(T), 0); \
-    kr_ = make_uint4(k_[0], k_[1], k_[2], k_[3]);                                                              \
-    vr_ = make_uint4(v_[0], v_[1], v_[2], v_[3]);                                                              \
+  // Stage loads for key block kb_ into LDS buffer buf_: FETCH starts them,
+  // LAND completes them (the caller then synchronises the workgroup).
+  //  BF16: buffer loads straight into LDS.  Wave w fills rows 16w .. 16w+15
+  //  of the K and V^T tiles, 8 rows (1 KB, 16 bytes per lane) per load; lane
+  //  L takes row 16w + 8j + L / 8 and the chunk whose swizzled slot is L % 8.
+  //  V^T arrives with bits 2 and 3 of the key index already swapped within
+  //  each group of 16 keys (the QKV epilogue writes it so; requests start on
+  //  16-key boundaries), so a lane's eight probabilities meet one 16-byte read.
+  //  FP32: 16-byte loads into registers, then LDS stores.
+  constexpr int R = NT / A::CPR;
+  const int c_row = tid / A::CPR;
+  const int c_col = (tid % A::CPR) * A::E;
+  int kvo[2], vvo[2];
+  if constexpr (sizeof(T) == 2) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int rr = wave * 16 + 8 * j + (lane >> 3);
+      const int cc = (lane & 7) ^ ((rr >> 1) & 7);
+      kvo[j] = (rr * 64 + cc * 8) * (int)sizeof(T);
+      vvo[j] = (rr * a.ldv + cc * 8) * (int)sizeof(T);
+    }
+  } else {
+    kvo[0] = (c_row * 64 + c_col) * (int)sizeof(T);
+    vvo[0] = (c_row * a.ldv + c_col) * (int)sizeof(T);
   }
-#define REVO_ATTN_LOAD(kb_)                                                                           \
-  REVO_ATTN_LOAD1(kb_, 0, kr0, vr0)                                                                   \
-  REVO_ATTN_LOAD1(kb_, 1, kr1, vr1)                                                                   \
-  if constexpr (A::LC == 4) { REVO_ATTN_LOAD1(kb_, 2, kr2, vr2) REVO_ATTN_LOAD1(kb_, 3, kr3, vr3) }
-  // V^T rows are stored with bits 2 and 3 of the key index swapped (bf16):
-  // a chunk of keys c..c+7 lands at c..c+3 and c+8..c+11 (c % 16 == 0) or at
-  // c-4..c-1 and c+4..c+7 (c % 16 == 8)
+  uint4 kr0, kr1, kr2, kr3, vr0, vr1, vr2, vr3;
+#define REVO_ATTN_LOAD1(kb_, i_, kr_, vr_)                                                                       \
+  {                                                                                                              \
+    auto k_ = __builtin_amdgcn_raw_buffer_load_b128(krs, kvo[0], ((kb_) + (i_) * R) * 64 * (int)sizeof(T), 0);  \
+    auto v_ = __builtin_amdgcn_raw_buffer_load_b128(vrs, vvo[0], ((i_) * R * a.ldv + (kb_)) * (int)sizeof(T), 0); \
+    kr_ = make_uint4(k_[0], k_[1], k_[2], k_[3]);                                                                \
+    vr_ = make_uint4(v_[0], v_[1], v_[2], v_[3]);                                                                \
+  }
 #define REVO_ATTN_STORE1(buf_, i_, kr_, vr_)                                                          \
   {                                                                                                   \
     *reinterpret_cast<uint4*>(&ks[buf_][(c_row + (i_) * R) * A::PITCH + c_col]) = kr_;                \
-    T* vrow_ = &vs[buf_][(c_row + (i_) * R) * A::PITCH];                                              \
-    if constexpr (sizeof(T) == 2) {                                                                   \
-      const int p0_ = c_col & 8 ? c_col - 4 : c_col;                                                 \
-      *reinterpret_cast<uint2*>(vrow_ + p0_) = make_uint2(vr_.x, vr_.y);                              \
-      *reinterpret_cast<uint2*>(vrow_ + p0_ + 8) = make_uint2(vr_.z, vr_.w);                          \
-    } else {                                                                                          \
-      *reinterpret_cast<uint4*>(vrow_ + c_col) = vr_;                                                 \
-    }                                                                                                 \
+    *reinterpret_cast<uint4*>(&vs[buf_][(c_row + (i_) * R) * A::PITCH + c_col]) = vr_;                \
   }
-#define REVO_ATTN_STORE(buf_)                                                                         \
-  REVO_ATTN_STORE1(buf_, 0, kr0, vr0)                                                                 \
-  REVO_ATTN_STORE1(buf_, 1, kr1, vr1)                                                                 \
-  if constexpr (A::LC == 4) { REVO_ATTN_STORE1(buf_, 2, kr2, vr2) REVO_ATTN_STORE1(buf_, 3, kr3, vr3) }
+#define REVO_ATTN_DMA(rs_, lds_, vo_, so_)                                                            \
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(rs_, (__attribute__((address_space(3))) void*)(lds_), 16, \
+                                           vo_, so_, 0, 0)
+#define REVO_ATTN_FETCH(kb_, buf_)                                                                    \
+  if constexpr (sizeof(T) == 2) {                                                                     \
+    REVO_ATTN_DMA(krs, &ks[buf_][(wave * 16) * 64], kvo[0], (kb_) * 64 * (int)sizeof(T));             \
+    REVO_ATTN_DMA(krs, &ks[buf_][(wave * 16 + 8) * 64], kvo[1], (kb_) * 64 * (int)sizeof(T));         \
+    REVO_ATTN_DMA(vrs, &vs[buf_][(wave * 16) * 64], vvo[0], (kb_) * (int)sizeof(T));                  \
+    REVO_ATTN_DMA(vrs, &vs[buf_][(wave * 16 + 8) * 64], vvo[1], (kb_) * (int)sizeof(T));              \
+  } else {                                                                                            \
+    REVO_ATTN_LOAD1(kb_, 0, kr0, vr0)                                                                 \
+    REVO_ATTN_LOAD1(kb_, 1, kr1, vr1)                                                                 \
+    REVO_ATTN_LOAD1(kb_, 2, kr2, vr2)                                                                 \
+    REVO_ATTN_LOAD1(kb_, 3, kr3, vr3)                                                                 \
+  }
+#define REVO_ATTN_LAND(buf_)                                                                          \
+  if constexpr (sizeof(T) == 2) {                                                                     \
+    __builtin_amdgcn_s_waitcnt(0x0F70); /* vmcnt(0): this wave's loads are in LDS */                  \
+  } else {                                                                                            \
+    REVO_ATTN_STORE1(buf_, 0, kr0, vr0)                                                               \
+    REVO_ATTN_STORE1(buf_, 1, kr1, vr1)                                                               \
+    REVO_ATTN_STORE1(buf_, 2, kr2, vr2)                                                               \
+    REVO_ATTN_STORE1(buf_, 3, kr3, vr3)                                                               \
+  }
+  static_assert(sizeof(T) == 2 || A::LC == 4, "FP32: 4 chunks per thread");
 
-  REVO_ATTN_LOAD(0);
-  REVO_ATTN_STORE(0);
+  REVO_ATTN_FETCH(0, 0);
+  REVO_ATTN_LAND(0);
   __syncthreads();
 
   f32x16 oacc[2] = {f32x16{}, f32x16{}};
@@ -313,16 +350,16 @@ __global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 3 : 2) void attn_
     // the first block sets the max; the prefetch of the next block (or, at
     // the end, a re-read of its own block into the idle buffer, which is
     // then never read) overlaps it
-    REVO_ATTN_LOAD(nkb > 1 ? KB : 0);
+    REVO_ATTN_FETCH(nkb > 1 ? KB : 0, 1);
     attn_block<Op, false, true>(ks[0], vs[0], qf, oacc, negm, m_run, l_run, lane, KB);
-    REVO_ATTN_STORE(1);
+    REVO_ATTN_LAND(1);
     __syncthreads();
 #define REVO_ATTN_STEP(b_, buf_)                                                                      \
   {                                                                                                   \
     const int kn_ = (b_) + 1 < nkb ? ((b_) + 1) * KB : (b_) * KB;                                     \
-    REVO_ATTN_LOAD(kn_);                                                                              \
+    REVO_ATTN_FETCH(kn_, buf_ ^ 1);                                                                   \
     attn_block<Op, false, false>(ks[buf_], vs[buf_], qf, oacc, negm, m_run, l_run, lane, KB);         \
-    REVO_ATTN_STORE(buf_ ^ 1);                                                                        \
+    REVO_ATTN_LAND(buf_ ^ 1);                                                                         \
     __syncthreads();                                                                                  \
   }
     int b = 1;
@@ -336,16 +373,17 @@ __global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 3 : 2) void attn_
       attn_block<Op, true, false>(ks[nfull & 1], vs[nfull & 1], qf, oacc, negm, m_run, l_run, lane, N - nfull * KB);
   }
 #undef REVO_ATTN_LOAD1
-#undef REVO_ATTN_LOAD
 #undef REVO_ATTN_STORE1
-#undef REVO_ATTN_STORE
+#undef REVO_ATTN_DMA
+#undef REVO_ATTN_FETCH
+#undef REVO_ATTN_LAND
 
   // The output goes through LDS (the K stages are free once every wave is
   // past its last block) so that whole 64-dim query rows are written in
   // 16-byte chunks rather than one short piece per query row.
   const float l_tot = xhalf_sum(l_run);
   const int ql = wave * 32 + (lane & 31);  // this lane's query within the tile
-  uint8_t* st = reinterpret_cast<uint8_t*>(&ks[0][0]);
+  uint8_t* st = reinterpret_cast<uint8_t*>(&kv[0][0]);
   __syncthreads();
   if (a.o_scale) {
     // FP8 output for an FP8 output projection
@@ -370,7 +408,7 @@ __global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 3 : 2) void attn_
   } else {
     constexpr int RB = 64 * (int)sizeof(T) + 16;
     constexpr int EC = 16 / (int)sizeof(T);  // elements per 16-byte chunk
-    static_assert(QT * RB <= (int)sizeof(ks), "output tile fits the K stages");
+    static_assert(QT * RB <= (int)sizeof(kv), "output tile fits the K and V stages");
     const float inv = 1.0f / l_tot;
 #pragma unroll
     for (int ds = 0; ds < 2; ++ds)

@@ -433,7 +433,7 @@ void worker_main(revo_ctx* c) {
             for (unsigned s : rec_streams[q])
               if (s == j->stream) conflict = true;
           } else {
-            add[q] = (request_tokens(m.H, m.W, c->J) + 7) & ~7;  // rows start 8-aligned
+            add[q] = (request_tokens(m.H, m.W, c->J) + 15) & ~15;  // rows start 16-aligned
             ju += work_units(request_tokens(m.H, m.W, c->J));
             if (tokens[q] + add[q] > cap) fits = false;
           }
@@ -623,7 +623,7 @@ int revo_recover_create(const revo_config* cfg_in, revo_ctx** out) {
         cap = avail > 0 ? (int)std::min(avail / per_tok, 1.0e6) : 0;
       }
     }
-    cap &= ~7;  // requests start on 8-row boundaries; V^T rows stay 16-byte aligned
+    cap &= ~15;  // requests start on 16-row boundaries (V^T key groups of 16)
     if (cap < 64) rc = REVO_ENOMEM;
     c->cfg.max_batch_tokens = cap;
     if (!rc) rc = workspace_alloc(c->ws[0], c->model[0], cap, cfg.max_batch, c->stream[0]);
@@ -658,7 +658,7 @@ int revo_recover_submit(revo_ctx* c, const revo_request* r, unsigned long long* 
   if (r->width < 16 || r->height < 16 || r->width > 4096 || r->height > 4096) return REVO_EINVAL;
   if (!r->rgb && !r->depth) return REVO_EINVAL;
   if ((r->mask_rgb && !r->rgb) || (r->mask_depth && !r->depth)) return REVO_EINVAL;
-  if (((request_tokens(r->height, r->width, c->J) + 7) & ~7) > c->cfg.max_batch_tokens) return REVO_EINVAL;
+  if (((request_tokens(r->height, r->width, c->J) + 15) & ~15) > c->cfg.max_batch_tokens) return REVO_EINVAL;
   {
     std::lock_guard<std::mutex> lk(c->mu);
     if (c->stop) return REVO_ESHUTDOWN;

@@ -365,8 +365,12 @@ __device__ __forceinline__ void gemm_epilogue_staged(const GemmArgs& a, f32x16 (
           for (int e = 0; e < 4; ++e) v[e] *= a.qscale;
         }
         if (vtile) {
+          // 2-byte V^T (BF16 attention): within each group of 16 tokens the
+          // column index has bits 2 and 3 swapped, the order in which a
+          // lane's eight probabilities meet the P V product
+          const int mc = sizeof(OutT) == 2 ? (ml & ~12) | ((ml & 4) << 1) | ((ml & 8) >> 1) : ml;
 #pragma unroll
-          for (int e = 0; e < 4; ++e) reinterpret_cast<OutT*>(smem + (nl + e) * TPV)[ml] = out_cast<OutT>(v[e], 1.0f);
+          for (int e = 0; e < 4; ++e) reinterpret_cast<OutT*>(smem + (nl + e) * TPV)[mc] = out_cast<OutT>(v[e], 1.0f);
         } else {
           Vec4<OutT>::store(reinterpret_cast<OutT*>(smem + ml * TPB) + nl, v, oinv);
         }
@@ -375,19 +379,22 @@ __device__ __forceinline__ void gemm_epilogue_staged(const GemmArgs& a, f32x16 (
   }
   __syncthreads();
   if (vtile) {
-    // V^T rows: EO consecutive tokens per 16-byte chunk
+    // V^T rows: EO consecutive columns per 16-byte chunk; a 2-byte chunk
+    // can hold permuted tokens up to the end of its group of 16, so it is
+    // written whole while its group starts below Mlive
+    const int Mcol = sizeof(OutT) == 2 ? (Mlive + 15) & ~15 : Mlive;
     for (int i = tid; i < BN * (BM / EO); i += NT) {
       const int nl = i / (BM / EO), c = (i - nl * (BM / EO)) * EO;
       const int m = m0 + c;
-      if (m >= Mlive) continue;
+      if (m >= Mcol) continue;
       const int n = n0 + nl;
       const int hd = (n - 2 * D) >> 6, dd = n & 63;
       OutT* dst = (OutT*)a.vt + ((size_t)hd * 64 + dd) * a.ldv + m;
       const OutT* src = reinterpret_cast<const OutT*>(smem + nl * TPV) + c;
-      if (m + EO <= Mlive) {
+      if (m + EO <= Mcol) {
         *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(src);
       } else {
-        for (int e = 0; m + e < Mlive; ++e) dst[e] = src[e];
+        for (int e = 0; m + e < Mcol; ++e) dst[e] = src[e];
       }
     }
     return;

@@ -391,7 +391,7 @@ int forward(const ModelW& m, Workspace& w, int slot, int nrec, int nall, int com
     d.P = d.gy * d.gx;
     if (d.H * d.W > max_pix) max_pix = d.H * d.W;
     if (r >= nrec) { d.tok_off = M; d.head_off = Mh; continue; }
-    M = (M + 7) & ~7;  // 16-byte aligned V^T columns for every request
+    M = (M + 15) & ~15;  // every request starts a V^T key group of 16 (and 16-byte aligned columns)
     d.tok_off = M;
     d.head_off = Mh;
     const int N = d.J * d.P;

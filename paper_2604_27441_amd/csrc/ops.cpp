@@ -75,7 +75,7 @@ int revo_op_attention(int precision, const void* q, const void* k, const void* v
   Prec p;
   if (!prec_of(precision, &p)) return REVO_ENOTSUP;
   if (heads <= 0 || ntok <= 0 || ld < ntok + 64 || !q || !k || !vt || !o) return REVO_EINVAL;
-  if (ld % 8) return REVO_EINVAL;  // 16-byte aligned vt rows
+  if (ld % 16) return REVO_EINVAL;  // 16-byte aligned vt rows, whole key groups of 16
   const int ntile = (ntok + 127) / 128;
   if (ntile >= ATTN_TARGET_TILE) return REVO_EINVAL;
   hipStream_t s = (hipStream_t)stream;

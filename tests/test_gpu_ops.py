@@ -76,8 +76,14 @@ def test_layernorm(prec, rows, D):
     assert np.all(np.abs(got - ref) <= tol), float(np.abs(got - ref).max())
 
 
+def _swap23(n):
+    """Column order of the BF16 V^T operand: token index with bits 2 and 3 swapped."""
+    c = np.arange(n)
+    return (c & ~12) | ((c & 4) << 1) | ((c & 8) >> 1)
+
+
 def _attn_inputs(heads, ntok, prec, scale=1.0, ld=None):
-    ld = ld or ((ntok + 64 + 7) // 8 * 8)
+    ld = ld or ((ntok + 64 + 15) // 16 * 16)
     q = RNG.standard_normal((heads, ntok, 64)) * scale
     k = RNG.standard_normal((heads, ntok, 64)) * scale
     v = RNG.standard_normal((heads, ntok, 64))
@@ -92,6 +98,8 @@ def _attn_inputs(heads, ntok, prec, scale=1.0, ld=None):
     qd[:, :ntok] = q_op
     kd[:, :ntok] = k_op
     vt[:, :, :ntok] = v_op.transpose(1, 2)
+    if prec == BF16:
+        vt = vt[:, :, _swap23(ld)]   # the BF16 kernel's V^T column order
     q64 = q_op.double().numpy() / (math.log2(math.e) / 8)
     return qd.cuda(), kd.cuda(), vt.cuda(), q64, k_op.double().numpy(), v_op.double().numpy(), ld
 
