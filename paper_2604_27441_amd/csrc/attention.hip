@@ -84,16 +84,26 @@ __device__ __forceinline__ void attn_block(const typename Op::T* __restrict__ kt
     sacc[0] = f32x16{};
     sacc[1] = f32x16{};
   }
+  if constexpr (sizeof(T) == 2) {
+    // all eight K fragments in flight before the first product
+    uint4 kf[A::QCH][2];
+#pragma unroll
+    for (int kc = 0; kc < A::QCH; ++kc)
+#pragma unroll
+      for (int st = 0; st < 2; ++st) kf[kc][st] = *reinterpret_cast<const uint4*>(kt + swz(st * 32 + l32, half * 4 + kc));
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int kc = 0; kc < A::QCH; ++kc)
+#pragma unroll
+      for (int st = 0; st < 2; ++st)
+        Op::mma(sacc[st], __builtin_bit_cast(bf16x8, kf[kc][st]), __builtin_bit_cast(bf16x8, qf[kc]));
+  }
 #pragma unroll
   for (int kc = 0; kc < A::QCH; ++kc) {
 #pragma unroll
     for (int st = 0; st < 2; ++st) {
-      const uint4 kf = sizeof(T) == 2
-                           ? *reinterpret_cast<const uint4*>(kt + swz(st * 32 + l32, half * 4 + kc))
-                           : *reinterpret_cast<const uint4*>(kt + (st * 32 + l32) * A::PITCH + half * 32 + kc * A::E);
-      if constexpr (sizeof(T) == 2) {
-        Op::mma(sacc[st], __builtin_bit_cast(bf16x8, kf), __builtin_bit_cast(bf16x8, qf[kc]));
-      } else {
+      if constexpr (sizeof(T) == 4) {
+        const uint4 kf = *reinterpret_cast<const uint4*>(kt + (st * 32 + l32) * A::PITCH + half * 32 + kc * A::E);
         Op::mma(sacc[st], __uint_as_float(kf.x), __uint_as_float(qf[kc].x));
         Op::mma(sacc[st], __uint_as_float(kf.y), __uint_as_float(qf[kc].y));
         Op::mma(sacc[st], __uint_as_float(kf.z), __uint_as_float(qf[kc].z));
