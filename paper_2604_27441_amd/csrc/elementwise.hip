@@ -70,6 +70,62 @@ __global__ __launch_bounds__(256) void layernorm_kernel(const float* __restrict_
   }
 }
 
+// The same LayerNorm with a group of L lanes per row and V float4 per lane
+// (D = 4 L V), so a wave holds 64 / L rows and every load is 16 bytes.
+template <class T, int L, int V>
+__global__ __launch_bounds__(256) void layernorm_rows_kernel(const float* __restrict__ x, const float* __restrict__ g,
+                                                             const float* __restrict__ b, T* __restrict__ y, int rows,
+                                                             const ReqDesc* reqs, int nreq, const int* dyn_rows,
+                                                             const int* dyn_nreq) {
+  constexpr int D = 4 * L * V;
+  const int j = threadIdx.x & (L - 1);
+  const int row = blockIdx.x * (256 / L) + (threadIdx.x / L);
+  if (dyn_rows) rows = *dyn_rows;
+  if (dyn_nreq) nreq = *dyn_nreq;
+  if (row >= rows) return;
+  int src = row;
+  if (reqs) {
+    const int r = find_req_head(reqs, nreq, row);
+    const ReqDesc& d = reqs[r];
+    src = d.tok_off + (d.J - 1) * d.P + (row - d.head_off);
+  }
+  const float4* xr = reinterpret_cast<const float4*>(x + (size_t)src * D);
+  float4 v[V];
+  float s = 0.0f;
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    v[i] = xr[j + L * i];
+    s += (v[i].x + v[i].y) + (v[i].z + v[i].w);
+  }
+#pragma unroll
+  for (int o = L / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  const float mean = s * (1.0f / (float)D);
+  float q = 0.0f;
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    v[i].x -= mean; v[i].y -= mean; v[i].z -= mean; v[i].w -= mean;
+    q += (v[i].x * v[i].x + v[i].y * v[i].y) + (v[i].z * v[i].z + v[i].w * v[i].w);
+  }
+#pragma unroll
+  for (int o = L / 2; o > 0; o >>= 1) q += __shfl_xor(q, o);
+  const float rstd = 1.0f / sqrtf(q * (1.0f / (float)D) + 1e-6f);
+  const float4* g4 = reinterpret_cast<const float4*>(g);
+  const float4* b4 = reinterpret_cast<const float4*>(b);
+  T* yr = y + (size_t)row * D;
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    const int c = j + L * i;
+    const float4 gg = g4[c], bb = b4[c];
+    const float y0 = v[i].x * rstd * gg.x + bb.x, y1 = v[i].y * rstd * gg.y + bb.y;
+    const float y2 = v[i].z * rstd * gg.z + bb.z, y3 = v[i].w * rstd * gg.w + bb.w;
+    if constexpr (sizeof(T) == 2) {
+      *reinterpret_cast<bf16x4*>(yr + 4 * c) = bf16x4{(__bf16)y0, (__bf16)y1, (__bf16)y2, (__bf16)y3};
+    } else {
+      *reinterpret_cast<float4*>(yr + 4 * c) = make_float4(y0, y1, y2, y3);
+    }
+  }
+}
+
 // Final frame of one request: lost pixels take the clamped prediction
 // (RGB in [0, 1], depth in [0, 65535] mm) quantised half-to-even, received
 // pixels are copied unchanged.  A request without a mask is a clean frame
@@ -224,6 +280,23 @@ int launch_layernorm(Prec out_prec, const float* x, const float* g, const float*
                      const ReqDesc* reqs, int nreq, hipStream_t s, const int* dyn_rows, const int* dyn_nreq) {
   if (rows <= 0) return 0;
   if (D > 512 || (D & 1)) return -22;
+  // the widths of the two networks (16-byte aligned operands): three float4
+  // per lane, 2 or 4 rows per wave
+#define REVO_LN_ROWS(L_)                                                                                          \
+  do {                                                                                                            \
+    const dim3 gr(cdiv(rows, 256 / (L_)));                                                                        \
+    if (out_prec == P_BF16)                                                                                       \
+      layernorm_rows_kernel<__bf16, L_, 3><<<gr, 256, 0, s>>>(x, g, b, (__bf16*)y, rows, reqs, nreq, dyn_rows,     \
+                                                              dyn_nreq);                                          \
+    else                                                                                                          \
+      layernorm_rows_kernel<float, L_, 3><<<gr, 256, 0, s>>>(x, g, b, (float*)y, rows, reqs, nreq, dyn_rows,       \
+                                                             dyn_nreq);                                           \
+    return hipGetLastError() == hipSuccess ? 0 : -5;                                                              \
+  } while (0)
+  const bool al16 = (((uintptr_t)x | (uintptr_t)g | (uintptr_t)b | (uintptr_t)y) & 15) == 0;
+  if (al16 && D == 384) REVO_LN_ROWS(32);
+  if (al16 && D == 192) REVO_LN_ROWS(16);
+#undef REVO_LN_ROWS
   dim3 grid(cdiv(rows, 4));
   if (out_prec == P_BF16)
     layernorm_kernel<__bf16><<<grid, 256, 0, s>>>(x, g, b, (__bf16*)y, rows, D, reqs, nreq, dyn_rows, dyn_nreq);
