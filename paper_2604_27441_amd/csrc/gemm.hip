@@ -597,6 +597,141 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
     gemm_epilogue_staged<Op, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, tid, smem);
 }
 
+
+// ---------------------------------------------------------------------------
+// BF16 dense form: operand stages go from HBM straight into LDS (buffer loads
+// with the LDS as destination) in a ring of NS stages, so no registers hold
+// stages in flight and no LDS stores are issued.  LDS rows are 128 bytes,
+// unpadded; 16-byte chunk c of row r sits in slot c ^ ((r >> 1) & 7), which
+// spreads the 32 rows one fragment read touches over all banks.
+__device__ __forceinline__ int gswz(int r, int c) { return r * 64 + ((c ^ ((r >> 1) & 7)) << 3); }
+
+// One 16-byte-per-lane buffer load into LDS: lane L's bytes land at lds + 16 L
+// (lds is wave-uniform).  Kept out of line of the kernel template's body: the
+// host pass drops a kernel template's launch stub when the builtin sits there.
+__device__ __forceinline__ void dma16(__amdgpu_buffer_rsrc_t rs, const void* lds, int vo, int so) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)lds, 16, vo, so, 0, 0);
+}
+
+// s_waitcnt vmcnt(N_): at most N_ of this wave's vector loads still in flight.
+template <int N_>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N_ >= 0 && N_ < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N_ & 15) | ((N_ >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+// One 64-deep K stage from LDS into the accumulators: all 16 fragment reads,
+// then the 16 products.  The operand pointers are restrict-qualified, so the
+// reads carry alias scopes and the compiler does not hold them behind the
+// ring's loads still in flight (the kernel orders those with vmcnt waits and
+// barriers itself).
+template <int BN>
+__device__ __forceinline__ void gemm_dma_stage(const __bf16* __restrict__ xb, const __bf16* __restrict__ wb,
+                                               f32x16 (&acc)[BN / 64][2], int wn, int wm, int half, int l32) {
+  constexpr int NSUB = BN / 64;
+  uint4 wf[4][NSUB], xf[4][2];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+#pragma unroll
+    for (int ns = 0; ns < NSUB; ++ns)
+      wf[s][ns] = *reinterpret_cast<const uint4*>(wb + gswz(wn * (BN / 2) + ns * 32 + l32, half * 4 + s));
+#pragma unroll
+    for (int ms = 0; ms < 2; ++ms)
+      xf[s][ms] = *reinterpret_cast<const uint4*>(xb + gswz(wm * 64 + ms * 32 + l32, half * 4 + s));
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int ns = 0; ns < NSUB; ++ns)
+#pragma unroll
+      for (int ms = 0; ms < 2; ++ms)
+        OpBF16::mma(acc[ns][ms], __builtin_bit_cast(bf16x8, wf[s][ns]), __builtin_bit_cast(bf16x8, xf[s][ms]));
+}
+
+template <int BN, int EPI, class OutT, int NS>
+__global__ __launch_bounds__(NT, 2) void gemm_dma_kernel(const GemmArgs a) {
+  typedef __bf16 T;
+  constexpr int BK = 64;
+  constexpr int XI = BM / 32, WI = BN / 32;  // 8-row loads per wave per stage
+  constexpr int SX = BM * BK, SW = BN * BK;  // elements per X / W stage
+  constexpr int OPE = NS * (SX + SW);
+  constexpr int EPE = (epi_stage_bytes<BN, OutT>() + 1) / 2;
+  // X stages at stg + b SX, W stages at stg + NS SX + b SW; the epilogue
+  // reuses the whole array
+  __shared__ __attribute__((aligned(16))) T stg[OPE > EPE ? OPE : EPE];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int half = lane >> 5, l32 = lane & 31;
+  // XCD-aware tile order, as in gemm_kernel
+  const int gn = a.N / BN;
+  const int ntiles = gridDim.x;
+  const int L = blockIdx.x;
+  const int xcd = L & 7, per = ntiles >> 3, rem = ntiles & 7;
+  const int tile = xcd * per + (xcd < rem ? xcd : rem) + (L >> 3);
+  const int m0 = (tile / gn) * BM;
+  const int n0 = (tile - (tile / gn) * gn) * BN;
+  const int Mlive = a.dyn_m ? *a.dyn_m : a.M;
+  const int nreq = a.dyn_nreq ? *a.dyn_nreq : a.nreq;
+  if (m0 >= Mlive) return;
+  const int KT = a.K / BK;
+
+  // rows at or past Mlive are outside the descriptor's range: they read as
+  // zeros and only ever reach outputs that are not stored
+  const __amdgpu_buffer_rsrc_t wrs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)a.W, (short)0, a.N * a.K * (int)sizeof(T), 0x00020000);
+  const __amdgpu_buffer_rsrc_t xrs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)a.X, (short)0, Mlive * a.K * (int)sizeof(T), 0x00020000);
+  // wave w fills rows w*BM/4 .. (w+1)*BM/4 - 1 of the X stage (likewise for
+  // W), 8 rows per load; lane L fills slot L % 8 of row L / 8 of its group
+  int xo[XI], wo[WI];
+#pragma unroll
+  for (int j = 0; j < XI; ++j) {
+    const int rr = wave * (BM / 4) + 8 * j + (lane >> 3);
+    xo[j] = ((m0 + rr) * a.K + (((lane & 7) ^ ((rr >> 1) & 7)) << 3)) * (int)sizeof(T);
+  }
+#pragma unroll
+  for (int j = 0; j < WI; ++j) {
+    const int rr = wave * (BN / 4) + 8 * j + (lane >> 3);
+    wo[j] = ((n0 + rr) * a.K + (((lane & 7) ^ ((rr >> 1) & 7)) << 3)) * (int)sizeof(T);
+  }
+#define REVO_GD_FETCH(kt_, buf_)                                                                         \
+  do {                                                                                                   \
+    _Pragma("unroll") for (int j = 0; j < XI; ++j)                                                       \
+      dma16(xrs, stg + (buf_) * SX + (wave * (BM / 4) + 8 * j) * 64, xo[j], (kt_) * BK * (int)sizeof(T));  \
+    _Pragma("unroll") for (int j = 0; j < WI; ++j)                                                       \
+      dma16(wrs, stg + NS * SX + (buf_) * SW + (wave * (BN / 4) + 8 * j) * 64, wo[j],                    \
+            (kt_) * BK * (int)sizeof(T));                                                                 \
+  } while (0)
+
+  const int wn = wave >> 1, wm = wave & 1;
+  f32x16 acc[BN / 64][2];
+#pragma unroll
+  for (int i = 0; i < BN / 64; ++i) { acc[i][0] = f32x16{}; acc[i][1] = f32x16{}; }
+
+  // stage k goes to buffer k % NS; loads past the last stage re-read it
+  // into a free buffer, which keeps the wait counts static
+#pragma unroll
+  for (int i = 0; i < NS - 1; ++i) REVO_GD_FETCH(i < KT ? i : KT - 1, i);
+  // the ring is unrolled NS times so that every buffer index is a constant
+  for (int kt = 0; kt < KT;) {
+#pragma unroll
+    for (int b = 0; b < NS; ++b) {
+      wait_vm<(NS - 2) * (XI + WI)>();  // this wave's part of stage kt is in LDS
+      // every wave's part is, and stage kt-1's buffer is free (a plain
+      // barrier: the fence of __syncthreads would also wait for the younger
+      // stage loads)
+      asm volatile("s_barrier" ::: "memory");
+      REVO_GD_FETCH(kt + NS - 1 < KT ? kt + NS - 1 : KT - 1, (b + NS - 1) % NS);
+      gemm_dma_stage<BN>(stg + b * SX, stg + NS * SX + b * SW, acc, wn, wm, half, l32);
+      if (++kt >= KT) break;
+    }
+  }
+  wait_vm<0>();  // no load still writes LDS when the epilogue reuses it
+#undef REVO_GD_FETCH
+  gemm_epilogue_staged<OpBF16, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, tid, reinterpret_cast<uint8_t*>(stg));
+}
+
 template <class Op, int EPI, int XM, class OutT>
 int launch_t(const GemmArgs& a, hipStream_t s) {
   const int gm = cdiv(a.M, BM);
@@ -604,6 +739,15 @@ int launch_t(const GemmArgs& a, hipStream_t s) {
   // whole row tiles, stay below 2 GiB
   const long long esz = sizeof(typename Op::T);
   if ((long long)gm * BM * a.K * esz >= (1LL << 31) || (long long)a.N * a.K * esz >= (1LL << 31)) return -22;
+  // BF16 dense products (all but the head) take the LDS-ring kernel
+  if constexpr (XM == X_DENSE && sizeof(typename Op::T) == 2 && EPI != EPI_HEAD) {
+    if (a.N % 128 == 0) {
+      gemm_dma_kernel<128, EPI, OutT, 2><<<dim3(gm * (a.N / 128)), NT, 0, s>>>(a);
+      return hipGetLastError() == hipSuccess ? 0 : -5;
+    }
+    gemm_dma_kernel<64, EPI, OutT, 2><<<dim3(gm * (a.N / 64)), NT, 0, s>>>(a);
+    return hipGetLastError() == hipSuccess ? 0 : -5;
+  }
   // the gather loader's per-row token coordinates leave no registers for a
   // 128-wide tile with two prefetched stages
   if constexpr (XM == X_DENSE) {
