@@ -24,7 +24,7 @@ enum revo_op_epilogue {
 };
 
 /* Linear layer of a Transformer block (Sec. 3.4.1): x [M][K] and w [N][K]
- * row-major in the operand type, bias [N] float, out [M][N].
+ * row-major in the operand type, bias [N] float (16-byte aligned), out [M][N].
  * Requires N % 64 == 0 and K % 64 == 0 (K % 32 for REVO_FP32). */
 int revo_op_linear(int precision, int epilogue, const void *x, const void *w, const float *bias,
                    void *out, int M, int N, int K, void *stream);
@@ -35,7 +35,7 @@ int revo_op_linear(int precision, int epilogue, const void *x, const void *w, co
  * sum_k x8[m][k] w8[n][k] * wscale[n] * (*xscale) + bias[n], accumulated in
  * float.  REVO_EPI_STORE writes bfloat16 out [M][N], REVO_EPI_RESIDUAL adds
  * into float out, REVO_EPI_GELU writes E4M3 bytes of GELU(.) / (*out_scale).
- * Requires N % 64 == 0 and K % 64 == 0. */
+ * bias and wscale are 16-byte aligned.  Requires N % 64 == 0 and K % 64 == 0. */
 int revo_op_linear_fp8(int epilogue, const void *x8, const void *w8, const float *wscale, const float *xscale,
                        const float *bias, void *out, const float *out_scale, int M, int N, int K, void *stream);
 

@@ -295,6 +295,29 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[B
 // LDS bytes of the staged epilogue: a row-major [BM][BN] tile of the output
 // type, or for the V part of the QKV product a transposed [BN][BM] tile
 // (rows padded by 16 bytes).
+// Bias (and, for FP8 operands, row-scale x activation-scale) values of the
+// output features one lane's accumulators hold: features
+// n0 + wn BN/2 + 32 ns + 8 g + 4 half + e.  Fetched as 16-byte vectors
+// (bias and scales are 16-byte aligned) all at once, early, instead of once
+// per group of four inside the epilogue.
+template <int BN>
+struct EpiCols {
+  f32x4 b[BN / 64][4], s[BN / 64][4];
+};
+template <class Op, int BN>
+__device__ __forceinline__ void epi_load_cols(const GemmArgs& a, int n0, int wn, int half, EpiCols<BN>& c) {
+  constexpr bool SC = sizeof(typename Op::T) == 1;
+  const float xsc = SC ? *a.xscale : 1.0f;
+#pragma unroll
+  for (int ns = 0; ns < BN / 64; ++ns)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int n = n0 + wn * (BN / 2) + ns * 32 + g * 8 + half * 4;
+      c.b[ns][g] = *reinterpret_cast<const f32x4*>(a.bias + n);
+      if constexpr (SC) c.s[ns][g] = *reinterpret_cast<const f32x4*>(a.wscale + n) * xsc;
+    }
+}
+
 template <int BN, class OutT>
 constexpr int epi_stage_bytes() {
   return BM * (BN * (int)sizeof(OutT) + 16) > BN * (BM * (int)sizeof(OutT) + 16) ? BM * (BN * (int)sizeof(OutT) + 16)
@@ -309,7 +332,8 @@ constexpr int epi_stage_bytes() {
 // contiguous token runs of V^T.  smem must hold epi_stage_bytes<BN, OutT>().
 template <class Op, int BN, int EPI, class OutT>
 __device__ __forceinline__ void gemm_epilogue_staged(const GemmArgs& a, f32x16 (&acc)[BN / 64][2], int m0, int n0,
-                                                     int Mlive, int nreq, int tid, uint8_t* smem) {
+                                                     int Mlive, int nreq, int tid, uint8_t* smem,
+                                                     const EpiCols<BN>& cols) {
   constexpr int NSUB = BN / 64;
   constexpr int TPB = BN * (int)sizeof(OutT) + 16;  // row pitch (bytes), row-major tile
   constexpr int TPV = BM * (int)sizeof(OutT) + 16;  // row pitch (bytes), transposed V tile
@@ -317,11 +341,11 @@ __device__ __forceinline__ void gemm_epilogue_staged(const GemmArgs& a, f32x16 (
   const int lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
   const int wn = wave >> 1, wm = wave & 1;
-  const float xsc = a.xscale ? *a.xscale : 1.0f;
   const float oinv = a.out_scale ? 1.0f / *a.out_scale : 1.0f;
   const int D = EPI == EPI_QKV ? a.heads * 64 : 1;
   const int part = EPI == EPI_QKV ? n0 / D : 0;  // tiles never straddle Q | K | V
   const bool vtile = EPI == EPI_QKV && part == 2;
+  constexpr bool SC = sizeof(typename Op::T) == 1;  // FP8 operands carry row scales
   __syncthreads();  // every wave is done with the operand tiles
 #pragma unroll
   for (int ms = 0; ms < 2; ++ms) {
@@ -343,13 +367,10 @@ __device__ __forceinline__ void gemm_epilogue_staged(const GemmArgs& a, f32x16 (
         const int nl = wn * (BN / 2) + ns * 32 + g * 8 + half * 4;
         const int n = n0 + nl;
         float v[4];
-        if (a.wscale) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = acc[ns][ms][4 * g + e] * (a.wscale[n + e] * xsc) + a.bias[n + e];
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = acc[ns][ms][4 * g + e] + a.bias[n + e];
-        }
+        for (int e = 0; e < 4; ++e)
+          v[e] = SC ? acc[ns][ms][4 * g + e] * cols.s[ns][g][e] + cols.b[ns][g][e]
+                    : acc[ns][ms][4 * g + e] + cols.b[ns][g][e];
         if (EPI == EPI_GELU) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) v[e] = gelu_erf(v[e]);
@@ -591,10 +612,13 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
 #undef REVO_GEMM_STORE
 #undef REVO_GEMM_COMPUTE
 
-  if constexpr (EPI == EPI_HEAD)
+  if constexpr (EPI == EPI_HEAD) {
     gemm_epilogue<Op, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, lane, wave);
-  else
-    gemm_epilogue_staged<Op, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, tid, smem);
+  } else {
+    EpiCols<BN> cols;
+    epi_load_cols<Op, BN>(a, n0, wn, half, cols);
+    gemm_epilogue_staged<Op, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, tid, smem, cols);
+  }
 }
 
 
@@ -708,6 +732,8 @@ __global__ __launch_bounds__(NT, 2) void gemm_dma_kernel(const GemmArgs a) {
   f32x16 acc[BN / 64][2];
 #pragma unroll
   for (int i = 0; i < BN / 64; ++i) { acc[i][0] = f32x16{}; acc[i][1] = f32x16{}; }
+  EpiCols<BN> cols;  // in flight during the K loop
+  epi_load_cols<OpBF16, BN>(a, n0, wn, half, cols);
 
   // stage k goes to buffer k % NS; loads past the last stage re-read it
   // into a free buffer, which keeps the wait counts static
@@ -729,7 +755,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_dma_kernel(const GemmArgs a) {
   }
   wait_vm<0>();  // no load still writes LDS when the epilogue reuses it
 #undef REVO_GD_FETCH
-  gemm_epilogue_staged<OpBF16, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, tid, reinterpret_cast<uint8_t*>(stg));
+  gemm_epilogue_staged<OpBF16, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, tid, reinterpret_cast<uint8_t*>(stg), cols);
 }
 
 template <class Op, int EPI, int XM, class OutT>
@@ -747,17 +773,18 @@ int launch_t(const GemmArgs& a, hipStream_t s) {
     }
     gemm_dma_kernel<64, EPI, OutT, 2><<<dim3(gm * (a.N / 64)), NT, 0, s>>>(a);
     return hipGetLastError() == hipSuccess ? 0 : -5;
-  }
-  // the gather loader's per-row token coordinates leave no registers for a
-  // 128-wide tile with two prefetched stages
-  if constexpr (XM == X_DENSE) {
-    if (a.N % 128 == 0) {
-      gemm_kernel<Op, 128, EPI, XM, OutT><<<dim3(gm * (a.N / 128)), NT, 0, s>>>(a);
-      return hipGetLastError() == hipSuccess ? 0 : -5;
+  } else {
+    // the gather loader's per-row token coordinates leave no registers for a
+    // 128-wide tile with two prefetched stages
+    if constexpr (XM == X_DENSE) {
+      if (a.N % 128 == 0) {
+        gemm_kernel<Op, 128, EPI, XM, OutT><<<dim3(gm * (a.N / 128)), NT, 0, s>>>(a);
+        return hipGetLastError() == hipSuccess ? 0 : -5;
+      }
     }
+    gemm_kernel<Op, 64, EPI, XM, OutT><<<dim3(gm * (a.N / 64)), NT, 0, s>>>(a);
+    return hipGetLastError() == hipSuccess ? 0 : -5;
   }
-  gemm_kernel<Op, 64, EPI, XM, OutT><<<dim3(gm * (a.N / 64)), NT, 0, s>>>(a);
-  return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 
 template <class Op>
@@ -811,6 +838,8 @@ int launch_tubelet_pack(Prec prec, const GemmArgs& a, void* out, hipStream_t s) 
 int launch_gemm(Prec prec, int epi, int xmode, const GemmArgs& a, hipStream_t s) {
   if (a.M <= 0) return 0;
   if (a.N % 64 != 0) return -22;
+  // the epilogue reads bias and row scales as 16-byte vectors
+  if (((uintptr_t)a.bias | (uintptr_t)a.wscale) & 15) return -22;
   if (prec == P_BF16) {
     if (a.K % OpBF16::BK != 0) return -22;
     return launch_op<OpBF16>(epi, xmode, a, s);
