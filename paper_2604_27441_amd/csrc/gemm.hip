@@ -20,6 +20,7 @@ namespace {
 constexpr int BM = 128;
 constexpr int NT = 256;
 
+
 // Four consecutive results of one row; inv = 1 / (output scale) for FP8.
 template <class T> struct Vec4;
 template <> struct Vec4<float> {
@@ -318,10 +319,11 @@ __device__ __forceinline__ void epi_load_cols(const GemmArgs& a, int n0, int wn,
     }
 }
 
-template <int BN, class OutT>
+template <int BN, class OutT, int BM_ = BM>
 constexpr int epi_stage_bytes() {
-  return BM * (BN * (int)sizeof(OutT) + 16) > BN * (BM * (int)sizeof(OutT) + 16) ? BM * (BN * (int)sizeof(OutT) + 16)
-                                                                                  : BN * (BM * (int)sizeof(OutT) + 16);
+  return BM_ * (BN * (int)sizeof(OutT) + 16) > BN * (BM_ * (int)sizeof(OutT) + 16)
+             ? BM_ * (BN * (int)sizeof(OutT) + 16)
+             : BN * (BM_ * (int)sizeof(OutT) + 16);
 }
 
 // Epilogue through LDS: the accumulators (lane = token, runs of four
@@ -329,18 +331,21 @@ constexpr int epi_stage_bytes() {
 // workgroup then writes whole output rows in 16-byte chunks, so every store
 // instruction covers contiguous row segments instead of one short piece per
 // token.  The V part of the QKV product is staged transposed and written as
-// contiguous token runs of V^T.  smem must hold epi_stage_bytes<BN, OutT>().
-template <class Op, int BN, int EPI, class OutT>
+// contiguous token runs of V^T.  smem must hold epi_stage_bytes<BN, OutT, BM_>().
+// The tile is BM_ tokens x BN features over 2 WM_ waves, wave w covering
+// tokens (w % WM_) 64 .. +63 and features (w / WM_) BN/2 .. +BN/2-1.
+template <class Op, int BN, int EPI, class OutT, int BM_ = BM, int WM_ = 2>
 __device__ __forceinline__ void gemm_epilogue_staged(const GemmArgs& a, f32x16 (&acc)[BN / 64][2], int m0, int n0,
                                                      int Mlive, int nreq, int tid, uint8_t* smem,
                                                      const EpiCols<BN>& cols) {
+  constexpr int NT_ = 128 * WM_;
   constexpr int NSUB = BN / 64;
-  constexpr int TPB = BN * (int)sizeof(OutT) + 16;  // row pitch (bytes), row-major tile
-  constexpr int TPV = BM * (int)sizeof(OutT) + 16;  // row pitch (bytes), transposed V tile
-  constexpr int EO = 16 / (int)sizeof(OutT);         // output elements per 16-byte chunk
+  constexpr int TPB = BN * (int)sizeof(OutT) + 16;   // row pitch (bytes), row-major tile
+  constexpr int TPV = BM_ * (int)sizeof(OutT) + 16;  // row pitch (bytes), transposed V tile
+  constexpr int EO = 16 / (int)sizeof(OutT);          // output elements per 16-byte chunk
   const int lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
-  const int wn = wave >> 1, wm = wave & 1;
+  const int wn = wave / WM_, wm = wave % WM_;
   const float oinv = a.out_scale ? 1.0f / *a.out_scale : 1.0f;
   const int D = EPI == EPI_QKV ? a.heads * 64 : 1;
   const int part = EPI == EPI_QKV ? n0 / D : 0;  // tiles never straddle Q | K | V
@@ -404,8 +409,8 @@ __device__ __forceinline__ void gemm_epilogue_staged(const GemmArgs& a, f32x16 (
     // can hold permuted tokens up to the end of its group of 16, so it is
     // written whole while its group starts below Mlive
     const int Mcol = sizeof(OutT) == 2 ? (Mlive + 15) & ~15 : Mlive;
-    for (int i = tid; i < BN * (BM / EO); i += NT) {
-      const int nl = i / (BM / EO), c = (i - nl * (BM / EO)) * EO;
+    for (int i = tid; i < BN * (BM_ / EO); i += NT_) {
+      const int nl = i / (BM_ / EO), c = (i - nl * (BM_ / EO)) * EO;
       const int m = m0 + c;
       if (m >= Mcol) continue;
       const int n = n0 + nl;
@@ -421,7 +426,7 @@ __device__ __forceinline__ void gemm_epilogue_staged(const GemmArgs& a, f32x16 (
     return;
   }
   constexpr int CPRO = BN / EO;
-  for (int i = tid; i < BM * CPRO; i += NT) {
+  for (int i = tid; i < BM_ * CPRO; i += NT_) {
     const int rl = i / CPRO, c = (i - rl * CPRO) * EO;
     const int m = m0 + rl;
     if (m >= Mlive) continue;
@@ -673,14 +678,18 @@ __device__ __forceinline__ void gemm_dma_stage(const __bf16* __restrict__ xb, co
         OpBF16::mma(acc[ns][ms], __builtin_bit_cast(bf16x8, wf[s][ns]), __builtin_bit_cast(bf16x8, xf[s][ms]));
 }
 
-template <int BN, int EPI, class OutT, int NS>
-__global__ __launch_bounds__(NT, 2) void gemm_dma_kernel(const GemmArgs a) {
+// Tile BM_ tokens x BN features, 2 WM_ waves (each 64 x BN/2), NS stages.
+template <int BN, int EPI, class OutT, int NS, int BM_, int WM_>
+__global__ __launch_bounds__(128 * WM_, 512 / (128 * WM_)) void gemm_dma_kernel(const GemmArgs a) {
   typedef __bf16 T;
   constexpr int BK = 64;
-  constexpr int XI = BM / 32, WI = BN / 32;  // 8-row loads per wave per stage
-  constexpr int SX = BM * BK, SW = BN * BK;  // elements per X / W stage
+  constexpr int NW = 2 * WM_;                         // waves
+  constexpr int XR = BM_ / NW, WR = BN / NW;          // stage rows each wave loads
+  constexpr int XI = XR / 8, WI = WR / 8;             // 8-row loads per wave per stage
+  static_assert(XI >= 1 && WI >= 1 && BM_ == 64 * WM_, "tile geometry");
+  constexpr int SX = BM_ * BK, SW = BN * BK;          // elements per X / W stage
   constexpr int OPE = NS * (SX + SW);
-  constexpr int EPE = (epi_stage_bytes<BN, OutT>() + 1) / 2;
+  constexpr int EPE = (epi_stage_bytes<BN, OutT, BM_>() + 1) / 2;
   // X stages at stg + b SX, W stages at stg + NS SX + b SW; the epilogue
   // reuses the whole array
   __shared__ __attribute__((aligned(16))) T stg[OPE > EPE ? OPE : EPE];
@@ -693,7 +702,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_dma_kernel(const GemmArgs a) {
   const int L = blockIdx.x;
   const int xcd = L & 7, per = ntiles >> 3, rem = ntiles & 7;
   const int tile = xcd * per + (xcd < rem ? xcd : rem) + (L >> 3);
-  const int m0 = (tile / gn) * BM;
+  const int m0 = (tile / gn) * BM_;
   const int n0 = (tile - (tile / gn) * gn) * BN;
   const int Mlive = a.dyn_m ? *a.dyn_m : a.M;
   const int nreq = a.dyn_nreq ? *a.dyn_nreq : a.nreq;
@@ -706,29 +715,29 @@ __global__ __launch_bounds__(NT, 2) void gemm_dma_kernel(const GemmArgs a) {
       __builtin_amdgcn_make_buffer_rsrc((void*)a.W, (short)0, a.N * a.K * (int)sizeof(T), 0x00020000);
   const __amdgpu_buffer_rsrc_t xrs =
       __builtin_amdgcn_make_buffer_rsrc((void*)a.X, (short)0, Mlive * a.K * (int)sizeof(T), 0x00020000);
-  // wave w fills rows w*BM/4 .. (w+1)*BM/4 - 1 of the X stage (likewise for
-  // W), 8 rows per load; lane L fills slot L % 8 of row L / 8 of its group
+  // wave w fills rows w XR .. (w+1) XR - 1 of the X stage (likewise for W),
+  // 8 rows per load; lane L fills slot L % 8 of row L / 8 of its group
   int xo[XI], wo[WI];
 #pragma unroll
   for (int j = 0; j < XI; ++j) {
-    const int rr = wave * (BM / 4) + 8 * j + (lane >> 3);
+    const int rr = wave * XR + 8 * j + (lane >> 3);
     xo[j] = ((m0 + rr) * a.K + (((lane & 7) ^ ((rr >> 1) & 7)) << 3)) * (int)sizeof(T);
   }
 #pragma unroll
   for (int j = 0; j < WI; ++j) {
-    const int rr = wave * (BN / 4) + 8 * j + (lane >> 3);
+    const int rr = wave * WR + 8 * j + (lane >> 3);
     wo[j] = ((n0 + rr) * a.K + (((lane & 7) ^ ((rr >> 1) & 7)) << 3)) * (int)sizeof(T);
   }
 #define REVO_GD_FETCH(kt_, buf_)                                                                         \
   do {                                                                                                   \
     _Pragma("unroll") for (int j = 0; j < XI; ++j)                                                       \
-      dma16(xrs, stg + (buf_) * SX + (wave * (BM / 4) + 8 * j) * 64, xo[j], (kt_) * BK * (int)sizeof(T));  \
+      dma16(xrs, stg + (buf_) * SX + (wave * XR + 8 * j) * 64, xo[j], (kt_) * BK * (int)sizeof(T));        \
     _Pragma("unroll") for (int j = 0; j < WI; ++j)                                                       \
-      dma16(wrs, stg + NS * SX + (buf_) * SW + (wave * (BN / 4) + 8 * j) * 64, wo[j],                    \
+      dma16(wrs, stg + NS * SX + (buf_) * SW + (wave * WR + 8 * j) * 64, wo[j],                          \
             (kt_) * BK * (int)sizeof(T));                                                                 \
   } while (0)
 
-  const int wn = wave >> 1, wm = wave & 1;
+  const int wn = wave / WM_, wm = wave % WM_;
   f32x16 acc[BN / 64][2];
 #pragma unroll
   for (int i = 0; i < BN / 64; ++i) { acc[i][0] = f32x16{}; acc[i][1] = f32x16{}; }
@@ -755,7 +764,8 @@ __global__ __launch_bounds__(NT, 2) void gemm_dma_kernel(const GemmArgs a) {
   }
   wait_vm<0>();  // no load still writes LDS when the epilogue reuses it
 #undef REVO_GD_FETCH
-  gemm_epilogue_staged<OpBF16, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, tid, reinterpret_cast<uint8_t*>(stg), cols);
+  gemm_epilogue_staged<OpBF16, BN, EPI, OutT, BM_, WM_>(a, acc, m0, n0, Mlive, nreq, tid, reinterpret_cast<uint8_t*>(stg),
+                                                         cols);
 }
 
 template <class Op, int EPI, int XM, class OutT>
@@ -765,13 +775,17 @@ int launch_t(const GemmArgs& a, hipStream_t s) {
   // whole row tiles, stay below 2 GiB
   const long long esz = sizeof(typename Op::T);
   if ((long long)gm * BM * a.K * esz >= (1LL << 31) || (long long)a.N * a.K * esz >= (1LL << 31)) return -22;
-  // BF16 dense products (all but the head) take the LDS-ring kernel
+  // BF16 dense products (all but the head) take the LDS-ring kernel, two
+  // stages: 128 x 128 tiles over 4 waves, or, for 64-wide feature tiles,
+  // 256 x 64 tiles over 8 waves (measured faster on the decoder's products)
   if constexpr (XM == X_DENSE && sizeof(typename Op::T) == 2 && EPI != EPI_HEAD) {
     if (a.N % 128 == 0) {
-      gemm_dma_kernel<128, EPI, OutT, 2><<<dim3(gm * (a.N / 128)), NT, 0, s>>>(a);
+      gemm_dma_kernel<128, EPI, OutT, 2, 128, 2><<<dim3(gm * (a.N / 128)), 256, 0, s>>>(a);
       return hipGetLastError() == hipSuccess ? 0 : -5;
     }
-    gemm_dma_kernel<64, EPI, OutT, 2><<<dim3(gm * (a.N / 64)), NT, 0, s>>>(a);
+    const int gm2 = cdiv(a.M, 256);
+    if ((long long)gm2 * 256 * a.K * esz >= (1LL << 31)) return -22;
+    gemm_dma_kernel<64, EPI, OutT, 2, 256, 4><<<dim3(gm2 * (a.N / 64)), 512, 0, s>>>(a);
     return hipGetLastError() == hipSuccess ? 0 : -5;
   } else {
     // the gather loader's per-row token coordinates leave no registers for a

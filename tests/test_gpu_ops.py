@@ -30,7 +30,7 @@ def _as_op(a, prec):
 
 
 @pytest.mark.parametrize("prec", [FP32, BF16])
-@pytest.mark.parametrize("M,N,K", [(1, 64, 64), (300, 192, 384), (1000, 1152, 384), (257, 384, 1536), (77, 64, 192)])
+@pytest.mark.parametrize("M,N,K", [(1, 64, 64), (300, 192, 384), (1000, 1152, 384), (257, 384, 1536), (77, 64, 192), (200, 256, 320)])
 @pytest.mark.parametrize("epi", [0, 1, 2])
 def test_linear(prec, M, N, K, epi):
     x = RNG.standard_normal((M, K))
