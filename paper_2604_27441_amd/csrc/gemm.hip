@@ -11,6 +11,8 @@
 // Tile: 128 tokens x BN features x one K stage (128 bytes per operand row;
 // 64 for FP8), 4 waves in a 2 x 2 grid, LDS double-buffered, row pitch padded
 // by 16 bytes.
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace revo {
@@ -201,15 +203,38 @@ __global__ void tubelet_pack_kernel(const ReqDesc* __restrict__ reqs, int nreq_,
   }
 }
 
+// Bias (and, for FP8 operands, row-scale x activation-scale) values of the
+// output features one lane's accumulators hold: features
+// n0 + wn BN/2 + 32 ns + 8 g + 4 half + e.  Fetched as 16-byte vectors
+// (bias and scales are 16-byte aligned) all at once, early, instead of once
+// per group of four inside the epilogue.
+template <int BN>
+struct EpiCols {
+  f32x4 b[BN / 64][4], s[BN / 64][4];
+};
+template <class Op, int BN>
+__device__ __forceinline__ void epi_load_cols(const GemmArgs& a, int n0, int wn, int half, EpiCols<BN>& c) {
+  constexpr bool SC = sizeof(typename Op::T) == 1;
+  const float xsc = SC ? *a.xscale : 1.0f;
+#pragma unroll
+  for (int ns = 0; ns < BN / 64; ++ns)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int n = n0 + wn * (BN / 2) + ns * 32 + g * 8 + half * 4;
+      c.b[ns][g] = *reinterpret_cast<const f32x4*>(a.bias + n);
+      if constexpr (SC) c.s[ns][g] = *reinterpret_cast<const f32x4*>(a.wscale + n) * xsc;
+    }
+}
+
 // Epilogue of one 128 x BN tile straight from the accumulators (the head's
 // unpatchify scatter), for the tile's rows below Mlive.
 template <class Op, int BN, int EPI, class OutT>
 __device__ __forceinline__ void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[BN / 64][2], int m0, int n0,
-                                              int Mlive, int nreq, int lane, int wave) {
+                                              int Mlive, int nreq, int lane, int wave, const EpiCols<BN>& cols) {
   constexpr int NSUB = BN / 64;
+  constexpr bool SC = sizeof(typename Op::T) == 1;  // FP8 operands carry row scales
   const int half = lane >> 5, l32 = lane & 31;
   const int wn = wave >> 1, wm = wave & 1;
-  const float xsc = a.xscale ? *a.xscale : 1.0f;
   const float oinv = a.out_scale ? 1.0f / *a.out_scale : 1.0f;
 #pragma unroll
   for (int ms = 0; ms < 2; ++ms) {
@@ -235,13 +260,10 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[B
       for (int g = 0; g < 4; ++g) {
         const int n = n0 + wn * (BN / 2) + ns * 32 + g * 8 + half * 4;
         float v[4];
-        if (a.wscale) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = acc[ns][ms][4 * g + e] * (a.wscale[n + e] * xsc) + a.bias[n + e];
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = acc[ns][ms][4 * g + e] + a.bias[n + e];
-        }
+        for (int e = 0; e < 4; ++e)
+          v[e] = SC ? acc[ns][ms][4 * g + e] * cols.s[ns][g][e] + cols.b[ns][g][e]
+                    : acc[ns][ms][4 * g + e] + cols.b[ns][g][e];
         if (EPI == EPI_STORE) {
           Vec4<OutT>::store((OutT*)a.out + (size_t)m * a.ldo + n, v, oinv);
         } else if (EPI == EPI_GELU) {
@@ -276,17 +298,21 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[B
             for (int e = 0; e < 4; ++e) vt[(size_t)e * a.ldv] = out_cast<OutT>(v[e], 1.0f);
           }
         } else if (EPI == EPI_HEAD) {
+          // feature c = (py * 16 + px) * C + ch; the two channel counts get
+          // constant divisors
           const ReqDesc& d = a.reqs[r];
-          const int C = a.channels;
+          auto put = [&](auto Cc) {
+            constexpr int C = decltype(Cc)::value;
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int c = n + e;
-            const int py = c / (16 * C);
-            const int px = (c / C) & 15;
-            const int ch = c - (c / C) * C;
-            const int Y = 16 * ty + py, Xp = 16 * tx + px;
-            if (Y < d.H && Xp < d.W) d.pred[((size_t)Y * d.W + Xp) * C + ch] = v[e];
-          }
+            for (int e = 0; e < 4; ++e) {
+              const int c = n + e;
+              const int py = c / (16 * C), px = (c / C) & 15, ch = c % C;
+              const int Y = 16 * ty + py, Xp = 16 * tx + px;
+              if (Y < d.H && Xp < d.W) d.pred[((size_t)Y * d.W + Xp) * C + ch] = v[e];
+            }
+          };
+          if (a.channels == 3) put(std::integral_constant<int, 3>{});
+          else put(std::integral_constant<int, 1>{});
         }
       }
     }
@@ -296,29 +322,6 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[B
 // LDS bytes of the staged epilogue: a row-major [BM][BN] tile of the output
 // type, or for the V part of the QKV product a transposed [BN][BM] tile
 // (rows padded by 16 bytes).
-// Bias (and, for FP8 operands, row-scale x activation-scale) values of the
-// output features one lane's accumulators hold: features
-// n0 + wn BN/2 + 32 ns + 8 g + 4 half + e.  Fetched as 16-byte vectors
-// (bias and scales are 16-byte aligned) all at once, early, instead of once
-// per group of four inside the epilogue.
-template <int BN>
-struct EpiCols {
-  f32x4 b[BN / 64][4], s[BN / 64][4];
-};
-template <class Op, int BN>
-__device__ __forceinline__ void epi_load_cols(const GemmArgs& a, int n0, int wn, int half, EpiCols<BN>& c) {
-  constexpr bool SC = sizeof(typename Op::T) == 1;
-  const float xsc = SC ? *a.xscale : 1.0f;
-#pragma unroll
-  for (int ns = 0; ns < BN / 64; ++ns)
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const int n = n0 + wn * (BN / 2) + ns * 32 + g * 8 + half * 4;
-      c.b[ns][g] = *reinterpret_cast<const f32x4*>(a.bias + n);
-      if constexpr (SC) c.s[ns][g] = *reinterpret_cast<const f32x4*>(a.wscale + n) * xsc;
-    }
-}
-
 template <int BN, class OutT, int BM_ = BM>
 constexpr int epi_stage_bytes() {
   return BM_ * (BN * (int)sizeof(OutT) + 16) > BN * (BM_ * (int)sizeof(OutT) + 16)
@@ -617,13 +620,14 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
 #undef REVO_GEMM_STORE
 #undef REVO_GEMM_COMPUTE
 
-  if constexpr (EPI == EPI_HEAD) {
-    gemm_epilogue<Op, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, lane, wave);
-  } else {
-    EpiCols<BN> cols;
-    epi_load_cols<Op, BN>(a, n0, wn, half, cols);
+  // bias (and scale) vectors fetched together after the K loop: this
+  // kernel has no registers to hold them through it
+  EpiCols<BN> cols;
+  epi_load_cols<Op, BN>(a, n0, wn, half, cols);
+  if constexpr (EPI == EPI_HEAD)
+    gemm_epilogue<Op, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, lane, wave, cols);
+  else
     gemm_epilogue_staged<Op, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, tid, smem, cols);
-  }
 }
 
 
@@ -854,6 +858,8 @@ int launch_gemm(Prec prec, int epi, int xmode, const GemmArgs& a, hipStream_t s)
   if (a.N % 64 != 0) return -22;
   // the epilogue reads bias and row scales as 16-byte vectors
   if (((uintptr_t)a.bias | (uintptr_t)a.wscale) & 15) return -22;
+  // the head's unpatchify knows RGB and depth pixels
+  if (epi == EPI_HEAD && a.channels != 3 && a.channels != 1) return -22;
   if (prec == P_BF16) {
     if (a.K % OpBF16::BK != 0) return -22;
     return launch_op<OpBF16>(epi, xmode, a, s);
