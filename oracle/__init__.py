@@ -8,6 +8,8 @@ which holds none of the method's arithmetic.
 Every function is a plain, slow, direct statement of one step of the method
 (Sec. 3.4.1 architecture, App. B.1 design differences, App. B.3 k and T), in
 float64 unless a rounding emulation is requested for error budgeting.
+``metrics`` holds the frame quality metrics and the per-modality training
+losses (Sec. 3.4.2, Sec. 4, Sec. 5.1).
 """
 from .model import (
     Arch, unpack_weights, normalise, zero_fill, sequence_frames, tubelet_vectors,
@@ -15,10 +17,16 @@ from .model import (
     self_attention, transformer_block, forward, place_target_slot, recover, composite, Rounding,
     bf16_round, e4m3_round, FP8Rounding, AbsMaxRecorder,
 )
+from .metrics import (
+    normalise_frame, gaussian_window, gaussian_filter_valid, ssim_map, ssim, total_variation, edge_loss,
+    frame_metrics, METRIC_KEYS,
+)
 
 __all__ = [
     "Arch", "unpack_weights", "normalise", "zero_fill", "sequence_frames", "tubelet_vectors",
     "sinusoid", "positional_embedding", "linear", "layer_norm", "gelu", "attention_head",
     "self_attention", "transformer_block", "forward", "place_target_slot", "recover", "composite", "Rounding",
     "bf16_round", "e4m3_round", "FP8Rounding", "AbsMaxRecorder",
+    "normalise_frame", "gaussian_window", "gaussian_filter_valid", "ssim_map", "ssim", "total_variation",
+    "edge_loss", "frame_metrics", "METRIC_KEYS",
 ]
