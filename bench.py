@@ -26,6 +26,12 @@ sys.path.insert(0, ROOT)
 METRIC = "recovered RGB-D frames/sec at 1280x720 (BF16 vs FP32) + p50/p99 latency"
 BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 MFMA
 FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 matrix
+HBM_PEAK_GBPS = 8000.0      # MI355X HBM3E
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (packed FMA; unpacked code reaches half)
+# frame metrics, per pixel and channel, separable SSIM: 5 moments x 11 taps
+# along rows and along columns (220 FMA = 220 FLOP x 2), 3 products, about 15
+# for the SSIM quotient and 12 for the pixel terms
+METRIC_FLOP_PER_SAMPLE = 2 * 110 + 3 + 15 + 12
 
 
 def model_flop_per_request(N, P, C, T=2, De=384, Dd=192, ne=12, nd=4):
@@ -91,7 +97,53 @@ def run_form(precision, reqs, blobs, steps, warmup, log, one_stream=False, profi
     lat.sort()
     pct = lambda p: lat[min(len(lat) - 1, int(round(p / 100.0 * (len(lat) - 1))))]
     return dict(seconds=dt, pairs=steps * len(reqs), ms_per_step=1e3 * dt / steps,
-                p50_ms=pct(50), p99_ms=pct(99), stats=st)
+                p50_ms=pct(50), p99_ms=pct(99), stats=st, outputs=outs)
+
+
+def metrics_bench(reqs, outs, log, iters=20):
+    """Quality metrics and training losses of the recovered frames against the
+    clean targets through revo_op_frame_metrics (SSIM, PSNR, L_RGB, L_Depth;
+    Sec. 3.4.2, Sec. 5.1), timed with HIP events on the launching stream.
+    Algorithmic traffic: each prediction and ground-truth byte read once."""
+    import numpy as np
+    import torch
+    from paper_2604_27441_amd import lib
+    B, H, W = len(reqs), reqs[0]["height"], reqs[0]["width"]
+    res = {}
+    for name, kind, C, pred, gt in (
+            ("rgb", 0, 3, torch.stack([o[0] for o in outs]),
+             torch.from_numpy(np.stack([r["rgb_clean"] for r in reqs])).cuda()),
+            ("depth", 1, 1, torch.stack([o[1] for o in outs]),
+             torch.from_numpy(np.stack([r["depth_clean"] for r in reqs]).view(np.int16)).cuda())):
+        assert pred.shape == gt.shape and pred.is_contiguous() and gt.is_contiguous()
+        assert pred.numel() == B * H * W * C and pred.element_size() == gt.element_size()
+        o = torch.empty((B, 8), dtype=torch.float64, device="cuda")
+        call = lambda: lib.revo_op_frame_metrics(kind, pred.data_ptr(), gt.data_ptr(), B, H, W, C, o.data_ptr(), None)
+        for _ in range(3):
+            assert call() == 0
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(iters):
+            call()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / iters
+        nbytes = 2 * pred.numel() * pred.element_size()
+        flop = METRIC_FLOP_PER_SAMPLE * B * H * W * C
+        v = o.cpu().numpy().mean(axis=0)
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        tf = flop / (ms * 1e-3) / 1e12
+        res[name] = {"ms_per_call": ms, "frames": B, "bytes_per_call": nbytes, "achieved_GBps": gbs,
+                     "hbm_frac": gbs / HBM_PEAK_GBPS, "flop_per_call": flop,
+                     "roofline": {"bound": "alu", "achieved": tf, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": tf / FP32_VECTOR_PEAK_TFLOPS},
+                     "ssim": float(v[4]), "psnr_db": float(v[5]), "loss": float(v[6] if name == "rgb" else v[7])}
+        log(f"frame metrics {name}: {ms * 1e3:.1f} us per call of {B} frames, {gbs:.0f} GB/s; "
+            f"SSIM {v[4]:.4f}, PSNR {v[5]:.2f} dB")
+    res["note"] = ("recovered frames of the timed BF16 run against the clean targets; the weights are random, so "
+                   "the quality values only exercise the path; loss = L_RGB for rgb, L_Depth for depth")
+    return res
 
 
 SERVE_RES = [(480, 640)] * 16 + [(540, 960)] * 16 + [(720, 1280)] * 32   # 1 : 1 : 2
@@ -433,6 +485,7 @@ def main():
     # stream so that kernels do not overlap, gives the per-class split
     bf = run_form(1, reqs, blobs, args.steps, args.warmup, log, args.one_stream)
     log(f"bf16: {bf['ms_per_step']:.2f} ms/step")
+    fm = metrics_bench(reqs, bf.pop("outputs"), log)
     split = run_form(1, reqs, blobs, 3, 1, log, True, profile=True)
     sst = split["stats"]
     fp = None
@@ -492,6 +545,7 @@ def main():
         },
         "linear_tflops": sst["gemm_flop"] / (sst["gemm_ms"] * 1e-3) / 1e12 if sst["gemm_ms"] > 0 else 0.0,
     }
+    out["frame_metrics"] = fm
     if fp:
         fv = fp["pairs"] / fp["seconds"]
         fst = fp["stats"]

@@ -62,6 +62,30 @@ int revo_op_attention(int precision, const void *q, const void *k, const void *v
  * saturating at +-448). */
 int revo_op_convert(int precision, const float *src, void *dst, long long n, void *stream);
 
+/* Frame element types for revo_op_frame_metrics. */
+enum revo_frame_kind {
+  REVO_FRAME_U8 = 0,  /* u8, normalised by 1/255 (RGB) */
+  REVO_FRAME_U16 = 1, /* u16 depth in mm, normalised by 1/4000; channels must be 1 */
+  REVO_FRAME_F32 = 2  /* float, already normalised */
+};
+
+/* Quality metrics and training losses of `batch` predicted frames against
+ * their ground truth (SSIM and PSNR of Sec. 5.1; L_RGB = MSE + 0.01 TV and
+ * L_Depth = 0.1 L1 + L_edge + (1 - SSIM) of the Sec. 3.4.2 loss equations
+ * with the Sec. 4 weights).  pred and gt: device pointers, batch frames of
+ * height x width x channels elements each, contiguous (HWC).  All values use
+ * normalised pixels (data range 1).  SSIM: 11 x 11 Gaussian window, sigma 1.5,
+ * K1 0.01, K2 0.03, valid windows only, mean over positions and channels.
+ * TV: mean |horizontal forward difference| + mean |vertical one| of pred.
+ * L_edge: mean over pixels with both forward differences of
+ * | |grad pred| - |grad gt| |.  out: device pointer to batch x 8 doubles,
+ * per frame [mse, l1, tv, edge, ssim, psnr, l_rgb, l_depth]
+ * (psnr = 10 log10(1 / mse), +inf for identical frames); it is also the
+ * accumulator, so its previous contents are lost.  Requires height, width
+ * >= 11 and 1 <= channels <= 4.  Runs asynchronously on `stream`. */
+int revo_op_frame_metrics(int kind, const void *pred, const void *gt, int batch, int height, int width,
+                          int channels, double *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,6 +16,7 @@ REVO_DEVICE_PTRS, REVO_HOLD = 0x1, 0x2
 REVO_CFG_SHED, REVO_CFG_PROFILE, REVO_CFG_ONE_STREAM, REVO_CFG_GRAPHS = 0x1, 0x2, 0x4, 0x8
 REVO_CFG_PROFILE_ATTN = 0x10
 REVO_DONE, REVO_SHED, REVO_FAILED = 0, 1, 2
+REVO_FRAME_U8, REVO_FRAME_U16, REVO_FRAME_F32 = 0, 1, 2
 
 
 class RevoConfig(C.Structure):
@@ -76,6 +77,8 @@ _sigs = {
     "revo_op_attention": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
                                     C.c_int, C.c_void_p]),
     "revo_op_convert": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_longlong, C.c_void_p]),
+    "revo_op_frame_metrics": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
+                                        C.c_void_p, C.c_void_p]),
 }
 for _name, (_res, _args) in _sigs.items():
     _f = getattr(lib, _name)

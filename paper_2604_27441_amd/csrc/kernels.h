@@ -108,6 +108,10 @@ int launch_scales_from_absmax(const unsigned* absmax, float* scale, int n, hipSt
 int launch_composite(const ReqDesc* reqs, int nreq, int channels, int max_pixels, int composite, hipStream_t s,
                      const int* dyn_nreq = nullptr);
 int launch_convert(Prec prec, const float* src, void* dst, long long n, hipStream_t s);
+// Frame metrics of B prediction / ground-truth frames (kind 0 u8, 1 u16, 2
+// float; H x W x C each, contiguous); out [B][8] doubles.
+int launch_frame_metrics(int kind, const void* pred, const void* gt, int B, int H, int W, int C, double* out,
+                         hipStream_t s);
 int launch_fill_zero(void* p, long long bytes, hipStream_t s);
 
 // row -> request lookup over the ascending tok_off (or head_off) values

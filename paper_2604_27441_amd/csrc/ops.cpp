@@ -115,4 +115,12 @@ int revo_op_convert(int precision, const float* src, void* dst, long long n, voi
   return launch_convert(p, src, dst, n, (hipStream_t)stream);
 }
 
+int revo_op_frame_metrics(int kind, const void* pred, const void* gt, int batch, int height, int width,
+                          int channels, double* out, void* stream) {
+  if (kind < REVO_FRAME_U8 || kind > REVO_FRAME_F32 || batch <= 0 || height < 11 || width < 11 || channels < 1 ||
+      channels > 4 || (kind == REVO_FRAME_U16 && channels != 1) || !pred || !gt || !out)
+    return REVO_EINVAL;
+  return launch_frame_metrics(kind, pred, gt, batch, height, width, channels, out, (hipStream_t)stream);
+}
+
 }  // extern "C"
