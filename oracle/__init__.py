@@ -9,7 +9,8 @@ Every function is a plain, slow, direct statement of one step of the method
 (Sec. 3.4.1 architecture, App. B.1 design differences, App. B.3 k and T), in
 float64 unless a rounding emulation is requested for error budgeting.
 ``metrics`` holds the frame quality metrics and the per-modality training
-losses (Sec. 3.4.2, Sec. 4, Sec. 5.1).
+losses (Sec. 3.4.2, Sec. 4, Sec. 5.1); ``render`` the RGB-D unprojection and
+z-buffered rendering of a new view (Sec. 2, Sec. 5).
 """
 from .model import (
     Arch, unpack_weights, normalise, zero_fill, sequence_frames, tubelet_vectors,
@@ -21,6 +22,7 @@ from .metrics import (
     normalise_frame, gaussian_window, gaussian_filter_valid, ssim_map, ssim, total_variation, edge_loss,
     frame_metrics, METRIC_KEYS,
 )
+from .render import unproject, project, render_view
 
 __all__ = [
     "Arch", "unpack_weights", "normalise", "zero_fill", "sequence_frames", "tubelet_vectors",
@@ -28,5 +30,5 @@ __all__ = [
     "self_attention", "transformer_block", "forward", "place_target_slot", "recover", "composite", "Rounding",
     "bf16_round", "e4m3_round", "FP8Rounding", "AbsMaxRecorder",
     "normalise_frame", "gaussian_window", "gaussian_filter_valid", "ssim_map", "ssim", "total_variation",
-    "edge_loss", "frame_metrics", "METRIC_KEYS",
+    "edge_loss", "frame_metrics", "METRIC_KEYS", "unproject", "project", "render_view",
 ]
