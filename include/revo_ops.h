@@ -86,6 +86,34 @@ enum revo_frame_kind {
 int revo_op_frame_metrics(int kind, const void *pred, const void *gt, int batch, int height, int width,
                           int channels, double *out, void *stream);
 
+/* RGB-D unprojection: an RGB-D frame projected into Cartesian space (Sec. 2),
+ * the first half of the receiver's rendering step (Sec. 5).  depth: device,
+ * batch x height x width u16 z in mm (0 = no measurement).  intrinsics: host,
+ * 4 floats (fx, fy, cx, cy) in pixels, pixel centres at integer coordinates.
+ * points: device, 16-byte aligned, batch x height x width float4
+ * (X, Y, Z in mm, valid 1 or 0) with X = (u - cx) Z / fx, Y = (v - cy) Z / fy.
+ * Requires batch and height <= 65535. */
+int revo_op_unproject(const unsigned short *depth, int batch, int height, int width, const float *intrinsics,
+                      float *points, void *stream);
+
+/* Z-buffered rendering of organised point clouds (from revo_op_unproject)
+ * into a new view, the second half of the rendering step (Sec. 5).  Each
+ * valid point moves by X' = R X + t (pose: host, 12 floats, R|t row-major
+ * 3 x 4, t in mm), projects with the target intrinsics (host, fx, fy, cx, cy)
+ * to the nearest target pixel centre, and is dropped when Z' <= 0 or it falls
+ * outside out_height x out_width.  Each target pixel shows the point of
+ * smallest Z' (ties to the lower point index): its colour from rgb (device,
+ * batch x height x width x 3 u8, the cloud's source frames) and Z' rounded
+ * half to even to mm (u16, clamped); pixels no point reaches are 0.  zbuf:
+ * device workspace of batch x out_height x out_width 64-bit words, 8-byte
+ * aligned; on return it holds per pixel (bits of Z') << 32 | point index, or
+ * all ones.  rgb_out: device, batch x out_height x out_width x 3 u8;
+ * depth_out: device, batch x out_height x out_width u16.  Requires
+ * height x width < 2^32 and batch, height, out_height <= 65535. */
+int revo_op_render_view(const float *points, const unsigned char *rgb, int batch, int height, int width,
+                        const float *pose, const float *intrinsics, int out_height, int out_width,
+                        unsigned long long *zbuf, unsigned char *rgb_out, unsigned short *depth_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

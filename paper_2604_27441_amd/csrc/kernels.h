@@ -112,6 +112,13 @@ int launch_convert(Prec prec, const float* src, void* dst, long long n, hipStrea
 // float; H x W x C each, contiguous); out [B][8] doubles.
 int launch_frame_metrics(int kind, const void* pred, const void* gt, int B, int H, int W, int C, double* out,
                          hipStream_t s);
+// RGB-D unprojection (depth [B][H][W] u16 mm -> float4 points [B][H][W]) and
+// z-buffered rendering of a new view (pose: R|t row-major 3 x 4, intrinsics
+// fx, fy, cx, cy; both host arrays).
+int launch_unproject(const uint16_t* depth, int B, int H, int W, const float* intr, float* pts, hipStream_t s);
+int launch_render_view(const float* pts, const uint8_t* rgb, int B, int H, int W, const float* pose,
+                       const float* intr, int Ho, int Wo, unsigned long long* zbuf, uint8_t* rgb_out,
+                       uint16_t* depth_out, hipStream_t s);
 int launch_fill_zero(void* p, long long bytes, hipStream_t s);
 
 // row -> request lookup over the ascending tok_off (or head_off) values

@@ -123,4 +123,20 @@ int revo_op_frame_metrics(int kind, const void* pred, const void* gt, int batch,
   return launch_frame_metrics(kind, pred, gt, batch, height, width, channels, out, (hipStream_t)stream);
 }
 
+int revo_op_unproject(const unsigned short* depth, int batch, int height, int width, const float* intrinsics,
+                      float* points, void* stream) {
+  if (batch <= 0 || height <= 0 || width <= 0 || !depth || !intrinsics || !points) return REVO_EINVAL;
+  return launch_unproject(depth, batch, height, width, intrinsics, points, (hipStream_t)stream);
+}
+
+int revo_op_render_view(const float* points, const unsigned char* rgb, int batch, int height, int width,
+                        const float* pose, const float* intrinsics, int out_height, int out_width,
+                        unsigned long long* zbuf, unsigned char* rgb_out, unsigned short* depth_out, void* stream) {
+  if (batch <= 0 || height <= 0 || width <= 0 || out_height <= 0 || out_width <= 0 || !points || !rgb || !pose ||
+      !intrinsics || !zbuf || !rgb_out || !depth_out)
+    return REVO_EINVAL;
+  return launch_render_view(points, rgb, batch, height, width, pose, intrinsics, out_height, out_width, zbuf, rgb_out,
+                            depth_out, (hipStream_t)stream);
+}
+
 }  // extern "C"
