@@ -632,12 +632,13 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
 
 
 // ---------------------------------------------------------------------------
-// BF16 dense form: operand stages go from HBM straight into LDS (buffer loads
-// with the LDS as destination) in a ring of NS stages, so no registers hold
-// stages in flight and no LDS stores are issued.  LDS rows are 128 bytes,
-// unpadded; 16-byte chunk c of row r sits in slot c ^ ((r >> 1) & 7), which
-// spreads the 32 rows one fragment read touches over all banks.
-__device__ __forceinline__ int gswz(int r, int c) { return r * 64 + ((c ^ ((r >> 1) & 7)) << 3); }
+// Dense BF16 and FP8 form: operand stages go from HBM straight into LDS
+// (buffer loads with the LDS as destination) in a ring of NS stages, so no
+// registers hold stages in flight and no LDS stores are issued.  A stage row
+// is 128 bytes of K (64 BF16 or 128 E4M3 values), unpadded; 16-byte chunk c
+// of row r sits at byte gswz(r, c), slot c ^ ((r >> 1) & 7), which spreads the
+// 32 rows one fragment read touches over all banks.
+__device__ __forceinline__ int gswz(int r, int c) { return r * 128 + ((c ^ ((r >> 1) & 7)) << 4); }
 
 // One 16-byte-per-lane buffer load into LDS: lane L's bytes land at lds + 16 L
 // (lds is wave-uniform).  Kept out of line of the kernel template's body: the
@@ -653,50 +654,66 @@ __device__ __forceinline__ void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N_ & 15) | ((N_ >> 4) << 14) | (0x7 << 4) | (0xF << 8));
 }
 
-// One 64-deep K stage from LDS into the accumulators: all 16 fragment reads,
-// then the 16 products.  The operand pointers are restrict-qualified, so the
-// reads carry alias scopes and the compiler does not hold them behind the
-// ring's loads still in flight (the kernel orders those with vmcnt waits and
-// barriers itself).
-template <int BN>
-__device__ __forceinline__ void gemm_dma_stage(const __bf16* __restrict__ xb, const __bf16* __restrict__ wb,
+// One 128-byte K stage from LDS into the accumulators: all 16 fragment
+// reads, then the products.  BF16: four 32x32x16 steps, lane half h taking
+// chunk 4h + s of step s.  FP8: two 32x32x64 steps, lane half h taking chunks
+// 4s + 2h and 4s + 2h + 1 (32 consecutive k, the layout of the register-staged
+// kernel).  The operand pointers are restrict-qualified, so the reads carry
+// alias scopes and the compiler does not hold them behind the ring's loads
+// still in flight (the kernel orders those with vmcnt waits and barriers).
+template <class Op, int BN>
+__device__ __forceinline__ void gemm_dma_stage(const uint8_t* __restrict__ xb, const uint8_t* __restrict__ wb,
                                                f32x16 (&acc)[BN / 64][2], int wn, int wm, int half, int l32) {
   constexpr int NSUB = BN / 64;
   uint4 wf[4][NSUB], xf[4][2];
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
+    // chunk read at s: BF16 step s; FP8 step s / 2, part s % 2
+    const int ch = sizeof(typename Op::T) == 2 ? half * 4 + s : (s >> 1) * 4 + half * 2 + (s & 1);
 #pragma unroll
     for (int ns = 0; ns < NSUB; ++ns)
-      wf[s][ns] = *reinterpret_cast<const uint4*>(wb + gswz(wn * (BN / 2) + ns * 32 + l32, half * 4 + s));
+      wf[s][ns] = *reinterpret_cast<const uint4*>(wb + gswz(wn * (BN / 2) + ns * 32 + l32, ch));
 #pragma unroll
     for (int ms = 0; ms < 2; ++ms)
-      xf[s][ms] = *reinterpret_cast<const uint4*>(xb + gswz(wm * 64 + ms * 32 + l32, half * 4 + s));
+      xf[s][ms] = *reinterpret_cast<const uint4*>(xb + gswz(wm * 64 + ms * 32 + l32, ch));
   }
   __builtin_amdgcn_sched_barrier(0);
+  if constexpr (sizeof(typename Op::T) == 2) {
 #pragma unroll
-  for (int s = 0; s < 4; ++s)
+    for (int s = 0; s < 4; ++s)
 #pragma unroll
-    for (int ns = 0; ns < NSUB; ++ns)
+      for (int ns = 0; ns < NSUB; ++ns)
 #pragma unroll
-      for (int ms = 0; ms < 2; ++ms)
-        OpBF16::mma(acc[ns][ms], __builtin_bit_cast(bf16x8, wf[s][ns]), __builtin_bit_cast(bf16x8, xf[s][ms]));
+        for (int ms = 0; ms < 2; ++ms)
+          Op::mma(acc[ns][ms], __builtin_bit_cast(bf16x8, wf[s][ns]), __builtin_bit_cast(bf16x8, xf[s][ms]));
+  } else {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int ns = 0; ns < NSUB; ++ns)
+#pragma unroll
+        for (int ms = 0; ms < 2; ++ms)
+          Op::mma(acc[ns][ms], frag_fp8(wf[2 * s][ns], wf[2 * s + 1][ns]), frag_fp8(xf[2 * s][ms], xf[2 * s + 1][ms]));
+  }
 }
 
-// Tile BM_ tokens x BN features, 2 WM_ waves (each 64 x BN/2), NS stages.
-template <int BN, int EPI, class OutT, int NS, int BM_, int WM_>
+// Tile BM_ tokens x BN features, 2 WM_ waves (each 64 x BN/2), NS stages of
+// 128 bytes of K.
+template <class Op, int BN, int EPI, class OutT, int NS, int BM_, int WM_>
 __global__ __launch_bounds__(128 * WM_, 512 / (128 * WM_)) void gemm_dma_kernel(const GemmArgs a) {
-  typedef __bf16 T;
-  constexpr int BK = 64;
+  typedef typename Op::T T;
+  constexpr int BK = 128 / (int)sizeof(T);  // K per stage
+  constexpr int E = 16 / (int)sizeof(T);    // K per 16-byte chunk
   constexpr int NW = 2 * WM_;                         // waves
   constexpr int XR = BM_ / NW, WR = BN / NW;          // stage rows each wave loads
   constexpr int XI = XR / 8, WI = WR / 8;             // 8-row loads per wave per stage
   static_assert(XI >= 1 && WI >= 1 && BM_ == 64 * WM_, "tile geometry");
-  constexpr int SX = BM_ * BK, SW = BN * BK;          // elements per X / W stage
-  constexpr int OPE = NS * (SX + SW);
-  constexpr int EPE = (epi_stage_bytes<BN, OutT, BM_>() + 1) / 2;
+  constexpr int SX = BM_ * 128, SW = BN * 128;        // bytes per X / W stage
+  constexpr int OPB = NS * (SX + SW);
+  constexpr int EPB = epi_stage_bytes<BN, OutT, BM_>();
   // X stages at stg + b SX, W stages at stg + NS SX + b SW; the epilogue
   // reuses the whole array
-  __shared__ __attribute__((aligned(16))) T stg[OPE > EPE ? OPE : EPE];
+  __shared__ __attribute__((aligned(16))) uint8_t stg[OPB > EPB ? OPB : EPB];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
@@ -725,20 +742,19 @@ __global__ __launch_bounds__(128 * WM_, 512 / (128 * WM_)) void gemm_dma_kernel(
 #pragma unroll
   for (int j = 0; j < XI; ++j) {
     const int rr = wave * XR + 8 * j + (lane >> 3);
-    xo[j] = ((m0 + rr) * a.K + (((lane & 7) ^ ((rr >> 1) & 7)) << 3)) * (int)sizeof(T);
+    xo[j] = ((m0 + rr) * a.K + ((lane & 7) ^ ((rr >> 1) & 7)) * E) * (int)sizeof(T);
   }
 #pragma unroll
   for (int j = 0; j < WI; ++j) {
     const int rr = wave * WR + 8 * j + (lane >> 3);
-    wo[j] = ((n0 + rr) * a.K + (((lane & 7) ^ ((rr >> 1) & 7)) << 3)) * (int)sizeof(T);
+    wo[j] = ((n0 + rr) * a.K + ((lane & 7) ^ ((rr >> 1) & 7)) * E) * (int)sizeof(T);
   }
 #define REVO_GD_FETCH(kt_, buf_)                                                                         \
   do {                                                                                                   \
     _Pragma("unroll") for (int j = 0; j < XI; ++j)                                                       \
-      dma16(xrs, stg + (buf_) * SX + (wave * XR + 8 * j) * 64, xo[j], (kt_) * BK * (int)sizeof(T));        \
+      dma16(xrs, stg + (buf_) * SX + (wave * XR + 8 * j) * 128, xo[j], (kt_) * 128);                      \
     _Pragma("unroll") for (int j = 0; j < WI; ++j)                                                       \
-      dma16(wrs, stg + NS * SX + (buf_) * SW + (wave * WR + 8 * j) * 64, wo[j],                          \
-            (kt_) * BK * (int)sizeof(T));                                                                 \
+      dma16(wrs, stg + NS * SX + (buf_) * SW + (wave * WR + 8 * j) * 128, wo[j], (kt_) * 128);            \
   } while (0)
 
   const int wn = wave / WM_, wm = wave % WM_;
@@ -746,7 +762,7 @@ __global__ __launch_bounds__(128 * WM_, 512 / (128 * WM_)) void gemm_dma_kernel(
 #pragma unroll
   for (int i = 0; i < BN / 64; ++i) { acc[i][0] = f32x16{}; acc[i][1] = f32x16{}; }
   EpiCols<BN> cols;  // in flight during the K loop
-  epi_load_cols<OpBF16, BN>(a, n0, wn, half, cols);
+  epi_load_cols<Op, BN>(a, n0, wn, half, cols);
 
   // stage k goes to buffer k % NS; loads past the last stage re-read it
   // into a free buffer, which keeps the wait counts static
@@ -762,14 +778,13 @@ __global__ __launch_bounds__(128 * WM_, 512 / (128 * WM_)) void gemm_dma_kernel(
       // stage loads)
       asm volatile("s_barrier" ::: "memory");
       REVO_GD_FETCH(kt + NS - 1 < KT ? kt + NS - 1 : KT - 1, (b + NS - 1) % NS);
-      gemm_dma_stage<BN>(stg + b * SX, stg + NS * SX + b * SW, acc, wn, wm, half, l32);
+      gemm_dma_stage<Op, BN>(stg + b * SX, stg + NS * SX + b * SW, acc, wn, wm, half, l32);
       if (++kt >= KT) break;
     }
   }
   wait_vm<0>();  // no load still writes LDS when the epilogue reuses it
 #undef REVO_GD_FETCH
-  gemm_epilogue_staged<OpBF16, BN, EPI, OutT, BM_, WM_>(a, acc, m0, n0, Mlive, nreq, tid, reinterpret_cast<uint8_t*>(stg),
-                                                         cols);
+  gemm_epilogue_staged<Op, BN, EPI, OutT, BM_, WM_>(a, acc, m0, n0, Mlive, nreq, tid, stg, cols);
 }
 
 template <class Op, int EPI, int XM, class OutT>
@@ -779,18 +794,25 @@ int launch_t(const GemmArgs& a, hipStream_t s) {
   // whole row tiles, stay below 2 GiB
   const long long esz = sizeof(typename Op::T);
   if ((long long)gm * BM * a.K * esz >= (1LL << 31) || (long long)a.N * a.K * esz >= (1LL << 31)) return -22;
-  // BF16 dense products (all but the head) take the LDS-ring kernel, two
-  // stages: 128 x 128 tiles over 4 waves, or, for 64-wide feature tiles,
-  // 256 x 64 tiles over 8 waves (measured faster on the decoder's products)
-  if constexpr (XM == X_DENSE && sizeof(typename Op::T) == 2 && EPI != EPI_HEAD) {
-    if (a.N % 128 == 0) {
-      gemm_dma_kernel<128, EPI, OutT, 2, 128, 2><<<dim3(gm * (a.N / 128)), 256, 0, s>>>(a);
+  // Dense BF16 products (all but the head) and FP8 products whose K is a
+  // multiple of 128 take the LDS-ring kernel, two stages: 128 x 128 tiles over
+  // 4 waves, or, for 64-wide feature tiles, 256 x 64 tiles over 8 waves
+  // (measured faster on the decoder's products)
+  constexpr bool RING = XM == X_DENSE && EPI != EPI_HEAD && sizeof(typename Op::T) <= 2;
+  if constexpr (RING) {
+    if (sizeof(typename Op::T) == 2 || a.K % 128 == 0) {
+      if (a.N % 128 == 0) {
+        gemm_dma_kernel<Op, 128, EPI, OutT, 2, 128, 2><<<dim3(gm * (a.N / 128)), 256, 0, s>>>(a);
+        return hipGetLastError() == hipSuccess ? 0 : -5;
+      }
+      const int gm2 = cdiv(a.M, 256);
+      if ((long long)gm2 * 256 * a.K * esz >= (1LL << 31)) return -22;
+      gemm_dma_kernel<Op, 64, EPI, OutT, 2, 256, 4><<<dim3(gm2 * (a.N / 64)), 512, 0, s>>>(a);
       return hipGetLastError() == hipSuccess ? 0 : -5;
     }
-    const int gm2 = cdiv(a.M, 256);
-    if ((long long)gm2 * 256 * a.K * esz >= (1LL << 31)) return -22;
-    gemm_dma_kernel<64, EPI, OutT, 2, 256, 4><<<dim3(gm2 * (a.N / 64)), 512, 0, s>>>(a);
-    return hipGetLastError() == hipSuccess ? 0 : -5;
+  }
+  if constexpr (RING && sizeof(typename Op::T) == 2) {
+    return -22;  // not reached: every BF16 dense product takes the ring
   } else {
     // the gather loader's per-row token coordinates leave no registers for a
     // 128-wide tile with two prefetched stages
