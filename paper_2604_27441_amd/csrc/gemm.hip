@@ -429,16 +429,39 @@ __device__ __forceinline__ void gemm_epilogue_staged(const GemmArgs& a, f32x16 (
     return;
   }
   constexpr int CPRO = BN / EO;
+  if constexpr (EPI == EPI_RESIDUAL) {
+    // every residual chunk of this thread is loaded before the first add and
+    // store (a load after a store to the same buffer would otherwise wait
+    // out one memory round trip per chunk)
+    static_assert(BM_ * CPRO % NT_ == 0, "whole chunks per thread");
+    constexpr int IT = BM_ * CPRO / NT_;
+    f32x4 res[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int i = tid + it * NT_;
+      const int rl = i / CPRO, c = (i - rl * CPRO) * EO;
+      const int m = m0 + rl;
+      res[it] = m < Mlive ? *reinterpret_cast<const f32x4*>((const float*)a.out + (size_t)m * a.ldo + n0 + c)
+                          : f32x4{};
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int i = tid + it * NT_;
+      const int rl = i / CPRO, c = (i - rl * CPRO) * EO;
+      const int m = m0 + rl;
+      if (m >= Mlive) continue;
+      const f32x4 v = *reinterpret_cast<const f32x4*>(smem + rl * TPB + c * (int)sizeof(OutT));
+      *reinterpret_cast<f32x4*>((float*)a.out + (size_t)m * a.ldo + n0 + c) = res[it] + v;
+    }
+    return;
+  }
   for (int i = tid; i < BM_ * CPRO; i += NT_) {
     const int rl = i / CPRO, c = (i - rl * CPRO) * EO;
     const int m = m0 + rl;
     if (m >= Mlive) continue;
     const int n = n0 + c;
     const uint4 val = *reinterpret_cast<const uint4*>(smem + rl * TPB + c * (int)sizeof(OutT));
-    if (EPI == EPI_RESIDUAL) {
-      f32x4* p = reinterpret_cast<f32x4*>((float*)a.out + (size_t)m * a.ldo + n);
-      *p = *p + __builtin_bit_cast(f32x4, val);
-    } else if (EPI == EPI_QKV) {
+    if (EPI == EPI_QKV) {
       const int hd = (n - part * D) >> 6, dd = n & 63;
       OutT* dst = (OutT*)(part == 0 ? a.q : a.k) + ((size_t)hd * a.ldqk + m) * 64 + dd;
       *reinterpret_cast<uint4*>(dst) = val;
