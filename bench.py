@@ -150,6 +150,40 @@ def render_bench(reqs, outs, log, iters=20):
             "target_pixels_hit": filled, "view": "yaw 5 degrees, 100 mm sideways, same intrinsics"}
 
 
+LINEAR_SHAPES = [(43200, 1152, 384, 0), (43200, 384, 384, 1), (43200, 1536, 384, 2), (43200, 384, 1536, 1),
+                 (43200, 576, 192, 0), (43200, 192, 768, 1)]
+
+
+def linear_shapes_bench(log, iters=10):
+    """The encoder and decoder products at 43200 tokens (BF16) through
+    revo_op_linear, one after another, timed with HIP events: the workload of
+    the GEMM counter profiles."""
+    import torch
+    from paper_2604_27441_amd import lib
+    rows = []
+    for (M, N, K, epi) in LINEAR_SHAPES:
+        torch.manual_seed(0)
+        x = torch.randn(M, K, device="cuda").to(torch.bfloat16)
+        w = (torch.randn(N, K, device="cuda") * 0.05).to(torch.bfloat16)
+        b = torch.zeros(N, device="cuda")
+        out = torch.zeros(M, N, device="cuda", dtype=torch.float32 if epi == 1 else torch.bfloat16)
+        assert x.shape == (M, K) and w.shape == (N, K) and out.shape == (M, N)
+        call = lambda: lib.revo_op_linear(1, epi, x.data_ptr(), w.data_ptr(), b.data_ptr(), out.data_ptr(), M, N, K, None)
+        assert call() == 0
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(iters):
+            call()
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / iters * 1e3
+        rows.append({"M": M, "N": N, "K": K, "epilogue": ["store", "residual", "gelu"][epi], "us": us,
+                     "tflops": 2 * M * N * K / (us * 1e-6) / 1e12})
+        log(f"linear {M}x{N}x{K} {rows[-1]['epilogue']}: {us:.1f} us, {rows[-1]['tflops']:.0f} TFLOP/s")
+    return rows
+
+
 def metrics_bench(reqs, outs, log, iters=20):
     """Quality metrics and training losses of the recovered frames against the
     clean targets through revo_op_frame_metrics (SSIM, PSNR, L_RGB, L_Depth;
@@ -502,6 +536,8 @@ def main():
     ap.add_argument("--serve-streams", type=int, default=64)
     ap.add_argument("--serve-cap", type=int, default=21600, help="tokens per batch per modality when serving")
     ap.add_argument("--serve-sweep", action="store_true", help="serve 4, 8, 16, 32, 64 streams")
+    ap.add_argument("--linear-shapes", action="store_true",
+                    help="only time the encoder/decoder products through revo_op_linear (GEMM profiles)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -523,6 +559,10 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: {n} bytes read + {n} bytes written")
         del src, dst
+
+    if args.linear_shapes:
+        print(json.dumps({"linear_shapes": linear_shapes_bench(log), "dtype": "bf16", "data": "synthetic"}), flush=True)
+        return
 
     import synth
     t = time.perf_counter()
