@@ -45,7 +45,7 @@ enum revo_status {
   REVO_ENOMEM = -12,     /* device memory or HBM budget exhausted */
   REVO_EDEVICE = -5,     /* HIP runtime error */
   REVO_ENOREF = -61,     /* recovery asked for before any clean frame of the stream */
-  REVO_ENOTSUP = -95,    /* configuration this build does not support */
+  REVO_ENOTSUP = -95,    /* configuration the library does not support */
   REVO_ESHUTDOWN = -108  /* context is being destroyed */
 };
 
