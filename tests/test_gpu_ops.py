@@ -217,7 +217,7 @@ def test_convert_fp8_rounding():
     assert np.array_equal(got, oracle.e4m3_round(x))
 
 
-@pytest.mark.parametrize("M,N,K", [(1, 64, 64), (300, 576, 192), (1000, 1152, 384), (257, 384, 1536)])
+@pytest.mark.parametrize("M,N,K", [(1, 64, 64), (300, 576, 192), (1000, 1152, 384), (257, 384, 1536), (200, 192, 256)])
 @pytest.mark.parametrize("epi", [0, 1, 2])
 def test_linear_fp8(M, N, K, epi):
     x = RNG.standard_normal((M, K)) * 3
