@@ -184,6 +184,36 @@ def linear_shapes_bench(log, iters=10):
     return rows
 
 
+def attention_only_bench(log, iters=10):
+    """revo_op_attention (BF16) on one 1280x720 encoder layer of the 4-request
+    batch laid out as 24 heads of one 10800-token request (the same work as
+    4 requests x 6 heads), timed with HIP events: the workload of the
+    attention counter profiles."""
+    import torch
+    from paper_2604_27441_amd import lib
+    heads, ntok = 24, 10800
+    ld = (ntok + 64 + 15) // 16 * 16
+    torch.manual_seed(0)
+    q = (torch.randn(heads, ld, 64, device="cuda") * 0.2).to(torch.bfloat16)
+    k = torch.randn(heads, ld, 64, device="cuda").to(torch.bfloat16)
+    vt = torch.randn(heads, 64, ld, device="cuda").to(torch.bfloat16)
+    o = torch.zeros(ntok, heads * 64, device="cuda", dtype=torch.bfloat16)
+    assert q.shape == (heads, ld, 64) and vt.shape == (heads, 64, ld) and ld >= ntok + 64 and ld % 16 == 0
+    call = lambda: lib.revo_op_attention(1, q.data_ptr(), k.data_ptr(), vt.data_ptr(), o.data_ptr(), heads, ntok, ld, None)
+    assert call() == 0
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(iters):
+        call()
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / iters * 1e3
+    tf = 4.0 * ntok * ntok * 64 * heads / (us * 1e-6) / 1e12
+    log(f"attention 24 heads x {ntok} tokens: {us:.1f} us per call (op setup included), {tf:.0f} TFLOP/s")
+    return {"heads": heads, "tokens": ntok, "us": us, "tflops": tf}
+
+
 def metrics_bench(reqs, outs, log, iters=20):
     """Quality metrics and training losses of the recovered frames against the
     clean targets through revo_op_frame_metrics (SSIM, PSNR, L_RGB, L_Depth;
@@ -536,6 +566,8 @@ def main():
     ap.add_argument("--serve-streams", type=int, default=64)
     ap.add_argument("--serve-cap", type=int, default=21600, help="tokens per batch per modality when serving")
     ap.add_argument("--serve-sweep", action="store_true", help="serve 4, 8, 16, 32, 64 streams")
+    ap.add_argument("--attention-only", action="store_true",
+                    help="only time revo_op_attention on one encoder layer's work (attention profiles)")
     ap.add_argument("--linear-shapes", action="store_true",
                     help="only time the encoder/decoder products through revo_op_linear (GEMM profiles)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -560,6 +592,9 @@ def main():
         log(f"copy calibration: {n} bytes read + {n} bytes written")
         del src, dst
 
+    if args.attention_only:
+        print(json.dumps({"attention": attention_only_bench(log), "dtype": "bf16", "data": "synthetic"}), flush=True)
+        return
     if args.linear_shapes:
         print(json.dumps({"linear_shapes": linear_shapes_bench(log), "dtype": "bf16", "data": "synthetic"}), flush=True)
         return
