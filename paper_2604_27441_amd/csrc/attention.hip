@@ -12,14 +12,18 @@
 // the QKV epilogue for that.  Q arrives pre-scaled by log2(e)/8, so
 // probabilities are exp2(s - m).
 //
-// The running max is updated lazily: a query keeps its max until a block's
-// scores exceed it by more than 8 (in log2 units), so probabilities stay
-// below 2^8 and the output rescale is skipped for almost every block; the
-// final division by the row sum makes the result independent of the max
-// used.  The first block sets the max; after it (BF16) the score products
+// The final division by the row sum makes the result independent of the
+// max subtracted before exp2, so any max that keeps the probabilities finite
+// will do.  The first block sets it; after that (BF16) the score products
 // accumulate onto a register block holding -max, so they come out already
-// shifted and the softmax is a bare exp2 per score.  Only the last key
-// block of a request checks key bounds.
+// shifted and the softmax is a bare exp2 per score.  BF16 rows first run a
+// pass that never changes that max and takes no block max at all; if some
+// row sum of the workgroup reaches 2^64 (or is not finite) the workgroup
+// repeats its rows in a pass that raises the max lazily: a query keeps its
+// max until a block's scores exceed it by more than 8 (in log2 units), so
+// probabilities stay below 2^8 and the output rescale is skipped for almost
+// every block.  FP32 rows always use the lazy form.  Only the last key block
+// of a request checks key bounds.
 // K and V^T blocks of 64 keys are double-buffered in LDS.  BF16 blocks go
 // from HBM straight into LDS (buffer loads with an LDS destination, no
 // registers in between) with swizzled, unpadded rows; FP32 blocks pass
@@ -64,7 +68,7 @@ struct AttnTile {
 __device__ __forceinline__ int swz(int row, int chunk) { return row * 64 + ((chunk ^ ((row >> 1) & 7)) << 3); }
 
 // One 64-key block for one wave: scores, online softmax, P V accumulation.
-template <class Op, bool MASK, bool FIRST>
+template <class Op, bool MASK, bool FIRST, bool FAST>
 __device__ __forceinline__ void attn_block(const typename Op::T* __restrict__ kt, const typename Op::T* __restrict__ vt,
                                            const uint4 (&qf)[AttnTile<typename Op::T>::QCH], f32x16 (&oacc)[2],
                                            f32x16& negm, float& m_run, float& l_run, int lane, int kvalid) {
@@ -119,57 +123,62 @@ __device__ __forceinline__ void attn_block(const typename Op::T* __restrict__ kt
         if (st * 32 + acc_row(i, lane) >= kvalid) sacc[st][i] = NEG_BIG;
   }
 
-  // block max of this query
-  float m0 = fmaxf(fmaxf(sacc[0][0], sacc[0][1]), sacc[0][2]);
-  float m1 = fmaxf(fmaxf(sacc[1][0], sacc[1][1]), sacc[1][2]);
+  // FAST (BF16, after the first block): the max stays where the first block
+  // put it and no block max is taken; the caller checks the row sums after
+  // the last block instead
+  if constexpr (!(SHIFTED && FAST)) {
+    // block max of this query
+    float m0 = fmaxf(fmaxf(sacc[0][0], sacc[0][1]), sacc[0][2]);
+    float m1 = fmaxf(fmaxf(sacc[1][0], sacc[1][1]), sacc[1][2]);
 #pragma unroll
-  for (int i = 3; i < 15; i += 2) {
-    m0 = fmaxf(fmaxf(m0, sacc[0][i]), sacc[0][i + 1]);
-    m1 = fmaxf(fmaxf(m1, sacc[1][i]), sacc[1][i + 1]);
-  }
-  float mloc = fmaxf(fmaxf(m0, sacc[0][15]), fmaxf(m1, sacc[1][15]));
-  mloc = xhalf_max(mloc);
-  if constexpr (FIRST) {
-    // nothing accumulated yet: take this block's max as it is
-    m_run = mloc;
-    if constexpr (sizeof(T) == 2) {
-#pragma unroll
-      for (int i = 0; i < 16; ++i) negm[i] = -mloc;
-#pragma unroll
-      for (int st = 0; st < 2; ++st)
-#pragma unroll
-        for (int i = 0; i < 16; ++i) sacc[st][i] -= mloc;
+    for (int i = 3; i < 15; i += 2) {
+      m0 = fmaxf(fmaxf(m0, sacc[0][i]), sacc[0][i + 1]);
+      m1 = fmaxf(fmaxf(m1, sacc[1][i]), sacc[1][i + 1]);
     }
-  } else if constexpr (SHIFTED) {
-    // mloc is relative to m_run here
-    const bool grow = mloc > LAZY;
-    if (__any(grow)) {
-      const float d = grow ? mloc : 0.0f;
-      const float alpha = __builtin_amdgcn_exp2f(-d);
-      m_run += d;
-      l_run *= alpha;
-      oacc[0] *= alpha;
-      oacc[1] *= alpha;
+    float mloc = fmaxf(fmaxf(m0, sacc[0][15]), fmaxf(m1, sacc[1][15]));
+    mloc = xhalf_max(mloc);
+    if constexpr (FIRST) {
+      // nothing accumulated yet: take this block's max as it is
+      m_run = mloc;
+      if constexpr (sizeof(T) == 2) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) negm[i] = -m_run;
+        for (int i = 0; i < 16; ++i) negm[i] = -mloc;
 #pragma unroll
-      for (int st = 0; st < 2; ++st)
+        for (int st = 0; st < 2; ++st)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) sacc[st][i] -= d;
-      // keep the rescale inside this (rarely taken) branch instead of letting
-      // it become unconditional work with a selected factor
-      asm volatile("" : "+v"(oacc[0]), "+v"(oacc[1]), "+v"(sacc[0]), "+v"(sacc[1]), "+v"(negm));
-    }
-  } else {
-    const bool grow = mloc > m_run + LAZY;
-    if (__any(grow)) {
-      const float m_new = grow ? mloc : m_run;
-      const float alpha = __builtin_amdgcn_exp2f(m_run - m_new);
-      m_run = m_new;
-      l_run *= alpha;
-      oacc[0] *= alpha;
-      oacc[1] *= alpha;
-      asm volatile("" : "+v"(oacc[0]), "+v"(oacc[1]));
+          for (int i = 0; i < 16; ++i) sacc[st][i] -= mloc;
+      }
+    } else if constexpr (SHIFTED) {
+      // mloc is relative to m_run here
+      const bool grow = mloc > LAZY;
+      if (__any(grow)) {
+        const float d = grow ? mloc : 0.0f;
+        const float alpha = __builtin_amdgcn_exp2f(-d);
+        m_run += d;
+        l_run *= alpha;
+        oacc[0] *= alpha;
+        oacc[1] *= alpha;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) negm[i] = -m_run;
+#pragma unroll
+        for (int st = 0; st < 2; ++st)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) sacc[st][i] -= d;
+        // keep the rescale inside this (rarely taken) branch instead of letting
+        // it become unconditional work with a selected factor
+        asm volatile("" : "+v"(oacc[0]), "+v"(oacc[1]), "+v"(sacc[0]), "+v"(sacc[1]), "+v"(negm));
+      }
+    } else {
+      const bool grow = mloc > m_run + LAZY;
+      if (__any(grow)) {
+        const float m_new = grow ? mloc : m_run;
+        const float alpha = __builtin_amdgcn_exp2f(m_run - m_new);
+        m_run = m_new;
+        l_run *= alpha;
+        oacc[0] *= alpha;
+        oacc[1] *= alpha;
+        asm volatile("" : "+v"(oacc[0]), "+v"(oacc[1]));
+      }
     }
   }
 
@@ -237,10 +246,13 @@ template <class Op>
 __global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 3 : 2) void attn_kernel(const AttnArgs a) {
   typedef typename Op::T T;
   typedef AttnTile<T> A;
-  // two K stages [key][dim] then two V^T stages [dim][key]
-  __shared__ __attribute__((aligned(16))) T kv[4][KB * A::PITCH];
-  T(*ks)[KB * A::PITCH] = kv;
-  T(*vs)[KB * A::PITCH] = kv + 2;
+  // two K stages [key][dim], two V^T stages [dim][key], then a flag.  One
+  // LDS object only: with a second one the compiler attaches alias scopes to
+  // the stage loads and then waits for every prefetch before reading.
+  __shared__ __attribute__((aligned(16))) T kv[4 * KB * A::PITCH + 16 / sizeof(T)];
+  T(*ks)[KB * A::PITCH] = reinterpret_cast<T(*)[KB * A::PITCH]>(kv);
+  T(*vs)[KB * A::PITCH] = ks + 2;
+  int& redo = *reinterpret_cast<int*>(kv + 4 * KB * A::PITCH);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5;
@@ -344,44 +356,69 @@ __global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 3 : 2) void attn_
   }
   static_assert(sizeof(T) == 2 || A::LC == 4, "FP32: 4 chunks per thread");
 
-  REVO_ATTN_FETCH(0, 0);
-  REVO_ATTN_LAND(0);
-  __syncthreads();
-
-  f32x16 oacc[2] = {f32x16{}, f32x16{}};
+  f32x16 oacc[2];
   f32x16 negm;
-  float m_run = 0.0f, l_run = 0.0f;
+  float m_run, l_run;
   const int nkb = (N + KB - 1) / KB;
   const int nfull = N / KB;
-  if (nfull == 0) {
-    // a single, ragged block
-    attn_block<Op, true, true>(ks[0], vs[0], qf, oacc, negm, m_run, l_run, lane, N);
-  } else {
-    // the first block sets the max; the prefetch of the next block (or, at
-    // the end, a re-read of its own block into the idle buffer, which is
-    // then never read) overlaps it
-    REVO_ATTN_FETCH(nkb > 1 ? KB : 0, 1);
-    attn_block<Op, false, true>(ks[0], vs[0], qf, oacc, negm, m_run, l_run, lane, KB);
-    REVO_ATTN_LAND(1);
-    __syncthreads();
-#define REVO_ATTN_STEP(b_, buf_)                                                                      \
+  // One pass over the key blocks.  FAST passes (BF16) keep the first block's
+  // max for the whole row (see attn_block); SAFE passes update it lazily.
+  // Written out in the kernel body (not a called function) so that the
+  // compiler keeps seeing the two LDS stages as distinct and does not wait
+  // for the prefetch before reading the current stage.
+#define REVO_ATTN_STEP(b_, buf_, fast_)                                                               \
   {                                                                                                   \
     const int kn_ = (b_) + 1 < nkb ? ((b_) + 1) * KB : (b_) * KB;                                     \
     REVO_ATTN_FETCH(kn_, buf_ ^ 1);                                                                   \
-    attn_block<Op, false, false>(ks[buf_], vs[buf_], qf, oacc, negm, m_run, l_run, lane, KB);         \
+    attn_block<Op, false, false, fast_>(ks[buf_], vs[buf_], qf, oacc, negm, m_run, l_run, lane, KB);  \
     REVO_ATTN_LAND(buf_ ^ 1);                                                                         \
     __syncthreads();                                                                                  \
   }
-    int b = 1;
-    for (; b + 1 < nfull; b += 2) {
-      REVO_ATTN_STEP(b, 1)
-      REVO_ATTN_STEP(b + 1, 0)
-    }
-    if (b < nfull) REVO_ATTN_STEP(b, 1)
-#undef REVO_ATTN_STEP
-    if (nfull < nkb)  // ragged last block, already in LDS
-      attn_block<Op, true, false>(ks[nfull & 1], vs[nfull & 1], qf, oacc, negm, m_run, l_run, lane, N - nfull * KB);
+#define REVO_ATTN_PASS(fast_)                                                                             \
+  {                                                                                                       \
+    oacc[0] = f32x16{};                                                                                   \
+    oacc[1] = f32x16{};                                                                                   \
+    m_run = 0.0f;                                                                                         \
+    l_run = 0.0f;                                                                                         \
+    REVO_ATTN_FETCH(0, 0);                                                                                \
+    REVO_ATTN_LAND(0);                                                                                    \
+    __syncthreads();                                                                                      \
+    if (nfull == 0) {                                                                                     \
+      /* a single, ragged block */                                                                        \
+      attn_block<Op, true, true, fast_>(ks[0], vs[0], qf, oacc, negm, m_run, l_run, lane, N);             \
+    } else {                                                                                              \
+      /* the first block sets the max; the prefetch of the next block (or, at the end, a re-read of its   \
+         own block into the idle buffer, which is then never read) overlaps it */                         \
+      REVO_ATTN_FETCH(nkb > 1 ? KB : 0, 1);                                                               \
+      attn_block<Op, false, true, fast_>(ks[0], vs[0], qf, oacc, negm, m_run, l_run, lane, KB);           \
+      REVO_ATTN_LAND(1);                                                                                  \
+      __syncthreads();                                                                                    \
+      int b = 1;                                                                                          \
+      for (; b + 1 < nfull; b += 2) {                                                                     \
+        REVO_ATTN_STEP(b, 1, fast_)                                                                       \
+        REVO_ATTN_STEP(b + 1, 0, fast_)                                                                   \
+      }                                                                                                   \
+      if (b < nfull) REVO_ATTN_STEP(b, 1, fast_)                                                          \
+      if (nfull < nkb) /* ragged last block, already in LDS */                                            \
+        attn_block<Op, true, false, fast_>(ks[nfull & 1], vs[nfull & 1], qf, oacc, negm, m_run, l_run, lane, \
+                                           N - nfull * KB);                                               \
+    }                                                                                                     \
   }
+  if constexpr (sizeof(T) == 2) {
+    // A FAST pass is exact as long as no probability overflowed: every
+    // probability of a lane's keys is at most that lane's row sum, so row sums
+    // below 2^64 bound them all (and the output by 2^64 max|v|).  Otherwise
+    // (or on NaN) the whole workgroup repeats the row in a SAFE pass.
+    if (tid == 0) redo = 0;  // ordered before any write by the pass's first barrier
+    REVO_ATTN_PASS(true)
+    if (__any(!(l_run < 0x1p64f)) && lane == 0) redo = 1;
+    __syncthreads();
+    if (redo) REVO_ATTN_PASS(false)  // every wave is past its last block
+  } else {
+    REVO_ATTN_PASS(false)
+  }
+#undef REVO_ATTN_PASS
+#undef REVO_ATTN_STEP
 #undef REVO_ATTN_LOAD1
 #undef REVO_ATTN_STORE1
 #undef REVO_ATTN_DMA
@@ -393,7 +430,7 @@ __global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 3 : 2) void attn_
   // 16-byte chunks rather than one short piece per query row.
   const float l_tot = xhalf_sum(l_run);
   const int ql = wave * 32 + (lane & 31);  // this lane's query within the tile
-  uint8_t* st = reinterpret_cast<uint8_t*>(&kv[0][0]);
+  uint8_t* st = reinterpret_cast<uint8_t*>(kv);
   __syncthreads();
   if (a.o_scale) {
     // FP8 output for an FP8 output projection

@@ -125,18 +125,21 @@ def test_attention(prec, heads, ntok):
 
 
 @pytest.mark.parametrize("prec", [FP32, BF16])
-@pytest.mark.parametrize("direction", [1, -1])
-def test_attention_drifting_max(prec, direction):
-    """Scores that rise (or fall) steadily over the keys, by about 300 in
-    natural-log units end to end: the running max is raised many times (or
-    set by the first block and never again), and the result must still be
-    the softmax average."""
+@pytest.mark.parametrize("direction,amp", [(1, 60.0), (-1, 60.0), (1, 6.0)])
+def test_attention_drifting_max(prec, direction, amp):
+    """Scores that rise (or fall) steadily over the keys, by amp * 5 in
+    natural-log units end to end.  A rise of 300 raises the running max many
+    times (BF16: the first pass, which keeps the first block's max,
+    overflows and the row is recomputed with running maxima); a fall leaves
+    the first block's max in place; a rise of 30 (43 in log2 units) keeps
+    the first pass, with probabilities up to about 2^43.  The result must be
+    the softmax average in every case."""
     heads, ntok = 2, 2000
     qd, kd, vt, q64, k64, v64, ld = _attn_inputs(heads, ntok, prec, scale=0.3)
     u = np.zeros(64)
     u[0] = 1.0
     ramp = np.linspace(0.0, 1.0, ntok) if direction > 0 else np.linspace(1.0, 0.0, ntok)
-    kk = k64 + 60.0 * ramp[None, :, None] * u
+    kk = k64 + amp * ramp[None, :, None] * u
     qq = q64 + 40.0 * u
     dt = _dt(prec)
     k_op = torch.tensor(kk, dtype=torch.float32).to(dt)
