@@ -161,6 +161,34 @@ def test_attention_drifting_max(prec, direction, amp):
         assert err.max() < bound * np.abs(v64[h]).max(), (float(err.max()), smax)
 
 
+def test_attention_overflow_in_some_tiles():
+    """BF16: only the queries aligned with the rising keys overflow the first
+    pass, so only their workgroups (query tiles 0, 4 and 5 of 128) repeat the
+    rows in the safe pass; every row must match the oracle."""
+    heads, ntok = 2, 1000
+    qd, kd, vt, q64, k64, v64, ld = _attn_inputs(heads, ntok, BF16, scale=0.3)
+    u = np.zeros(64)
+    u[0] = 1.0
+    kk = k64 + 60.0 * np.linspace(0.0, 1.0, ntok)[None, :, None] * u
+    hot = np.zeros(ntok, dtype=bool)
+    hot[:100] = True
+    hot[600:700] = True
+    qq = q64 + 40.0 * hot[None, :, None] * u
+    k_op = torch.tensor(kk, dtype=torch.float32).to(torch.bfloat16)
+    q_op = torch.tensor(qq * (math.log2(math.e) / 8), dtype=torch.float32).to(torch.bfloat16)
+    kd[:, :ntok] = k_op.cuda()
+    qd[:, :ntok] = q_op.cuda()
+    q64 = q_op.double().numpy() / (math.log2(math.e) / 8)
+    k64 = k_op.double().numpy()
+    o = torch.zeros((ntok, heads * 64), dtype=torch.bfloat16).cuda()
+    assert _lib().revo_op_attention(BF16, qd.data_ptr(), kd.data_ptr(), vt.data_ptr(), o.data_ptr(), heads, ntok, ld, None) == 0
+    got = o.double().cpu().numpy()
+    for h in range(heads):
+        ref = oracle.attention_head(q64[h], k64[h], v64[h])
+        err = np.abs(got[:, h * 64:(h + 1) * 64] - ref)
+        assert err.max() < 1.5e-2 * np.abs(v64[h]).max(), float(err.max())
+
+
 def test_attention_uniform_keys_average_values():
     """Equal keys give the mean of V exactly up to rounding (softmax is uniform)."""
     heads, ntok = 2, 300
