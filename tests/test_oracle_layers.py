@@ -232,3 +232,22 @@ def test_head_placement_is_the_index_bijection(gy, gx, T, C):
     used = np.sort(frame.ravel())
     want = np.sort((np.arange(P)[:, None] * 100000.0 + ((T - 1) * 256 * C + np.arange(256 * C))[None, :]).ravel())
     assert np.array_equal(used, want)
+
+
+def test_absmax_recorder_scale_values():
+    """Calibration scales are max |activation| over every call of a site,
+    divided by 448 (the E4M3 maximum), and 1 for a site that only saw zeros;
+    with such a scale the largest activation maps onto 448 exactly."""
+    rec = oracle.AbsMaxRecorder()
+    x1 = np.array([[0.5, -2.0], [1.0, 0.25]])
+    x2 = np.array([[-3.5, 0.0, 1.5]])
+    assert rec.act(x1, "enc0.qkv") is x1                      # exact arithmetic passes through
+    rec.act(x2, "enc0.qkv")
+    rec.act(np.zeros((3, 4)), "enc0.proj")
+    rec.act(np.array([[7.0]]), "dec0.fc2")
+    rec.act(np.array([[-1.0]]), "dec0.fc2")
+    s = rec.scales()
+    assert s == {"enc0.qkv": 3.5 / 448.0, "enc0.proj": 1.0, "dec0.fc2": 7.0 / 448.0}
+    r = oracle.FP8Rounding(s)
+    q = r.act(x2, "enc0.qkv")
+    assert q[0, 0] == -3.5 and q[0, 1] == 0.0                 # -absmax -> -448 -> back exactly

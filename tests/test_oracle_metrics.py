@@ -112,3 +112,41 @@ def test_depth_is_normalised_by_4000_mm():
     # constant frames 0.5 vs 0.6: SSIM is the luminance term
     c1 = 0.01 ** 2
     assert math.isclose(m["ssim"], (2 * 0.5 * 0.6 + c1) / (0.25 + 0.36 + c1), rel_tol=1e-12)
+
+
+def test_l_rgb_is_mse_plus_tv_of_the_prediction():
+    """L_RGB = MSE + alpha TV with alpha = 0.01 (Sec. 3.4.2 RGB loss, Sec. 4),
+    TV taken on the prediction.  A horizontal ramp a*x against a zero ground
+    truth has MSE = a^2 (W-1)(2W-1)/6 (mean of squares of 0..W-1) and TV = a
+    (every horizontal step is a, every vertical one 0); swapping the two
+    frames keeps the MSE and makes the prediction's TV zero."""
+    H, W, a = 12, 17, 0.013
+    ramp = np.broadcast_to((a * np.arange(W))[None, :, None], (H, W, 3)).copy()
+    zero = np.zeros((H, W, 3))
+    mse = a * a * (W - 1) * (2 * W - 1) / 6.0
+    m = oracle.frame_metrics(ramp, zero)
+    assert math.isclose(m["mse"], mse, rel_tol=1e-12)
+    assert math.isclose(m["tv"], a, rel_tol=1e-12)
+    assert math.isclose(m["l_rgb"], mse + 0.01 * a, rel_tol=1e-12)
+    assert math.isclose(m["l_rgb"] - m["mse"], 0.01 * a, rel_tol=1e-9)
+    swapped = oracle.frame_metrics(zero, ramp)
+    assert math.isclose(swapped["mse"], mse, rel_tol=1e-12)
+    assert swapped["tv"] == 0.0 and math.isclose(swapped["l_rgb"], mse, rel_tol=1e-12)
+
+
+def test_l_depth_weights_on_flat_frames():
+    """L_Depth = 0.1 L1 + L_edge + (1 - SSIM) (Sec. 3.4.2 depth loss, Sec. 4
+    weights).  Two flat depth frames at u and v mm: L1 = |u - v| / 4000, no
+    gradients so L_edge = 0, and SSIM is the luminance term alone,
+    (2ab + C1) / (a^2 + b^2 + C1) with a = u/4000, b = v/4000, C1 = 1e-4."""
+    u, v = 1200, 1700
+    pred = np.full((20, 24), u, np.uint16)
+    gt = np.full((20, 24), v, np.uint16)
+    a, b = u / 4000.0, v / 4000.0
+    lum = (2 * a * b + 1e-4) / (a * a + b * b + 1e-4)
+    m = oracle.frame_metrics(pred, gt)
+    assert math.isclose(m["l1"], abs(a - b), rel_tol=1e-12)
+    assert m["edge"] == 0.0
+    assert math.isclose(m["ssim"], lum, rel_tol=1e-12)
+    # 1 - SSIM carries the float64 rounding of the filtered moments (~1e-17 against C2)
+    assert math.isclose(m["l_depth"], 0.1 * abs(a - b) + (1.0 - lum), rel_tol=0, abs_tol=1e-12)
