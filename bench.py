@@ -357,17 +357,46 @@ def serve_bench(blobs, streams, seconds, warm_seconds, cap_tokens, log, seed=0):
     per_res = {}
     for r in sorted(set(res)):
         lr = sorted((c.done_ns - x[3]) * 1e-6 for c, x in ok if x[1] == r)
-        per_res[f"{r[1]}x{r[0]}"] = {"served_per_s": len(lr) / seconds, "p50_ms": pct(lr, 50), "p99_ms": pct(lr, 99)}
-    out = {
+        nr = sum(1 for _, x in served if x[1] == r)
+        per_res[f"{r[1]}x{r[0]}"] = {"served_per_s": len(lr) / seconds, "offered_per_s": nr / seconds,
+                                     "p50_ms": pct(lr, 50), "p99_ms": pct(lr, 99)}
+    # per stream: served fraction of its recoveries, the longest run of shed
+    # recoveries, and whether some window of 30 frames (one GoP) that holds
+    # recoveries has none served (the stream frozen on its last good frame)
+    by_stream = {}
+    for c, x in served:
+        by_stream.setdefault(c.stream_id, []).append((c.frame_index, c.status == 0))
+    fracs, runs, frozen = [], [], 0
+    for sid, seq in by_stream.items():
+        seq.sort()
+        fracs.append(sum(ok for _, ok in seq) / len(seq))
+        run = best = 0
+        for _, ok in seq:
+            run = 0 if ok else run + 1
+            best = max(best, run)
+        runs.append(best)
+        good = [f for f, ok in seq if ok]
+        for f, _ in seq:
+            # the window of 30 frames ending at this recovery
+            if not any(f - 29 <= g <= f for g in good) and seq[0][0] <= f - 29:
+                frozen += 1
+                break
         "streams": streams, "seconds": seconds, "offered_recoveries_per_s": n_rec / seconds,
         "served_pairs_per_s": len(ok) / seconds, "shed_fraction": shed / max(1, n_rec),
         "failed": sum(1 for c, _ in served if c.status == 2),
         "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
         "deadline_met_fraction": (sum(1 for v in lat if v <= 1000 / 30.0) / len(lat)) if lat else None,
         "per_resolution": per_res, "batch_token_cap": cap_tokens,
+        "fairness": {
+            "min_stream_served_fraction": min(fracs) if fracs else None,
+            "max_shed_run": max(runs) if runs else None,
+            "streams_frozen_for_a_gop": frozen,
+            "note": "per stream over the measured window: fraction of its recoveries served, longest run of shed "
+                    "recoveries, and streams with a 30-frame window of recoveries none of which was served",
+        },
     }
     log(f"serving {streams} streams: {out['served_pairs_per_s']:.1f} pairs/s served, shed {100 * out['shed_fraction']:.1f} %,"
-        f" p50 {out['p50_ms']} ms, p99 {out['p99_ms']} ms")
+        f" p50 {out['p50_ms']} ms, p99 {out['p99_ms']} ms, max shed run {out['fairness']['max_shed_run']}")
     return out
 
 
@@ -565,7 +594,8 @@ def main():
     ap.add_argument("--serve-warmup", type=float, default=2.0)
     ap.add_argument("--serve-streams", type=int, default=64)
     ap.add_argument("--serve-cap", type=int, default=21600, help="tokens per batch per modality when serving")
-    ap.add_argument("--serve-sweep", action="store_true", help="serve 4, 8, 16, 32, 64 streams")
+    ap.add_argument("--serve-sweep-seconds", type=float, default=3.0,
+                    help="measured window of each point of the 4, 8, 16, 32-stream sweep (0 = no sweep)")
     ap.add_argument("--attention-only", action="store_true",
                     help="only time revo_op_attention on one encoder layer's work (attention profiles)")
     ap.add_argument("--linear-shapes", action="store_true",
@@ -697,9 +727,12 @@ def main():
     if args.serve_seconds > 0:
         out["serving"] = serve_bench(blobs, args.serve_streams, args.serve_seconds, args.serve_warmup,
                                      args.serve_cap, log)
-        if args.serve_sweep:
-            out["serving_sweep"] = [serve_bench(blobs, n, args.serve_seconds, args.serve_warmup, args.serve_cap, log)
-                                    for n in (4, 8, 16, 32)]
+        if args.serve_sweep_seconds > 0:
+            # the stream-count knee: where shedding starts
+            sweep = [serve_bench(blobs, n, args.serve_sweep_seconds, 1.0, args.serve_cap, log) for n in (4, 8, 16, 32)]
+            out["serving_sweep"] = [
+                {k: v[k] for k in ("streams", "offered_recoveries_per_s", "served_pairs_per_s", "shed_fraction",
+                                   "p50_ms", "p99_ms", "fairness")} for v in sweep + [out["serving"]]]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(reqs[0], log)
     print(json.dumps(out), flush=True)

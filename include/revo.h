@@ -84,8 +84,9 @@ enum revo_completion_status {
 typedef struct revo_config {
   int device;                 /* HIP device ordinal */
   int precision;              /* revo_precision */
-  int k;                      /* clean reference frames per recovery, 1..7 (paper: 5) */
-  int tubelet;                /* frames per tubelet T, 1..4 (paper: 2); (k+1) padded to a multiple of T */
+  int k;                      /* clean reference frames per recovery, 1..7 (paper: 5, App. B.3) */
+  int tubelet;                /* frames per tubelet T, 1..4 (paper: 2, App. B.3); (k+1) padded to a
+                                 multiple of T with the oldest frame, at most 9 frames in all */
   int enc_depth;              /* encoder blocks; 0 = 12 */
   int dec_depth;              /* decoder blocks; 0 = 4 */
   int composite;              /* 1 = replace lost pixels only; 0 = raw clamped prediction everywhere */
@@ -99,6 +100,9 @@ typedef struct revo_config {
   const float *weights_depth; /* host FP32 blob for the depth model */
   size_t n_weights_depth;
   unsigned flags;             /* REVO_CFG_* */
+  void *hip_stream;           /* optional hipStream_t of the caller: each submit's input copies are
+                                 ordered after the work already enqueued on it (NULL: inputs must
+                                 be complete when submit is called) */
 } revo_config;
 
 /*
@@ -141,38 +145,60 @@ typedef struct revo_completion {
   long long submit_ns, done_ns;   /* CLOCK_MONOTONIC */
 } revo_completion;
 
-/* Fill cfg with the paper's configuration: BF16, k = 5, T = 2, 12 + 4 blocks,
- * composite on, 30 fps.  Weights must still be set. */
+/* Fill cfg with the paper's configuration: k = 5 references and T = 2 frame
+ * tubelets (App. B.3), 12 + 4 blocks, BF16, composite on, 30 fps (the
+ * receiver's frame budget, Sec. 3.3 Eq. 1).  Weights must still be set. */
 void revo_config_default(revo_config *cfg);
 
-/* Number of floats in one modality's weight blob (channels 3 or 1). */
+/* Number of floats in one modality's weight blob (channels 3 or 1; the RGB
+ * and depth models are separate, Sec. 3.4.2).  0 for invalid arguments. */
 size_t revo_weight_count(int channels, int tubelet, int enc_depth, int dec_depth);
 
-/* Create a context on cfg->device: uploads and converts the weights, sizes
- * the workspaces, starts the worker thread.  *out is set on success. */
+/* Create a context on cfg->device: uploads and converts both models'
+ * weights (Sec. 3.4.1 architecture, one model per modality, Sec. 3.4.2),
+ * sizes the workspaces from max_batch_tokens or hbm_budget_bytes, starts the
+ * worker and completion threads (the receiver's recovery thread, Sec. 4).
+ * The weight blobs are copied; the caller keeps ownership.  *out is set on
+ * success.  Errors: REVO_EINVAL (bad k, tubelet, depths or weights),
+ * REVO_ENOTSUP (precision), REVO_EDEVICE (no such device, HIP failure),
+ * REVO_ENOMEM (device memory, or a budget below the weights and the
+ * smallest workspace). */
 int revo_recover_create(const revo_config *cfg, revo_ctx **out);
 
-/* Queue one frame (RGB and/or depth) of one stream.  Non-blocking with
- * respect to the GPU work: inputs are copied into library staging before
- * it returns, so input buffers may be reused at once; output buffers must
- * stay valid until poll reports the ticket.  A modality with a mask is
- * recovered against the stream's clean references as they stand at this
- * submit; a modality without a mask becomes the newest clean reference
- * (a resolution change resets the stream's references) and is copied to
- * the output.  Recovered frames never become references.
- * Returns REVO_OK and sets *ticket, REVO_EAGAIN if the queue is full, or
- * an error.  Recovery without any clean reference completes with
- * status REVO_FAILED, error REVO_ENOREF. */
+/* Queue one frame (RGB and/or depth) of one stream: the recovery module's
+ * input is the k closest clean frames of the stream plus the corrupted
+ * frame, and its output the reconstructed frame (Sec. 3.4.1); intact frames
+ * bypass recovery (Sec. 3.1).  Non-blocking with respect to the GPU work:
+ * inputs are copied into library staging before it returns, so input
+ * buffers may be reused at once; output buffers must stay valid until poll
+ * reports the ticket.  A modality with a mask is recovered against the
+ * stream's clean references as they stand at this submit; a modality
+ * without a mask becomes the newest clean reference (a resolution change
+ * resets the stream's references) and is copied to the output.  Recovered
+ * frames never become references (Sec. 3.4.1, reference reuse).
+ * Returns REVO_OK and sets *ticket; REVO_EAGAIN when the queue is full or
+ * the HBM budget has no room for the request's staging and prediction
+ * buffers (poll, then retry); REVO_ENOREF when a modality is to be
+ * recovered but no clean frame of that stream and modality at this size
+ * was submitted before it; REVO_EINVAL for bad sizes or pointers.  A clean
+ * frame whose reference update fails later (device memory) completes with
+ * status REVO_FAILED, and a recovery queued behind it with error
+ * REVO_ENOREF. */
 int revo_recover_submit(revo_ctx *ctx, const revo_request *req, unsigned long long *ticket);
 
 /* Collect up to max completions, waiting up to timeout_us (0 = no wait,
- * -1 = wait for at least one).  Returns the count (>= 0) or an error. */
+ * -1 = wait for at least one): the display thread's side of the receiver
+ * (Sec. 4).  Outputs of a reported ticket are complete.  Returns the count
+ * (>= 0) or REVO_EINVAL. */
 int revo_recover_poll(revo_ctx *ctx, revo_completion *out, int max, int timeout_us);
 
-/* Drain queued and in-flight work, stop the worker and free everything. */
+/* Drain queued and in-flight work (completions are posted but no longer
+ * collectable), stop the threads and free every device allocation. */
 void revo_recover_destroy(revo_ctx *ctx);
 
-/* FP8 calibration (REVO_FP8 contexts only; REVO_ENOTSUP otherwise).
+/* FP8 calibration (REVO_FP8 contexts only; REVO_ENOTSUP otherwise).  The
+ * paper states no inference precision; the FP8 form's static activation
+ * scales come from this pass.
  * phase = 1: wait for queued work, clear the recorded maxima; recoveries
  * submitted afterwards run in BF16 and raise the per-tensor maximum of every
  * FP8 product input over their tokens.  phase = 0: wait for queued work, set
@@ -195,12 +221,14 @@ typedef struct revo_stats {
   long long other_launches;         /* LayerNorm and composite launches */
   double other_ms;
   double forward_ms;                /* whole forward passes, both modalities summed */
+  long long hbm_fixed_bytes;        /* weights + workspaces (always filled, never reset) */
+  long long hbm_pool_bytes;         /* reference rings + staging held in the pool, cached blocks included */
 } revo_stats;
 
 /* Copy the counters into *out; reset = 1 zeroes them afterwards. */
 int revo_get_stats(revo_ctx *ctx, revo_stats *out, int reset);
 
-/* Static text for a revo_status code. */
+/* Static text for a revo_status code ("unknown error" otherwise). */
 const char *revo_strerror(int code);
 
 #ifdef __cplusplus

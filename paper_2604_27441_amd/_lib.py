@@ -27,7 +27,7 @@ class RevoConfig(C.Structure):
         ("hbm_budget_bytes", C.c_size_t), ("fps", C.c_float),
         ("weights_rgb", C.POINTER(C.c_float)), ("n_weights_rgb", C.c_size_t),
         ("weights_depth", C.POINTER(C.c_float)), ("n_weights_depth", C.c_size_t),
-        ("flags", C.c_uint),
+        ("flags", C.c_uint), ("hip_stream", C.c_void_p),
     ]
 
 
@@ -55,6 +55,7 @@ class RevoStats(C.Structure):
         ("attn_launches", C.c_longlong), ("attn_ms", C.c_double), ("attn_flop", C.c_double),
         ("gemm_launches", C.c_longlong), ("gemm_ms", C.c_double), ("gemm_flop", C.c_double),
         ("other_launches", C.c_longlong), ("other_ms", C.c_double), ("forward_ms", C.c_double),
+        ("hbm_fixed_bytes", C.c_longlong), ("hbm_pool_bytes", C.c_longlong),
     ]
 
 

@@ -42,7 +42,7 @@ class Recoverer:
     def __init__(self, weights_rgb, weights_depth, precision=REVO_BF16, device=0, k=5, tubelet=2,
                  enc_depth=0, dec_depth=0, composite=1, max_streams=64, max_batch=16, max_batch_tokens=0,
                  hbm_budget_bytes=0, fps=30.0, shed=False, profile=False, one_stream=False,
-                 graphs=False):
+                 graphs=False, hip_stream=None):
         cfg = RevoConfig()
         lib.revo_config_default(C.byref(cfg))
         self._w = [np.ascontiguousarray(weights_rgb, np.float32), np.ascontiguousarray(weights_depth, np.float32)]
@@ -55,6 +55,7 @@ class Recoverer:
         prof_flag = _lib.REVO_CFG_PROFILE_ATTN if profile == "attention" else (_lib.REVO_CFG_PROFILE if profile else 0)
         cfg.flags = ((_lib.REVO_CFG_SHED if shed else 0) | prof_flag
                      | (_lib.REVO_CFG_ONE_STREAM if one_stream else 0) | (_lib.REVO_CFG_GRAPHS if graphs else 0))
+        cfg.hip_stream = hip_stream
         cfg.weights_rgb = self._w[0].ctypes.data_as(C.POINTER(C.c_float))
         cfg.n_weights_rgb = self._w[0].size
         cfg.weights_depth = self._w[1].ctypes.data_as(C.POINTER(C.c_float))

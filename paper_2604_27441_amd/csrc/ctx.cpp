@@ -8,7 +8,9 @@
 // the RGB and depth networks on two streams, and posts completions that
 // poll() hands out.  Deadlines follow the receiver's 1/fps budget (Sec. 3.3,
 // Eq. 1); with shedding enabled a job that cannot finish in time completes
-// as REVO_SHED, the analogue of the display repeating its last frame.
+// as REVO_SHED, the analogue of the display repeating its last frame.  A
+// stream whose recent recoveries were all shed is served first, so no stream
+// is left frozen on its last good frame for a whole GoP (Sec. 3.3).
 #include <string.h>
 #include <time.h>
 
@@ -23,6 +25,7 @@
 
 #include "../../include/revo.h"
 #include "model.h"
+#include "sched.h"
 
 using namespace revo;
 
@@ -167,6 +170,26 @@ struct revo_ctx {
   long long last_done_ns = 0;
   int device_error = 0;
   double sec_per_unit = 3e-11;  // cost model for shedding: seconds per work unit (guarded by mu)
+  // per stream (guarded by mu): frame size of the last clean frame submitted
+  // per modality (a recovery needs one at its own size), and the run of
+  // recoveries shed since the last one admitted to a batch (sched.h)
+  struct StreamState {
+    int clean_h[2] = {0, 0}, clean_w[2] = {0, 0};
+  };
+  std::vector<StreamState> sst;
+  std::vector<int> shed_run;
+  // reference frames dropped by a resolution change while batches launched
+  // before it may still read them: returned to the pool once every batch
+  // numbered below `after` has completed (guarded by mu)
+  struct Deferred {
+    void* p;
+    size_t n;
+    unsigned long long after;
+  };
+  std::vector<Deferred> deferred;
+  unsigned long long batch_seq = 0;       // batches formed so far (guarded by mu)
+  unsigned long long completed_seq = 0;   // every batch up to this number has completed (guarded by mu)
+  hipEvent_t caller_ev = nullptr;         // orders input copies after cfg.hip_stream (guarded by copy_mu)
   std::mutex stats_mu;
   revo_stats stats;
 };
@@ -174,8 +197,11 @@ struct revo_ctx {
 namespace {
 
 const int kMaxQueue = 4096;
-
-double work_units(int N) { return (double)N * N + 2300.0 * N; }
+// Shedding policy (sched.h): a stream whose last kFairRun recovery requests
+// were all shed goes ahead of the submission order (half of a 30-frame GoP, so
+// every stream keeps a served recovery in every GoP-long window while the GPU
+// can afford one per stream per kFairRun frames).
+const int kFairRun = 15;
 
 void release_mod(revo_ctx* c, Mod& m, int C) {
   const size_t px = (size_t)m.H * m.W;
@@ -205,13 +231,29 @@ void finish(revo_ctx* c, Job* j) {
   delete j;
 }
 
+// Return reference frames dropped by batch `seq` to the pool once every
+// earlier batch has completed (they may still be reading them).
+void defer_free(revo_ctx* c, void* p, size_t n, unsigned long long seq) {
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->completed_seq + 1 < seq) {
+      c->deferred.push_back({p, n, seq});
+      return;
+    }
+  }
+  c->pool.put(p, n);
+}
+
 // Push a clean frame into its stream's ring on the modality's stream (the
 // ring slot is only read by batches launched earlier on that same stream).
-int push_clean(revo_ctx* c, Job* j, int q) {
+// seq numbers the batch being formed.
+int push_clean(revo_ctx* c, Job* j, int q, unsigned long long seq) {
   Mod& m = j->mod[q];
   Ring& ring = c->rings[q][j->stream];
   if (ring.H != m.H || ring.W != m.W) {
-    for (auto& f : ring.frames) c->pool.put(f.dev, (size_t)ring.H * ring.W * (q == 0 ? 3 : 2));
+    // a resolution change starts a new reference set; the old frames may
+    // still be read by batches in flight, so their memory waits for them
+    for (auto& f : ring.frames) defer_free(c, f.dev, (size_t)ring.H * ring.W * (q == 0 ? 3 : 2), seq);
     ring.frames.clear();
     ring.H = m.H; ring.W = m.W;
   }
@@ -265,6 +307,7 @@ void fill_desc(revo_ctx* c, Job* j, int q, ReqDesc& d) {
 // A batch enqueued on the GPU, waiting for its completion events.
 struct InFlight {
   std::vector<Job*> batch;
+  unsigned long long seq = 0;  // batch number (batches complete in this order)
   bool record = false;  // FP8 calibration batch
   int slot = 0;
   int rc = 0;
@@ -373,11 +416,24 @@ void completer_main(revo_ctx* c) {
       f = c->inflight.front();
     }
     complete_batch(c, f);
+    std::vector<revo_ctx::Deferred> ready;
     {
       std::lock_guard<std::mutex> lk(c->mu);
       c->inflight.pop_front();
       c->free_slots.push_back(f->slot);
+      c->completed_seq = f->seq;
+      auto& dl = c->deferred;
+      for (size_t i = 0; i < dl.size();) {
+        if (dl[i].after <= f->seq + 1) {
+          ready.push_back(dl[i]);
+          dl[i] = dl.back();
+          dl.pop_back();
+        } else {
+          ++i;
+        }
+      }
     }
+    for (auto& d : ready) c->pool.put(d.p, d.n);
     c->cv_work.notify_all();
     c->cv_done.notify_all();
     delete f;
@@ -391,7 +447,8 @@ void worker_main(revo_ctx* c) {
   for (;;) {
     std::vector<Job*> batch;
     int slot = -1;
-    double batch_units = 0.0, batch_start = 0.0;
+    unsigned long long seq = 0;
+    double batch_start = 0.0;
     {
       std::unique_lock<std::mutex> lk(c->mu);
       for (;;) {
@@ -409,63 +466,55 @@ void worker_main(revo_ctx* c) {
       }
       slot = c->free_slots.back();
       c->free_slots.pop_back();
-      // Take jobs in submission order (deadlines follow arrival order) while
-      // they fit the token capacity.  Stop before a clean frame of a stream
-      // that already has a recovery in this batch.  With shedding, a job that
-      // cannot finish by its deadline even alone after the queued work is
-      // shed, and the batch closes before a job whose addition would make
-      // the whole batch (which completes at once) miss a member's deadline.
-      const bool shed = (c->cfg.flags & REVO_CFG_SHED) != 0;
-      const double start = std::max((double)now_ns(), c->busy_until_ns);
-      const double spu = 1e9 * c->sec_per_unit;
-      double min_deadline = 1e300;
-      int tokens[2] = {0, 0};
-      std::vector<unsigned> rec_streams[2];
-      while (!c->queue.empty() && (int)batch.size() < max_batch) {
-        Job* j = c->queue.front();
-        bool fits = true, conflict = false;
-        int add[2] = {0, 0};
-        double ju = 0.0;
+      // the next batch (sched.h): submission order, starving streams first,
+      // deadline shedding
+      const int nq = (int)c->queue.size();
+      std::vector<SchedJob> sj(nq);
+      std::vector<int> dec(nq);
+      for (int i = 0; i < nq; ++i) {
+        const Job* j = c->queue[i];
+        SchedJob& e = sj[i];
+        e.stream = j->stream;
+        e.units = 0.0;
+        e.deadline_ns = (double)j->deadline;
         for (int q = 0; q < 2; ++q) {
           const Mod& m = j->mod[q];
-          if (!m.present) continue;
-          if (m.clean) {
-            for (unsigned s : rec_streams[q])
-              if (s == j->stream) conflict = true;
-          } else {
-            add[q] = (request_tokens(m.H, m.W, c->J) + 15) & ~15;  // rows start 16-aligned
-            ju += work_units(request_tokens(m.H, m.W, c->J));
-            if (tokens[q] + add[q] > cap) fits = false;
+          e.clean[q] = m.present && m.clean;
+          e.tokens[q] = 0;
+          if (m.present && !m.clean) {
+            const int N = request_tokens(m.H, m.W, c->J);
+            e.tokens[q] = (N + 15) & ~15;  // rows start 16-aligned
+            e.units += work_units(N);
           }
         }
-        bool shed_this = false;
-        if (shed && ju > 0.0) {
-          // plan with a safety margin: 3 ms (completion hand-off and output
-          // copies after the GPU span) plus 10 % of the estimate
-          auto late = [&](double units, double deadline) {
-            const double est = spu * units;
-            return start + 1.1 * est + 3.0e6 > deadline;
-          };
-          if (late(ju, (double)j->deadline)) shed_this = true;
-          else if (!batch.empty() && late(batch_units + ju, std::min(min_deadline, (double)j->deadline))) break;
-        }
-        if (!batch.empty() && (conflict || (!fits && !shed_this))) break;
-        c->queue.pop_front();
-        if (shed_this) {
-          j->status = REVO_SHED;
-        } else {
-          for (int q = 0; q < 2; ++q) {
-            tokens[q] += add[q];
-            if (j->mod[q].present && !j->mod[q].clean) rec_streams[q].push_back(j->stream);
+      }
+      SchedParams sp;
+      sp.shed = (c->cfg.flags & REVO_CFG_SHED) != 0;
+      sp.start_ns = std::max((double)now_ns(), c->busy_until_ns);
+      sp.ns_per_unit = 1e9 * c->sec_per_unit;
+      sp.cap_tokens = cap;
+      sp.max_batch = max_batch;
+      sp.fair_run = kFairRun;
+      sp.max_streams = c->cfg.max_streams;
+      plan_batch(sj.data(), nq, c->shed_run.data(), sp, dec.data());
+      const double start = sp.start_ns;
+      // the batch in submission order, as the ring updates below expect; the
+      // rest stays queued in order
+      {
+        std::deque<Job*> rest;
+        for (int i = 0; i < nq; ++i) {
+          Job* j = c->queue[i];
+          if (dec[i] == SCHED_KEEP) {
+            rest.push_back(j);
+            continue;
           }
-          if (ju > 0.0) {
-            batch_units += ju;
-            min_deadline = std::min(min_deadline, (double)j->deadline);
-          }
+          if (dec[i] == SCHED_SHED) j->status = REVO_SHED;
+          batch.push_back(j);
         }
-        batch.push_back(j);
+        c->queue.swap(rest);
       }
       batch_start = start;
+      seq = ++c->batch_seq;
     }
     c->cv_done.notify_all();  // queue space freed
 
@@ -483,21 +532,21 @@ void worker_main(revo_ctx* c) {
         if (!m.present) continue;
         if (m.clean) {
           // clean frames always refresh the references, shed or not
-          const int e = push_clean(c, j, q);
+          const int e = push_clean(c, j, q, seq);
           if (e) { m.error = e; j->status = REVO_FAILED; j->error = e; }
         } else if (j->status == REVO_DONE) {
+          // (submit checked that a clean frame of this size came first; its
+          // ring update can still have failed for memory)
           const Ring& ring = c->rings[q][j->stream];
           if (ring.frames.empty() || ring.H != m.H || ring.W != m.W) {
             m.error = REVO_ENOREF; j->status = REVO_FAILED; j->error = REVO_ENOREF;
-            continue;
           }
-          m.pred = (float*)c->pool.get((size_t)m.H * m.W * (q == 0 ? 3 : 1) * 4);
-          if (!m.pred) { m.error = REVO_ENOMEM; j->status = REVO_FAILED; j->error = REVO_ENOMEM; }
         }
       }
     }
     InFlight* f = new InFlight();
     f->batch.swap(batch);
+    f->seq = seq;
     f->record = c->calibrating.load();
     f->slot = slot;
     f->units = units;
@@ -529,6 +578,10 @@ int stage_mod(revo_ctx* c, Mod& m, const void* frame, const unsigned char* mask,
     m.mask = (uint8_t*)c->pool.get(px);
     if (!m.mask) return REVO_EAGAIN;
     if (hipMemcpyAsync(m.mask, mask, px, kind, c->copy) != hipSuccess) return REVO_EDEVICE;
+    // the prediction buffer is admitted here too, so that a queued job never
+    // fails for memory later
+    m.pred = (float*)c->pool.get(px * C * 4);
+    if (!m.pred) return REVO_EAGAIN;
   }
   if (!dev) {
     if (out_i && !(m.out_i_st = c->pool.get(m.frame_bytes))) return REVO_EAGAIN;
@@ -598,6 +651,8 @@ int revo_recover_create(const revo_config* cfg_in, revo_ctx** out) {
   c->prec = cfg.precision == REVO_BF16 ? P_BF16 : cfg.precision == REVO_FP8 ? P_FP8 : P_FP32;
   c->rings[0].resize(cfg.max_streams);
   c->rings[1].resize(cfg.max_streams);
+  c->sst.resize(cfg.max_streams);
+  c->shed_run.assign(cfg.max_streams, 0);
   int rc = 0;
   const int nstreams = (cfg.flags & REVO_CFG_ONE_STREAM) ? 1 : 2;
   for (int q = 0; q < nstreams && !rc; ++q)
@@ -605,6 +660,8 @@ int revo_recover_create(const revo_config* cfg_in, revo_ctx** out) {
   if (nstreams == 1) c->stream[1] = c->stream[0];
   if (!rc && hipStreamCreateWithFlags(&c->copy, hipStreamNonBlocking) != hipSuccess) rc = REVO_EDEVICE;
   if (!rc && hipStreamCreateWithFlags(&c->d2h, hipStreamNonBlocking) != hipSuccess) rc = REVO_EDEVICE;
+  if (!rc && cfg.hip_stream && hipEventCreateWithFlags(&c->caller_ev, hipEventDisableTiming) != hipSuccess)
+    rc = REVO_EDEVICE;
   for (int sl = 0; sl < WS_SLOTS && !rc; ++sl)
     for (int q = 0; q < 2 && !rc; ++q)
       if (hipEventCreateWithFlags(&c->done_ev[sl][q], hipEventDisableTiming) != hipSuccess) rc = REVO_EDEVICE;
@@ -682,7 +739,11 @@ int revo_recover_submit(revo_ctx* c, const revo_request* r, unsigned long long* 
   {
     std::lock_guard<std::mutex> lk(c->copy_mu);
     (void)hipSetDevice(c->cfg.device);
-    if (r->rgb) rc = stage_mod(c, j->mod[0], r->rgb, r->mask_rgb, r->rgb_out, r->rgb_out_f32, 3, r->height, r->width, dev);
+    // the input copies come after the caller's work already on its stream
+    if (c->caller_ev && (hipEventRecord(c->caller_ev, (hipStream_t)c->cfg.hip_stream) != hipSuccess ||
+                         hipStreamWaitEvent(c->copy, c->caller_ev, 0) != hipSuccess))
+      rc = REVO_EDEVICE;
+    if (!rc && r->rgb) rc = stage_mod(c, j->mod[0], r->rgb, r->mask_rgb, r->rgb_out, r->rgb_out_f32, 3, r->height, r->width, dev);
     if (!rc && r->depth)
       rc = stage_mod(c, j->mod[1], r->depth, r->mask_depth, r->depth_out, r->depth_out_f32, 1, r->height, r->width, dev);
     if (hipStreamSynchronize(c->copy) != hipSuccess && !rc) rc = REVO_EDEVICE;
@@ -692,11 +753,29 @@ int revo_recover_submit(revo_ctx* c, const revo_request* r, unsigned long long* 
     delete j;
     return rc;
   }
-  j->ticket = c->next_ticket++;
-  if (ticket) *ticket = j->ticket;
   {
+    // A recovery needs a clean frame of its stream and modality at its own
+    // size submitted before it (Sec. 3.4.1: the k closest clean frames are
+    // its input); a clean frame becomes that stream's reference.  Checked in
+    // queue order, so tickets follow the queue.
     std::lock_guard<std::mutex> lk(c->mu);
-    c->queue.push_back(j);
+    revo_ctx::StreamState& ss = c->sst[j->stream];
+    for (int q = 0; q < 2 && !rc; ++q) {
+      const Mod& m = j->mod[q];
+      if (m.present && !m.clean && (ss.clean_h[q] != m.H || ss.clean_w[q] != m.W)) rc = REVO_ENOREF;
+    }
+    if (!rc) {
+      for (int q = 0; q < 2; ++q)
+        if (j->mod[q].present && j->mod[q].clean) { ss.clean_h[q] = j->mod[q].H; ss.clean_w[q] = j->mod[q].W; }
+      j->ticket = c->next_ticket++;
+      if (ticket) *ticket = j->ticket;
+      c->queue.push_back(j);
+    }
+  }
+  if (rc) {
+    for (int q = 0; q < 2; ++q) release_mod(c, j->mod[q], q == 0 ? 3 : 1);
+    delete j;
+    return rc;
   }
   c->cv_work.notify_one();
   return REVO_OK;
@@ -749,6 +828,11 @@ int revo_get_stats(revo_ctx* c, revo_stats* out, int reset) {
   std::lock_guard<std::mutex> lk(c->stats_mu);
   *out = c->stats;
   if (reset) memset(&c->stats, 0, sizeof(c->stats));
+  {
+    std::lock_guard<std::mutex> pl(c->pool.mu);
+    out->hbm_fixed_bytes = (long long)c->pool.fixed;
+    out->hbm_pool_bytes = (long long)c->pool.live;
+  }
   return REVO_OK;
 }
 
@@ -774,7 +858,10 @@ void revo_recover_destroy(revo_ctx* c) {
     workspace_free(c->ws[q]);
     model_free(c->model[q]);
   }
+  for (auto& d : c->deferred) c->pool.put(d.p, d.n);  // every batch has completed
+  c->deferred.clear();
   c->pool.clear();
+  if (c->caller_ev) (void)hipEventDestroy(c->caller_ev);
   if (c->stream[0]) (void)hipStreamDestroy(c->stream[0]);
   if (c->stream[1] && c->stream[1] != c->stream[0]) (void)hipStreamDestroy(c->stream[1]);
   if (c->copy) (void)hipStreamDestroy(c->copy);

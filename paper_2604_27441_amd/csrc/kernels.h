@@ -2,7 +2,7 @@
 #pragma once
 #include "common.h"
 
-#define REVO_MAX_FRAMES 8
+#define REVO_MAX_FRAMES 9
 #define REVO_PATCH 16
 
 namespace revo {

@@ -91,7 +91,8 @@ def test_ragged_sizes_fp32(H, W):
     assert e["rgb_maxabs"] <= 1e-4 and e["depth_maxabs"] <= 0.5, e
 
 
-@pytest.mark.parametrize("k,T,n_ref", [(5, 2, 2), (4, 2, None), (5, 3, None), (3, 1, None), (7, 2, 5)])
+@pytest.mark.parametrize("k,T,n_ref", [(5, 2, 2), (4, 2, None), (5, 3, None), (3, 1, None), (7, 2, 5), (7, 3, None),
+                                       (6, 3, 4)])
 def test_history_and_tubelet_variants(k, T, n_ref):
     req = synth.make_request(41, 42, 48, 64, k=k, loss=("stripes", 0.5))
     out, ref = _small(FP32, req, k=k, T=T, n_ref=n_ref)
@@ -143,13 +144,10 @@ def test_references_reused_across_later_targets():
     assert compare(later, b, rb)["rgb_maxabs"] <= 1e-4
 
 
-def test_clean_frame_copy_and_missing_references():
+def test_clean_frame_copy_and_resolution_change():
     blobs = synth.make_weights(3, **SMALL)
     req = synth.make_request(81, 82, 32, 48, loss=("stripes", 0.5))
     with _rec(blobs, BF16, **SMALL) as rec:
-        # recovery before any clean frame of the stream
-        out = recover(rec, [(5, req)])[0]
-        assert out["completion"].status == 2 and out["completion"].error == -61
         # a clean frame comes back unchanged
         clean = dict(req)
         clean["mask_rgb"] = np.zeros_like(req["mask_rgb"])
@@ -157,10 +155,18 @@ def test_clean_frame_copy_and_missing_references():
         push_refs(rec, 5, req)
         out = recover(rec, [(5, clean)])[0]
         assert np.array_equal(out["rgb"], req["rgb"]) and np.array_equal(out["depth"], req["depth"])
-        # a resolution change drops the stream's references
+        # a resolution change starts a new reference set: one clean frame at
+        # the new size serves (repeated as the oldest, k - 1 times)
         other = synth.make_request(83, 84, 48, 64, loss=("stripes", 0.5))
+        push_refs(rec, 5, other, n_ref=1)
         out = recover(rec, [(5, other)])[0]
-        assert out["completion"].status == 2 and out["completion"].error == -61
+        assert out["completion"].status == 0
+    r1 = dict(other)
+    for key in ("rgb_refs", "depth_refs", "ref_idx"):
+        r1[key] = other[key][-1:]
+    ref = oracle.recover(r1, blobs, **SMALL)
+    e = compare(other, out, ref)
+    assert e["rgb_psnr"] >= 40, e
 
 
 @pytest.mark.parametrize("loss", [0.10, 0.30, 0.50])
