@@ -381,6 +381,7 @@ def serve_bench(blobs, streams, seconds, warm_seconds, cap_tokens, log, seed=0):
             if not any(f - 29 <= g <= f for g in good) and seq[0][0] <= f - 29:
                 frozen += 1
                 break
+    out = {
         "streams": streams, "seconds": seconds, "offered_recoveries_per_s": n_rec / seconds,
         "served_pairs_per_s": len(ok) / seconds, "shed_fraction": shed / max(1, n_rec),
         "failed": sum(1 for c, _ in served if c.status == 2),
