@@ -369,13 +369,13 @@ def serve_bench(blobs, streams, seconds, warm_seconds, cap_tokens, log, seed=0):
     fracs, runs, frozen = [], [], 0
     for sid, seq in by_stream.items():
         seq.sort()
-        fracs.append(sum(ok for _, ok in seq) / len(seq))
+        fracs.append(sum(hit for _, hit in seq) / len(seq))
         run = best = 0
-        for _, ok in seq:
-            run = 0 if ok else run + 1
+        for _, hit in seq:
+            run = 0 if hit else run + 1
             best = max(best, run)
         runs.append(best)
-        good = [f for f, ok in seq if ok]
+        good = [f for f, hit in seq if hit]
         for f, _ in seq:
             # the window of 30 frames ending at this recovery
             if not any(f - 29 <= g <= f for g in good) and seq[0][0] <= f - 29:
