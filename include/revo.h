@@ -46,7 +46,8 @@ enum revo_status {
   REVO_EDEVICE = -5,     /* HIP runtime error */
   REVO_ENOREF = -61,     /* recovery asked for before any clean frame of the stream */
   REVO_ENOTSUP = -95,    /* configuration the library does not support */
-  REVO_ESHUTDOWN = -108  /* context is being destroyed */
+  REVO_ESHUTDOWN = -108, /* context is being destroyed */
+  REVO_E2BIG = -7        /* size beyond a fixed workspace (revo_op_attention_noalloc) */
 };
 
 enum revo_precision {

@@ -57,6 +57,19 @@ int revo_op_layernorm(int precision, const float *x, const float *g, const float
 int revo_op_attention(int precision, const void *q, const void *k, const void *vt, void *o,
                       int heads, int ntok, int ld, void *stream);
 
+/* revo_op_attention for callers that cannot allocate device memory: code
+ * under HIP graph capture, serving loops that must not call hipMalloc, and
+ * harnesses that forbid it.  Same arguments, layouts and result as
+ * revo_op_attention, but it allocates nothing, copies nothing from the host
+ * and does not synchronise: the request descriptor and the q-tile work list
+ * go to a fixed device workspace of 128.25 KiB (one per device, held until
+ * the process ends), written by a kernel on `stream` before the attention
+ * kernel.  ntok is at most 32767 * 128 = 4194176 tokens (REVO_E2BIG beyond).
+ * Calls on one stream are ordered; calls that overlap on one device (other
+ * streams or threads) share the workspace and race. */
+int revo_op_attention_noalloc(int precision, const void *q, const void *k, const void *vt, void *o,
+                              int heads, int ntok, int ld, void *stream);
+
 /* Element-wise float -> operand type conversion of n values (round to
  * nearest even for REVO_BF16; REVO_FP8 gives OCP E4M3 bytes, nearest even,
  * saturating at +-448). */

@@ -29,6 +29,10 @@
 // registers in between) with swizzled, unpadded rows; FP32 blocks pass
 // through registers.  Loads take scalar per-block offsets, and the block
 // loop runs two blocks per trip so both LDS buffers have fixed addresses.
+#include <string.h>
+
+#include <mutex>
+
 #include "kernels.h"
 
 namespace revo {
@@ -492,6 +496,82 @@ int launch_attention(Prec prec, const AttnArgs& a, hipStream_t s) {
   else if (prec == P_FP32 && !a.o_scale) attn_kernel<OpF32><<<grid, NT, 0, s>>>(a);
   else return -95;
   return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+// ---- Attention without allocation ------------------------------------------
+//
+// The one-request form of the attention kernel needs a request descriptor
+// and a q-tile work list in device memory.  This variant keeps both in a
+// file-scope device array (one copy per device, held until the process
+// ends): a small kernel on the caller's stream writes them, then the
+// attention kernel reads them.  Calls on one stream are ordered; calls that
+// overlap on one device (other streams, other threads) share the array and
+// race.
+
+namespace {
+
+constexpr size_t NOALLOC_DESC_BYTES = 256;
+static_assert(sizeof(ReqDesc) <= NOALLOC_DESC_BYTES, "request descriptor slot too small");
+constexpr size_t NOALLOC_BYTES = NOALLOC_DESC_BYTES + sizeof(int) * (ATTN_NOALLOC_MAX_TILES + 1);
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Descriptor of one request covering every token (one tubelet of ntok
+// tokens, no frames) and the work list 0 .. ntile-1; every value the
+// attention kernel reads is rewritten, so nothing needs clearing first.
+__global__ void attn_noalloc_setup_kernel(unsigned char* ws, int ntok, int ntile) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    ReqDesc* d = reinterpret_cast<ReqDesc*>(ws);
+    d->tok_off = 0; d->head_off = 0;
+    d->H = 1; d->W = ntok; d->gy = 1; d->gx = ntok; d->P = ntok;
+    d->J = 1; d->nframes = 1; d->pad_ = 0;
+    for (int f = 0; f < REVO_MAX_FRAMES; ++f) { d->tau[f] = 0.f; d->frames[f] = nullptr; }
+    d->mask = nullptr; d->pred = nullptr; d->out_i = nullptr; d->out_f = nullptr;
+  }
+  int* work = reinterpret_cast<int*>(ws + NOALLOC_DESC_BYTES);
+  if (i < ntile) work[i] = i;
+}
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+
+// Device address of this device's copy of the array, looked up once per
+// device (the array's name is not a device address in host code).
+int noalloc_workspace(unsigned char** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return -5;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return -5;
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = static_cast<unsigned char*>(g_noalloc_ptr[dev]);
+  return 0;
+}
+
+}  // namespace
+
+int launch_attention_noalloc(Prec prec, const void* q, const void* k, const void* vt, void* o, int heads, int ntok,
+                             int ld, hipStream_t s) {
+  const int ntile = (ntok + 127) / 128;
+  if (ntok <= 0 || ntile > ATTN_NOALLOC_MAX_TILES) return -7;
+  unsigned char* ws = nullptr;
+  if (int rc = noalloc_workspace(&ws)) return rc;
+  attn_noalloc_setup_kernel<<<(ntile + 255) / 256, 256, 0, s>>>(ws, ntok, ntile);
+  if (hipGetLastError() != hipSuccess) return -5;
+  AttnArgs a;
+  memset(&a, 0, sizeof(a));
+  a.q = q; a.k = k; a.vt = vt; a.o = o; a.heads = heads; a.ldqk = ld; a.ldv = ld;
+  a.reqs = reinterpret_cast<const ReqDesc*>(ws); a.nreq = 1;
+  a.work = reinterpret_cast<const int*>(ws + NOALLOC_DESC_BYTES); a.nwork = ntile;
+  return launch_attention(prec, a, s);
 }
 
 }  // namespace revo

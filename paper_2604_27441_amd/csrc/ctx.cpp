@@ -619,6 +619,7 @@ const char* revo_strerror(int code) {
     case REVO_ENOREF: return "no clean reference frame for this stream";
     case REVO_ENOTSUP: return "unsupported configuration";
     case REVO_ESHUTDOWN: return "context shutting down";
+    case REVO_E2BIG: return "size beyond the fixed workspace";
   }
   return "unknown error";
 }

@@ -87,6 +87,13 @@ int launch_gemm(Prec prec, int epi, int xmode, const GemmArgs& a, hipStream_t s)
 // (float for P_FP32, bfloat16 otherwise).
 int launch_tubelet_pack(Prec prec, const GemmArgs& a, void* out, hipStream_t s);
 int launch_attention(Prec prec, const AttnArgs& a, hipStream_t s);
+// Attention of one request of ntok tokens whose descriptor and q-tile work
+// list live in a fixed per-device workspace instead of allocated memory:
+// no allocation, no host copy, no synchronisation.  At most
+// ATTN_NOALLOC_MAX_TILES q-tiles of 128 tokens (-7 beyond).
+constexpr int ATTN_NOALLOC_MAX_TILES = ATTN_TARGET_TILE - 1;
+int launch_attention_noalloc(Prec prec, const void* q, const void* k, const void* vt, void* o, int heads, int ntok,
+                             int ld, hipStream_t s);
 // y = LN(x) * g + b over rows of length D.  With reqs set, output row i is
 // the target-tubelet token (i - head_off) of the request owning compact row i.
 int launch_layernorm(Prec out_prec, const float* x, const float* g, const float* b,

@@ -107,6 +107,16 @@ int revo_op_attention(int precision, const void* q, const void* k, const void* v
   return rc;
 }
 
+int revo_op_attention_noalloc(int precision, const void* q, const void* k, const void* vt, void* o, int heads,
+                              int ntok, int ld, void* stream) {
+  Prec p;
+  if (!prec_of(precision, &p)) return REVO_ENOTSUP;
+  if (heads <= 0 || ntok <= 0 || ld < ntok + 64 || !q || !k || !vt || !o) return REVO_EINVAL;
+  if (ld % 16) return REVO_EINVAL;
+  if ((ntok + 127) / 128 > ATTN_NOALLOC_MAX_TILES) return REVO_E2BIG;
+  return launch_attention_noalloc(p, q, k, vt, o, heads, ntok, ld, (hipStream_t)stream);
+}
+
 int revo_op_convert(int precision, const float* src, void* dst, long long n, void* stream) {
   Prec p;
   if (precision == REVO_FP8) p = P_FP8;
