@@ -491,12 +491,12 @@ def fp8_bench(blobs, c3, steps, log):
     return res
 
 
-def sweep_kt(log, reps=5):
+def sweep_kt(log, reps=3):
     """Per-frame recovery latency at 1280x720 (one RGB-D pair, BF16) over
     k in 1..7 clean references and tubelet T in {1, 2, 3}: the shape of the
     paper's latency-versus-k and k x T ablations (App. B.3), here with
-    seeded weights.  Combinations needing more than 8 input frames are
-    skipped."""
+    seeded weights.  k + 1 frames are padded up to whole tubelets by
+    repeating the oldest reference (at most 9 frames: k = 7 at T = 3)."""
     import synth
     from paper_2604_27441_amd import Recoverer
     from tests.gpu_util import push_refs, recover
@@ -505,7 +505,7 @@ def sweep_kt(log, reps=5):
         blobs = synth.make_weights(0, tubelet=T)
         for k in range(1, 8):
             nframes = -(-(k + 1) // T) * T
-            if nframes > 8:
+            if nframes > 9:
                 continue
             req = synth.make_request(1003, 2003, 720, 1280, k=k, loss=("ge", 0.2))
             rec = Recoverer(blobs[0], blobs[1], precision=1, device=0, k=k, tubelet=T,
@@ -536,6 +536,61 @@ def attention_traffic():
     if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
         return None
     return rec["bytes_per_launch"]
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def small_configs_bench(blobs, log, steps=20, oracle_runs=True):
+    """The plain FP32 form at 256x192 (stripes, p = 0.2) and at 640x480
+    (Gilbert-Elliott loss 10, 30 and 50 %, burst 4), batch 1: frames/s and
+    p50 latency through the ABI, and at 256x192 and 640x480 / 10 % the error
+    against the FP64 oracle, whose own seconds per pair (both modalities,
+    full network) are timed beside it."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    import oracle
+    import synth
+    from tests.gpu_util import compare
+
+    threads = sum(i.get("num_threads", 0) for i in threadpool_info() if i.get("user_api") == "blas") or os.cpu_count()
+    cases = [("256x192", synth.make_batch("c1")[0], True)]
+    for L in (0.1, 0.3, 0.5):
+        cases.append((f"640x480 loss {int(L * 100)}%", synth.make_request(1002, 2002, 480, 640, loss=("ge", L)),
+                      L == 0.1))
+    rows = {}
+    for name, req, with_oracle in cases:
+        r = run_form(0, [req], blobs, steps, 3, lambda m: None, profile=False)
+        o = r.pop("outputs")
+        row = {"frames_per_s": r["pairs"] / r["seconds"], "ms_per_pair": r["ms_per_step"], "p50_ms": r["p50_ms"],
+               "p99_ms": r["p99_ms"], "lost_fraction_rgb": float(np.mean(req["mask_rgb"] != 0))}
+        if with_oracle and oracle_runs:
+            t = time.perf_counter()
+            ref = oracle.recover(req, blobs)
+            row["oracle_seconds_per_pair"] = time.perf_counter() - t
+            row["oracle_threads"] = int(threads)
+            # one more recovery with float outputs for the error figures
+            from paper_2604_27441_amd import Recoverer
+            from tests.gpu_util import push_refs, recover
+            with Recoverer(blobs[0], blobs[1], precision=0, device=0, max_batch_tokens=10800 + 64) as rec:
+                push_refs(rec, 0, req)
+                got = recover(rec, [(0, req)])[0]
+            e = compare(req, got, ref)
+            row["fp32_vs_fp64"] = {"rgb_psnr_db": e["rgb_psnr"], "rgb_maxabs": e["rgb_maxabs"],
+                                   "depth_maxabs_mm": e["depth_maxabs"], "depth_rms_lost_mm": e["depth_rms_lost"]}
+        rows[name] = row
+        log(f"fp32 {name}: {row['frames_per_s']:.1f} pairs/s"
+            + (f", oracle {row['oracle_seconds_per_pair']:.1f} s per pair, error {row['fp32_vs_fp64']}"
+               if "oracle_seconds_per_pair" in row else ""))
+    return rows
 
 
 def cpu_baseline(req, log):
@@ -575,6 +630,8 @@ def cpu_baseline(req, log):
                    f"({t11:.1f} s) plus one encoder block ({t_enc:.1f} s) and one decoder block ({t_dec:.1f} s) "
                    "timed alone; pair = 2 x (t11 + 11 enc + 3 dec)"),
         "seconds_per_pair": pair_s,
+        "cpu_model": cpu_model(),
+        "logical_cpus": os.cpu_count(),
     }
 
 
@@ -588,7 +645,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--one-stream", action="store_true",
                     help="run RGB and depth one after the other on one stream (clean per-kernel times)")
-    ap.add_argument("--sweep-kt", action="store_true", help="latency over k = 1..7 and T = 1..3 (1280x720)")
+    ap.add_argument("--no-sweep-kt", action="store_true", help="skip the latency sweep over k = 1..7, T = 1..3")
+    ap.add_argument("--no-small", action="store_true", help="skip the FP32 256x192 and 640x480 lines")
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 form (batch 8)")
     ap.add_argument("--fp8-steps", type=int, default=5)
     ap.add_argument("--serve-seconds", type=float, default=6.0, help="measured serving window (0 = skip)")
@@ -723,8 +781,10 @@ def main():
         }
     if not args.no_fp8:
         out["fp8"] = fp8_bench(blobs, reqs, args.fp8_steps, log)
-    if args.sweep_kt:
+    if not args.no_sweep_kt:
         out["k_t_sweep"] = sweep_kt(log)
+    if not args.no_small:
+        out["fp32_small"] = small_configs_bench(blobs, log, oracle_runs=not args.no_cpu_baseline)
     if args.serve_seconds > 0:
         out["serving"] = serve_bench(blobs, args.serve_streams, args.serve_seconds, args.serve_warmup,
                                      args.serve_cap, log)

@@ -170,6 +170,10 @@ struct revo_ctx {
   long long last_done_ns = 0;
   int device_error = 0;
   double sec_per_unit = 3e-11;  // cost model for shedding: seconds per work unit (guarded by mu)
+  // completion time minus predicted completion of recent batches (ns,
+  // guarded by mu): its tail widens the shedding margin
+  std::vector<double> lateness;
+  size_t lateness_next = 0;
   // per stream (guarded by mu): frame size of the last clean frame submitted
   // per modality (a recovery needs one at its own size), and the run of
   // recoveries shed since the last one admitted to a batch (sched.h)
@@ -202,6 +206,19 @@ const int kMaxQueue = 4096;
 // every stream keeps a served recovery in every GoP-long window while the GPU
 // can afford one per stream per kFairRun frames).
 const int kFairRun = 15;
+
+// Shedding margin: 3 ms, or the 99th percentile of how late the last
+// kLatenessWindow batches completed against their prediction plus 1 ms,
+// whichever is larger (at most 10 ms).
+const size_t kLatenessWindow = 256;
+
+double shed_margin_ns(const std::vector<double>& late) {
+  if (late.size() < 16) return 3e6;
+  std::vector<double> v(late);
+  const size_t k = (v.size() * 99) / 100;
+  std::nth_element(v.begin(), v.begin() + k, v.end());
+  return std::min(10e6, std::max(3e6, v[k] + 1e6));
+}
 
 void release_mod(revo_ctx* c, Mod& m, int C) {
   const size_t px = (size_t)m.H * m.W;
@@ -372,6 +389,11 @@ void complete_batch(revo_ctx* c, InFlight* f) {
     const double span = (double)(t_done - std::max(f->t_enq, c->last_done_ns)) * 1e-9;
     if (f->units > 0.0 && rc == 0 && span > 0.0) c->sec_per_unit = 0.7 * c->sec_per_unit + 0.3 * (span / f->units);
     c->last_done_ns = t_done;
+    if (f->units > 0.0 && rc == 0) {
+      const double late = (double)t_done - f->predicted_done_ns;
+      if (c->lateness.size() < kLatenessWindow) c->lateness.push_back(late);
+      else c->lateness[c->lateness_next++ % kLatenessWindow] = late;
+    }
     if (c->inflight.size() > 1) c->busy_until_ns += (double)t_done - f->predicted_done_ns;
     else c->busy_until_ns = (double)t_done;
   }
@@ -496,6 +518,7 @@ void worker_main(revo_ctx* c) {
       sp.max_batch = max_batch;
       sp.fair_run = kFairRun;
       sp.max_streams = c->cfg.max_streams;
+      sp.margin_ns = shed_margin_ns(c->lateness);
       plan_batch(sj.data(), nq, c->shed_run.data(), sp, dec.data());
       const double start = sp.start_ns;
       // the batch in submission order, as the ring updates below expect; the

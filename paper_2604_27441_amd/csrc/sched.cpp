@@ -11,7 +11,7 @@ int plan_batch(const SchedJob* q, int n, int* shed_run, const SchedParams& p, in
   int count = 0, tokens[2] = {0, 0};
   double units = 0.0, min_deadline = 1e300;
   std::vector<unsigned> rec_streams[2];
-  auto late = [&](double u, double deadline) { return p.start_ns + 1.1 * p.ns_per_unit * u + 3.0e6 > deadline; };
+  auto late = [&](double u, double deadline) { return p.start_ns + 1.1 * p.ns_per_unit * u + p.margin_ns > deadline; };
   // 0 = taken or shed, 1 = does not fit, 2 = the batch is closed
   auto consider = [&](int i, bool in_order) -> int {
     const SchedJob& j = q[i];

@@ -21,6 +21,7 @@ struct SchedParams {
   int max_batch;        // jobs per batch (shed ones included)
   int fair_run;         // a stream with this many shed recoveries in a row goes first
   int max_streams;
+  double margin_ns;     // fixed part of the plan's safety margin
 };
 
 enum { SCHED_KEEP = 0, SCHED_TAKE = 1, SCHED_SHED = 2 };
@@ -43,7 +44,8 @@ inline double work_units(int N) { return (double)N * N + 2300.0 * N; }
 // deadline even alone, started at start_ns, is shed; the batch, which
 // completes at once, closes before a job that would make a member miss its
 // deadline.  The plan keeps a margin of
-// 3 ms (completion hand-off and output copies after the GPU span) plus 10 %.
+// margin_ns (completion hand-off and output copies after the GPU span, and
+// the cost model's recent tail error) plus 10 % of the predicted cost.
 int plan_batch(const SchedJob* q, int n, int* shed_run, const SchedParams& p, int* decision);
 
 }  // namespace revo

@@ -24,7 +24,7 @@ class Job(C.Structure):
 class Params(C.Structure):
     _fields_ = [("shed", C.c_bool), ("start_ns", C.c_double), ("ns_per_unit", C.c_double),
                 ("cap_tokens", C.c_int), ("max_batch", C.c_int),
-                ("fair_run", C.c_int), ("max_streams", C.c_int)]
+                ("fair_run", C.c_int), ("max_streams", C.c_int), ("margin_ns", C.c_double)]
 
 
 @pytest.fixture(scope="module")
@@ -47,7 +47,7 @@ def plan(tmp_path_factory):
         p = Params(shed=kw.get("shed", True), start_ns=kw.get("start", 0.0), ns_per_unit=kw.get("npu", 1.0),
                    cap_tokens=kw.get("cap", 1 << 20),
                    max_batch=kw.get("max_batch", 16), fair_run=kw.get("fair_run", 15),
-                   max_streams=len(shed_run))
+                   max_streams=len(shed_run), margin_ns=kw.get("margin", 3 * MS))
         arr = (Job * max(1, len(jobs)))(*jobs)
         run_arr = (C.c_int * len(shed_run))(*shed_run)
         dec = (C.c_int * max(1, len(jobs)))()
@@ -99,6 +99,14 @@ def test_deadline_shedding_and_runs(plan):
     jobs = [rec(0, 10, 24), rec(1, 10, 60)]   # together: 1.1 * 20 + 3 = 25 > 24
     n, dec = plan(jobs, run, start=0.0)
     assert dec == [TAKE, KEEP] and run == [0, 0, 0]
+
+
+def test_margin_is_a_parameter(plan):
+    # 1.1 * 20 + 3 = 25 fits a 26 ms deadline; with a 5 ms margin (a cost
+    # model that ran late) it is shed
+    run = [0]
+    assert plan([rec(0, 20, 26)], run)[1] == [TAKE]
+    assert plan([rec(0, 20, 26)], run, margin=5 * MS)[1] == [SHED] and run == [1]
 
 
 def test_starving_stream_goes_first(plan):
