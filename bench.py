@@ -551,8 +551,8 @@ def cpu_model():
 def small_configs_bench(blobs, log, steps=20, oracle_runs=True):
     """The plain FP32 form at 256x192 (stripes, p = 0.2) and at 640x480
     (Gilbert-Elliott loss 10, 30 and 50 %, burst 4), batch 1: frames/s and
-    p50 latency through the ABI, and at 256x192 and 640x480 / 10 % the error
-    against the FP64 oracle, whose own seconds per pair (both modalities,
+    p50 latency through the ABI, and at 256x192 and 640x480 / 30 % the error
+    against the FP64 oracle (the 10 % draw of that mask seed loses no slice), whose own seconds per pair (both modalities,
     full network) are timed beside it."""
     import numpy as np
     from threadpoolctl import threadpool_info
@@ -565,7 +565,7 @@ def small_configs_bench(blobs, log, steps=20, oracle_runs=True):
     cases = [("256x192", synth.make_batch("c1")[0], True)]
     for L in (0.1, 0.3, 0.5):
         cases.append((f"640x480 loss {int(L * 100)}%", synth.make_request(1002, 2002, 480, 640, loss=("ge", L)),
-                      L == 0.1))
+                      L == 0.3))
     rows = {}
     for name, req, with_oracle in cases:
         r = run_form(0, [req], blobs, steps, 3, lambda m: None, profile=False)

@@ -13,16 +13,27 @@ from tests.gpu_util import check_received_and_codes, push_refs, recover
 
 pytestmark = pytest.mark.gpu
 
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_720p_samples.json")
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+# sampled oracle outputs of requests 0 and 1 of the 1280x720 batch of 4
+GOLDEN = {0: os.path.join(GOLDEN_DIR, "c3_720p_samples.json"),
+          1: os.path.join(GOLDEN_DIR, "c3_720p_request1_samples.json")}
+GOLDEN_FP8 = os.path.join(GOLDEN_DIR, "c4_720p_fp8_samples.json")
 
 
 @pytest.fixture(scope="module")
 def c3():
-    return synth.make_batch("c3"), synth.make_weights(0), json.load(open(GOLDEN))
+    return synth.make_batch("c3"), synth.make_weights(0), {i: json.load(open(p)) for i, p in GOLDEN.items()}
 
 
-def _run(c3, prec):
+@pytest.fixture(scope="module")
+def c3_outs(c3):
+    return {}
+
+
+def _run(c3, prec, cache=None):
     from paper_2604_27441_amd import Recoverer
+    if cache is not None and prec in cache:
+        return cache[prec]
     reqs, blobs, _ = c3
     with Recoverer(blobs[0], blobs[1], precision=prec, max_batch_tokens=4 * 10800 + 64, max_batch=8) as rec:
         for s, r in enumerate(reqs):
@@ -31,24 +42,41 @@ def _run(c3, prec):
     for r, o in zip(reqs, outs):
         assert o["completion"].status == 0
         check_received_and_codes(r, o)
+    if cache is not None:
+        cache[prec] = outs
     return outs
 
 
-def _sample_errors(g, out):
+def _sample_errors(g, out, emu_key="oracle_bf16_rounding"):
     res = {}
-    for mod, key, scale in (("rgb", "rgb_f", 1.0), ("depth", "depth_f", 1.0)):
+    for mod, key in (("rgb", "rgb_f"), ("depth", "depth_f")):
         y, x = np.array(g[mod]["y"]), np.array(g[mod]["x"])
         ref = np.array(g[mod]["oracle"], np.float64)
-        emu = np.array(g[mod]["oracle_bf16_rounding"], np.float64)
+        emu = np.array(g[mod][emu_key], np.float64)
         got = out[key][y, x].astype(np.float64)
         lost = slice(0, 1536)  # the first 1536 samples are lost pixels, the rest received
         res[mod] = dict(err=got - ref, emu=emu - ref, lost=lost)
     return res
 
 
-def test_fullsize_fp32_samples(c3):
-    g = c3[2]
-    out = _run(c3, 0)[0]
+def _within_rounding_budget(e, tag):
+    """GPU error against FP64 on the lost samples: rms at most sqrt(2) times
+    (MSE at most twice) and max at most four times the rounding oracle's;
+    received samples are copies."""
+    for mod in ("rgb", "depth"):
+        err, emu = e[mod]["err"][:1536], e[mod]["emu"][:1536]
+        rms, rms_emu = np.sqrt(np.mean(err ** 2)), np.sqrt(np.mean(emu ** 2))
+        print(f"{tag} {mod}: rms {rms:.4g} (rounding oracle {rms_emu:.4g}), max {np.abs(err).max():.4g} "
+              f"(rounding oracle {np.abs(emu).max():.4g})")
+        assert np.abs(e[mod]["err"][1536:]).max() <= (6e-8 + 1e-9 if mod == "rgb" else 0.0)
+        assert rms <= np.sqrt(2.0) * rms_emu, (mod, rms, rms_emu)
+        assert np.abs(err).max() <= 4.0 * max(np.abs(emu).max(), 1e-6), mod
+
+
+@pytest.mark.parametrize("index", [0, 1])
+def test_fullsize_fp32_samples(c3, c3_outs, index):
+    g = c3[2][index]
+    out = _run(c3, 0, c3_outs)[index]
     e = _sample_errors(g, out)
     rgb, dep = e["rgb"], e["depth"]
     print("fp32 720p: rgb max", np.abs(rgb["err"]).max(), "depth max mm", np.abs(dep["err"]).max())
@@ -59,21 +87,41 @@ def test_fullsize_fp32_samples(c3):
     assert np.abs(dep["err"]).max() <= 1.0
 
 
-def test_fullsize_bf16_samples(c3):
-    g = c3[2]
-    out = _run(c3, 1)[0]
+@pytest.mark.parametrize("index", [0, 1])
+def test_fullsize_bf16_samples(c3, c3_outs, index):
+    g = c3[2][index]
+    out = _run(c3, 1, c3_outs)[index]
     e = _sample_errors(g, out)
-    for mod in ("rgb", "depth"):
-        err, emu = e[mod]["err"][:1536], e[mod]["emu"][:1536]
-        rms, rms_emu = np.sqrt(np.mean(err ** 2)), np.sqrt(np.mean(emu ** 2))
-        print(f"bf16 720p {mod}: rms {rms:.4g} (rounding oracle {rms_emu:.4g}), max {np.abs(err).max():.4g} "
-              f"(rounding oracle {np.abs(emu).max():.4g})")
-        assert np.abs(e[mod]["err"][1536:]).max() <= (6e-8 + 1e-9 if mod == "rgb" else 0.0)
-        assert rms <= np.sqrt(2.0) * rms_emu, (mod, rms, rms_emu)
-        assert np.abs(err).max() <= 4.0 * max(np.abs(emu).max(), 1e-6), mod
+    _within_rounding_budget(e, f"bf16 720p request {index}")
     rgb_all = e["rgb"]["err"]
     psnr = 10 * np.log10(1.0 / np.mean(rgb_all[:1536] ** 2))
     assert psnr >= 45.0, psnr
+
+
+def test_fullsize_fp8_samples():
+    """The FP8 form at its own size (1280x720, 12 + 4 blocks): calibrated
+    through the ABI on the same 8 seeded 1280x720 frames the fixture's
+    oracle calibrated on, request 0 of the batch of 8 stays within the
+    FP8-rounding oracle's error budget against FP64."""
+    from paper_2604_27441_amd import Recoverer
+    g = json.load(open(GOLDEN_FP8))
+    req = synth.make_batch("c4", n=1)[0]
+    calib = synth.make_calibration_set(720, 1280, n=8)
+    blobs = synth.make_weights(0)
+    with Recoverer(blobs[0], blobs[1], precision=2, max_batch_tokens=4 * 10800 + 64, max_batch=8,
+                   max_streams=16) as rec:
+        for sc in range(4):
+            push_refs(rec, 8 + sc, next(x for x in calib if x["scene"] == sc))
+        push_refs(rec, 0, req)
+        rec.calibrate(1)
+        for i in range(0, len(calib), 4):
+            for o in recover(rec, [(8 + x["scene"], x) for x in calib[i:i + 4]]):
+                assert o["completion"].status == 0
+        rec.calibrate(0)
+        out = recover(rec, [(0, req)])[0]
+    assert out["completion"].status == 0
+    check_received_and_codes(req, out)
+    _within_rounding_budget(_sample_errors(g, out, "oracle_fp8_rounding"), "fp8 720p")
 
 
 def test_fullsize_batch_members_are_independent(c3):
