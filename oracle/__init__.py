@@ -23,6 +23,7 @@ from .metrics import (
     frame_metrics, METRIC_KEYS,
 )
 from .render import unproject, project, render_view
+from . import train
 
 __all__ = [
     "Arch", "unpack_weights", "normalise", "zero_fill", "sequence_frames", "tubelet_vectors",

@@ -100,3 +100,23 @@ def make_calibration_set(height, width, n=32, mean_loss=0.3, scenes=4, k=5, burs
                             rgb=rt, depth=dt, mask_rgb=mr[i], mask_depth=md[i],
                             rgb_clean=rgb[k + i], depth_clean=depth[k + i]))
     return out
+
+
+def make_pretrain_batch(seed, batch, height, width, channels, k=5, mask_p=0.3):
+    """Seeded pretraining samples of one modality (Sec. 3.4.2: frames with
+    randomly masked pixels): per sample a scene (seed 50000 + 1000 seed + i),
+    k clean references, the clean target frame and a per-pixel Bernoulli
+    mask (1 = masked, probability mask_p) that the network's input zero-fills.
+    channels 3 gives u8 RGB frames, 1 gives u16 depth frames in mm."""
+    H, W = int(height), int(width)
+    out = []
+    for i in range(batch):
+        s = 50000 + 1000 * seed + i
+        ref_idx = np.arange(4, 4 + k, dtype=np.int64)
+        t = 4 + k
+        rgb, depth = scene_frames(s, H, W, list(ref_idx) + [t])
+        frames = rgb if channels == 3 else depth
+        mask = (np.random.default_rng(s + 500).random((H, W)) < mask_p).astype(np.uint8)
+        out.append(dict(height=H, width=W, ref_idx=ref_idx, t_target=t, refs=np.ascontiguousarray(frames[:k]),
+                        target=np.ascontiguousarray(frames[k]), mask=mask))
+    return out

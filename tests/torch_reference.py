@@ -26,7 +26,7 @@ def _pe(D, tau, gy, gx):
 
 class Params:
     def __init__(self, blob, C, T, De, ne, Dd, nd):
-        self.t = torch.tensor(blob, dtype=torch.float64)
+        self.t = blob if isinstance(blob, torch.Tensor) else torch.tensor(blob, dtype=torch.float64)
         self.pos = 0
         L = T * 256 * C
         self.emb_w, self.emb_b = self.take(De, L), self.take(De)
@@ -61,8 +61,9 @@ def _block(x, p, heads):
 
 
 def predict(refs, ref_idx, target, t_target, mask, blob, C, k=5, T=2,
-            De=384, ne=12, heads_e=6, Dd=192, nd=4, heads_d=3):
-    """Prediction [H, W, C] in model units."""
+            De=384, ne=12, heads_e=6, Dd=192, nd=4, heads_d=3, as_tensor=False):
+    """Prediction [H, W, C] in model units (a float64 tensor that keeps the
+    autograd graph to blob with as_tensor, when blob is a tensor)."""
     P = Params(blob, C, T, De, ne, Dd, nd)
     scale = 255.0 if C == 3 else 4000.0
     tgt = torch.tensor(target, dtype=torch.float64) / scale
@@ -94,4 +95,4 @@ def predict(refs, ref_idx, target, t_target, mask, blob, C, k=5, T=2,
     z = F.layer_norm(z, (Dd,), P.dec_g, P.dec_b, eps=1e-6)
     o = F.linear(z, P.head_w, P.head_b).view(J, gy, gx, T, 16, 16, C)[J - 1, :, :, T - 1]
     img = o.permute(0, 2, 1, 3, 4).reshape(gy * 16, gx * 16, C)
-    return img[:H, :W].numpy()
+    return img[:H, :W] if as_tensor else img[:H, :W].numpy()
