@@ -6,6 +6,6 @@ arguments and uses PyTorch only for device memory and streams.  Importing
 it fails loudly when the library has not been built.
 """
 from ._lib import lib, LIB_PATH, RevoError, check
-from .api import Recoverer, Completion, REVO_FP32, REVO_BF16, REVO_FP8
+from .api import Recoverer, Trainer, Completion, REVO_FP32, REVO_BF16, REVO_FP8
 
-__all__ = ["lib", "LIB_PATH", "RevoError", "check", "Recoverer", "Completion", "REVO_FP32", "REVO_BF16", "REVO_FP8"]
+__all__ = ["lib", "LIB_PATH", "RevoError", "check", "Recoverer", "Trainer", "Completion", "REVO_FP32", "REVO_BF16", "REVO_FP8"]

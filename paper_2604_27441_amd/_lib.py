@@ -1,4 +1,4 @@
-"""ctypes declarations mirroring include/revo.h and include/revo_ops.h."""
+"""ctypes declarations mirroring include/revo.h, include/revo_ops.h and include/revo_train.h."""
 import ctypes as C
 import os
 
@@ -59,6 +59,22 @@ class RevoStats(C.Structure):
     ]
 
 
+class RevoTrainConfig(C.Structure):
+    _fields_ = [
+        ("device", C.c_int), ("channels", C.c_int), ("k", C.c_int), ("tubelet", C.c_int),
+        ("enc_depth", C.c_int), ("dec_depth", C.c_int), ("batch", C.c_int), ("height", C.c_int), ("width", C.c_int),
+        ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float), ("tv_weight", C.c_float),
+        ("weights", C.POINTER(C.c_float)), ("n_weights", C.c_size_t),
+    ]
+
+
+class RevoTrainBatch(C.Structure):
+    _fields_ = [
+        ("refs", C.c_void_p), ("target", C.c_void_p), ("mask", C.c_void_p),
+        ("ref_idx", C.POINTER(C.c_longlong)), ("t_target", C.POINTER(C.c_longlong)),
+    ]
+
+
 _sigs = {
     "revo_config_default": (None, [C.POINTER(RevoConfig)]),
     "revo_weight_count": (C.c_size_t, [C.c_int, C.c_int, C.c_int, C.c_int]),
@@ -79,6 +95,12 @@ _sigs = {
                                     C.c_int, C.c_void_p]),
     "revo_op_attention_noalloc": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
                                             C.c_int, C.c_int, C.c_void_p]),
+    "revo_train_create": (C.c_int, [C.POINTER(RevoTrainConfig), C.POINTER(C.c_void_p)]),
+    "revo_train_step": (C.c_int, [C.c_void_p, C.POINTER(RevoTrainBatch), C.POINTER(C.c_double)]),
+    "revo_train_get_weights": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "revo_train_get_grads": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "revo_train_get_pred": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "revo_train_destroy": (None, [C.c_void_p]),
     "revo_op_convert": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_longlong, C.c_void_p]),
     "revo_op_frame_metrics": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
                                         C.c_void_p, C.c_void_p]),

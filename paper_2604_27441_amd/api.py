@@ -1,11 +1,11 @@
-"""Python face of the C ABI: a Recoverer holds one revo_ctx."""
+"""Python face of the C ABI: a Recoverer holds one revo_ctx, a Trainer one revo_trainer."""
 import ctypes as C
 from dataclasses import dataclass
 
 import numpy as np
 
 from . import _lib
-from ._lib import lib, check, RevoConfig, RevoRequest, RevoCompletion
+from ._lib import lib, check, RevoConfig, RevoRequest, RevoCompletion, RevoTrainConfig, RevoTrainBatch
 
 REVO_FP32, REVO_BF16, REVO_FP8 = 0, 1, 2
 
@@ -139,3 +139,65 @@ class Recoverer:
 
 def weight_count(channels, tubelet=2, enc_depth=12, dec_depth=4):
     return int(lib.revo_weight_count(channels, tubelet, enc_depth, dec_depth))
+
+
+class Trainer:
+    """revo_train_create / step / get_* / destroy: the FP32 pretraining step
+    of one modality's model (channels 3 RGB, 1 depth) at a fixed batch shape."""
+
+    def __init__(self, weights, channels, batch, height, width, device=0, k=5, tubelet=2, enc_depth=12,
+                 dec_depth=4, lr=0.0, beta1=0.0, beta2=0.0, eps=0.0, tv_weight=0.0):
+        self._w = np.ascontiguousarray(weights, dtype=np.float32)
+        cfg = RevoTrainConfig(device=device, channels=channels, k=k, tubelet=tubelet, enc_depth=enc_depth,
+                              dec_depth=dec_depth, batch=batch, height=height, width=width, lr=lr, beta1=beta1,
+                              beta2=beta2, eps=eps, tv_weight=tv_weight,
+                              weights=self._w.ctypes.data_as(C.POINTER(C.c_float)), n_weights=self._w.size)
+        h = C.c_void_p()
+        check(lib.revo_train_create(C.byref(cfg), C.byref(h)), "revo_train_create")
+        self._h = h
+        self.count = self._w.size
+        self.pred_count = batch * height * width * channels
+        self.shape = (batch, height, width, channels)
+
+    def step(self, refs, target, mask, ref_idx, t_target):
+        """refs / target / mask: contiguous device tensors (see revo_train.h);
+        ref_idx [batch][k], t_target [batch]: host integers.  Returns the loss."""
+        ri = np.ascontiguousarray(ref_idx, dtype=np.int64)
+        tt = np.ascontiguousarray(t_target, dtype=np.int64)
+        b = RevoTrainBatch(refs=_ptr(refs), target=_ptr(target), mask=_ptr(mask),
+                           ref_idx=ri.ctypes.data_as(C.POINTER(C.c_longlong)),
+                           t_target=tt.ctypes.data_as(C.POINTER(C.c_longlong)))
+        loss = C.c_double()
+        check(lib.revo_train_step(self._h, C.byref(b), C.byref(loss)), "revo_train_step")
+        return loss.value
+
+    def _get(self, fn, n):
+        out = np.empty(n, np.float32)
+        check(fn(self._h, out.ctypes.data, n), fn.__name__)
+        return out
+
+    def weights(self):
+        return self._get(lib.revo_train_get_weights, self.count)
+
+    def grads(self):
+        return self._get(lib.revo_train_get_grads, self.count)
+
+    def pred(self):
+        return self._get(lib.revo_train_get_pred, self.pred_count).reshape(self.shape)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.revo_train_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

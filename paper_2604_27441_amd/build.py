@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librevo.so")
-SOURCES = ["gemm.hip", "attention.hip", "elementwise.hip", "metrics.hip", "render.hip", "model.cpp", "ctx.cpp", "sched.cpp", "ops.cpp"]
+SOURCES = ["gemm.hip", "attention.hip", "elementwise.hip", "metrics.hip", "render.hip", "model.cpp", "ctx.cpp", "sched.cpp", "ops.cpp", "train.hip", "train.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -434,6 +434,8 @@ __global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 3 : 2) void attn_
   // 16-byte chunks rather than one short piece per query row.
   const float l_tot = xhalf_sum(l_run);
   const int ql = wave * 32 + (lane & 31);  // this lane's query within the tile
+  if (sizeof(T) == 4 && a.lse && lane < 32 && q_local < N)
+    a.lse[(size_t)hd * a.ldqk + q] = m_run + log2f(l_tot);  // P = exp2(s - lse)
   uint8_t* st = reinterpret_cast<uint8_t*>(kv);
   __syncthreads();
   if (a.o_scale) {

@@ -79,6 +79,7 @@ struct AttnArgs {
   const int* dyn_nwork;  // nullable
   const int* dyn_nreq;   // nullable
   const float* o_scale;  // nullable: store o / (*o_scale) as FP8 E4M3
+  float* lse;            // nullable (FP32): [heads][ldqk] base-2 log of each query's normaliser
 };
 
 int launch_gemm(Prec prec, int epi, int xmode, const GemmArgs& a, hipStream_t s);

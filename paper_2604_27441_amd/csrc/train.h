@@ -1,0 +1,35 @@
+// Host launchers of the pretraining-step kernels (train.hip).
+#pragma once
+#include "kernels.h"
+
+namespace revo {
+
+// out[c][r] = in[r][c] for r < rows, c < cols.
+int launch_transpose(const float* in, float* out, int rows, int cols, int ld_in, int ld_out, hipStream_t s);
+// out[c] = sum over rows of x[r][c] (fixed order: 256-row chunks, then the
+// chunks); part holds max_chunks x cols floats.
+int launch_colsum(const float* x, int rows, int cols, int ld, float* part, int max_chunks, float* out, hipStream_t s);
+int launch_gelu_fwd(const float* h, float* g, long long n, hipStream_t s);
+int launch_gelu_bwd(const float* dg, const float* h, float* dh, long long n, hipStream_t s);
+// LayerNorm backward (y = LN(x) g + b, eps 1e-6): dres[row] += dL/dx,
+// xdy = xhat * dy; with rowmap, dy row i belongs to x / dres row rowmap[i].
+int launch_ln_bwd(const float* x, const float* g, const float* dy, float* dres, float* xdy, int rows, int D,
+                  const int* rowmap, hipStream_t s);
+// Batch loss mean_b [MSE + alpha TV(pred)] and its gradient dpred; part
+// receives nblocks partial sums of the loss.
+int launch_pretrain_loss(const float* pred, const void* gt, int B, int H, int W, int C, float alpha, float* dpred,
+                         double* part, int nblocks, hipStream_t s);
+// Dense head-output gradient [Mh_pad][256 C] of the target slot from dpred
+// (frames of frame_elems values each, request order).
+int launch_head_grad(const ReqDesc* reqs, int nreq, int Mh, int Mh_pad, int C, const float* dpred,
+                     long long frame_elems, float* dhead, hipStream_t s);
+// Attention backward from the saved forward (q scaled by log2(e)/8, k, v^T,
+// o, base-2 log normalisers lse) and dout: dqkv [M][3 heads 64]; dv is a
+// [heads][ld] scratch; work lists (request << 16) | 64-row block.
+int launch_attention_bwd(const float* q, const float* k, const float* vt, const float* o, const float* dout,
+                         const float* lse, float* dv, float* dqkv, int M, int heads, int ld, const ReqDesc* reqs,
+                         const int* work, int nwork, hipStream_t s);
+int launch_adam(float* p, const float* g, float* m, float* v, long long n, float lr, float b1, float b2, float eps,
+                float bc1, float bc2, hipStream_t s);
+
+}  // namespace revo

@@ -1,0 +1,525 @@
+// Kernels of the pretraining step (backward pass and Adam) of the recovery
+// network: the RGB objective MSE + alpha TV on the raw prediction of the
+// target frame (Sec. 3.4.2 RGB loss equation, used for both models in
+// pretraining), reverse-mode gradients of every layer, and Adam (Sec. 4;
+// Kingma & Ba 2015, Algorithm 1).  FP32 throughout.
+#include "train.h"
+
+namespace revo {
+
+namespace {
+
+constexpr int TB = 256;
+
+// erf by Abramowitz & Stegun 7.1.26 (|error| <= 1.5e-7), as the forward GELU
+__device__ inline float erf_as_t(float x) {
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+  const float poly = t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f),
+                              0.254829592f);
+  const float r = 1.0f - poly * __builtin_amdgcn_exp2f(-ax * ax * 1.4426950408889634f);
+  return copysignf(r, x);
+}
+
+// ---- transposes and column sums ---------------------------------------------
+
+// out[c][r] = in[r][c] for a rows x cols block (row pitches ld_in, ld_out)
+__global__ __launch_bounds__(TB) void transpose_kernel(const float* __restrict__ in, float* __restrict__ out, int rows,
+                                                       int cols, int ld_in, int ld_out) {
+  __shared__ float t[64][65];
+  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int i = ty; i < 64; i += 4) {
+    const int r = r0 + i, c = c0 + tx;
+    t[i][tx] = (r < rows && c < cols) ? in[(size_t)r * ld_in + c] : 0.0f;
+  }
+  __syncthreads();
+  for (int i = ty; i < 64; i += 4) {
+    const int c = c0 + i, r = r0 + tx;
+    if (c < cols && r < rows) out[(size_t)c * ld_out + r] = t[tx][i];
+  }
+}
+
+// Partial column sums of x [rows][cols] over chunks of `chunk` rows:
+// part[blockIdx.y][c].  64 columns x 4 row lanes per block.
+__global__ __launch_bounds__(TB) void colsum_part_kernel(const float* __restrict__ x, int rows, int cols, int ld,
+                                                         int chunk, float* __restrict__ part) {
+  __shared__ float red[4][64];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63), lane_r = threadIdx.x >> 6;
+  const int r0 = blockIdx.y * chunk, r1 = min(rows, r0 + chunk);
+  float s = 0.0f;
+  if (c < cols)
+    for (int r = r0 + lane_r; r < r1; r += 4) s += x[(size_t)r * ld + c];
+  red[lane_r][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (lane_r == 0 && c < cols)
+    part[(size_t)blockIdx.y * cols + c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+__global__ __launch_bounds__(TB) void colsum_final_kernel(const float* __restrict__ part, int nchunk, int cols,
+                                                          float* __restrict__ out) {
+  const int c = blockIdx.x * TB + threadIdx.x;
+  if (c >= cols) return;
+  float s = 0.0f;
+  for (int i = 0; i < nchunk; ++i) s += part[(size_t)i * cols + c];
+  out[c] = s;
+}
+
+// ---- elementwise ----------------------------------------------------------------
+
+__global__ __launch_bounds__(TB) void gelu_fwd_kernel(const float* __restrict__ h, float* __restrict__ g, long long n) {
+  for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB) {
+    const float v = h[i];
+    g[i] = 0.5f * v * (1.0f + erf_as_t(v * 0.70710678118654752f));
+  }
+}
+
+// dh = dg * GELU'(h), GELU'(v) = Phi(v) + v phi(v)
+__global__ __launch_bounds__(TB) void gelu_bwd_kernel(const float* __restrict__ dg, const float* __restrict__ h,
+                                                      float* __restrict__ dh, long long n) {
+  for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB) {
+    const float v = h[i];
+    const float cdf = 0.5f * (1.0f + erf_as_t(v * 0.70710678118654752f));
+    const float pdf = 0.3989422804014327f * __builtin_amdgcn_exp2f(-0.5f * v * v * 1.4426950408889634f);
+    dh[i] = dg[i] * (cdf + v * pdf);
+  }
+}
+
+// ---- LayerNorm backward -------------------------------------------------------------
+//
+// y = xhat g + b with xhat = (x - mean) rstd.  One wave per row:
+// dx = rstd (dy g - mean(dy g) - xhat mean(dy g xhat)), added into dres;
+// xdy = xhat dy for the gain gradient (its column sums).  With rowmap, row
+// i of dy / xdy belongs to row rowmap[i] of x and dres.
+__global__ __launch_bounds__(TB) void ln_bwd_kernel(const float* __restrict__ x, const float* __restrict__ g,
+                                                    const float* __restrict__ dy, float* __restrict__ dres,
+                                                    float* __restrict__ xdy, int rows, int D,
+                                                    const int* __restrict__ rowmap) {
+  const int wave = (blockIdx.x * TB + threadIdx.x) >> 6, lane = threadIdx.x & 63;
+  if (wave >= rows) return;
+  const int xr = rowmap ? rowmap[wave] : wave;
+  const float* xp = x + (size_t)xr * D;
+  const float* dp = dy + (size_t)wave * D;
+  constexpr int MAXE = 8;  // D <= 512
+  float xv[MAXE], gv[MAXE];
+  float s = 0.0f;
+#pragma unroll
+  for (int e = 0; e < MAXE; ++e) {
+    const int d = lane + 64 * e;
+    xv[e] = d < D ? xp[d] : 0.0f;
+    s += xv[e];
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  const float mean = s / D;
+  float v = 0.0f;
+#pragma unroll
+  for (int e = 0; e < MAXE; ++e) {
+    const int d = lane + 64 * e;
+    const float c = d < D ? xv[e] - mean : 0.0f;
+    v += c * c;
+  }
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const float rstd = 1.0f / sqrtf(v / D + 1e-6f);
+  float s1 = 0.0f, s2 = 0.0f;
+#pragma unroll
+  for (int e = 0; e < MAXE; ++e) {
+    const int d = lane + 64 * e;
+    if (d < D) {
+      const float xh = (xv[e] - mean) * rstd;
+      const float dyv = dp[d];
+      gv[e] = dyv * g[d];
+      s1 += gv[e];
+      s2 += gv[e] * xh;
+      xdy[(size_t)wave * D + d] = xh * dyv;
+      xv[e] = xh;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    s1 += __shfl_xor(s1, o);
+    s2 += __shfl_xor(s2, o);
+  }
+  const float m1 = s1 / D, m2 = s2 / D;
+  float* rp = dres + (size_t)xr * D;
+#pragma unroll
+  for (int e = 0; e < MAXE; ++e) {
+    const int d = lane + 64 * e;
+    if (d < D) rp[d] += rstd * (gv[e] - m1 - xv[e] * m2);
+  }
+}
+
+// ---- loss ---------------------------------------------------------------------------
+//
+// Per frame b: MSE(pred, gt) + alpha (mean |x forward difference| + mean |y
+// forward difference|) of pred, averaged over the batch.  dpred is the
+// gradient of that batch loss (sign(0) = 0 for the absolute values);
+// part[block] the block's share of the loss.  gt: u8 HWC (C = 3, / 255) or
+// u16 HW (C = 1, / 4000 mm).
+__global__ __launch_bounds__(TB) void pretrain_loss_kernel(const float* __restrict__ pred, const void* __restrict__ gt,
+                                                           int B, int H, int W, int C, float alpha,
+                                                           float* __restrict__ dpred, double* __restrict__ part) {
+  __shared__ double red[TB / 64];
+  const long long per = (long long)H * W * C;
+  const long long n = per * B;
+  const float inv_n = 1.0f / (float)per;
+  const float inv_h = W > 1 ? 1.0f / (float)((long long)H * (W - 1) * C) : 0.0f;
+  const float inv_v = H > 1 ? 1.0f / (float)((long long)(H - 1) * W * C) : 0.0f;
+  const float inv_b = 1.0f / (float)B;
+  double acc = 0.0;
+  for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB) {
+    const long long f = i / per, r = i - f * per;
+    const int ch = (int)(r % C);
+    const long long px = r / C;
+    const int y = (int)(px / W), x = (int)(px - (long long)y * W);
+    const float p = pred[i];
+    const float gv = C == 3 ? (float)((const uint8_t*)gt)[i] * (1.0f / 255.0f)
+                            : (float)((const uint16_t*)gt)[i] * (1.0f / 4000.0f);
+    const float e = p - gv;
+    float d = 2.0f * e * inv_n;
+    float l = e * e * inv_n;
+    auto sgn = [](float v) { return v > 0.0f ? 1.0f : (v < 0.0f ? -1.0f : 0.0f); };
+    if (x + 1 < W) {
+      const float t = pred[i + C] - p;
+      l += alpha * fabsf(t) * inv_h;
+      d -= alpha * sgn(t) * inv_h;
+    }
+    if (x > 0) d += alpha * sgn(p - pred[i - C]) * inv_h;
+    if (y + 1 < H) {
+      const float t = pred[i + (long long)W * C] - p;
+      l += alpha * fabsf(t) * inv_v;
+      d -= alpha * sgn(t) * inv_v;
+    }
+    if (y > 0) d += alpha * sgn(p - pred[i - (long long)W * C]) * inv_v;
+    dpred[i] = d * inv_b;
+    acc += (double)l;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < TB / 64; ++w) s += red[w];
+    part[blockIdx.x] = s * (1.0 / B);
+  }
+}
+
+// Head gradient rows: dhead[i][c] for compact target row i and slot column
+// c = (py 16 + px) C + ch takes dpred at pixel (16 ty + py, 16 tx + px),
+// channel ch of the row's request (0 outside the frame and past Mh).
+__global__ __launch_bounds__(TB) void head_grad_kernel(const ReqDesc* __restrict__ reqs, int nreq, int Mh, int Mh_pad,
+                                                       int C, const float* __restrict__ dpred, long long frame_elems,
+                                                       float* __restrict__ dhead) {
+  const int cols = 256 * C;
+  const long long n = (long long)Mh_pad * cols;
+  for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB) {
+    const int row = (int)(i / cols), c = (int)(i - (long long)row * cols);
+    float v = 0.0f;
+    if (row < Mh) {
+      const int r = find_req_head(reqs, nreq, row);
+      const ReqDesc& d = reqs[r];
+      const int p = row - d.head_off;
+      const int ty = p / d.gx, tx = p - ty * d.gx;
+      const int ch = c % C, px = (c / C) & 15, py = c / (16 * C);
+      const int Y = 16 * ty + py, X = 16 * tx + px;
+      if (Y < d.H && X < d.W) v = dpred[(long long)r * frame_elems + ((long long)Y * d.W + X) * C + ch];
+    }
+    dhead[i] = v;
+  }
+}
+
+// ---- attention backward ---------------------------------------------------------------
+//
+// Forward: Q arrives scaled, qs = q log2(e) / 8, and P_ij = exp2(qs_i . k_j -
+// lse_i) with lse the base-2 log of the row's normaliser.  With dO the
+// output gradient and Dv_i = dO_i . O_i, the gradient with respect to the
+// natural scores s_ij = q_i . k_j / 8 is dS_ij = P_ij (dO_i . v_j - Dv_i);
+// then dq_i = sum_j dS_ij k_j / 8, dk_j = sum_i dS_ij q_i / 8 =
+// sum_i dS_ij qs_i / log2(e), dv_j = sum_i P_ij dO_i.  Blocks of 64 queries x
+// 64 keys; each of 256 threads holds a 4 x 4 piece of a tile.
+
+// Dv[h][t] = sum_d dO[t][h 64 + d] O[t][h 64 + d]
+__global__ __launch_bounds__(TB) void attn_bwd_dot_kernel(const float* __restrict__ o, const float* __restrict__ dout,
+                                                          int M, int heads, int ld, float* __restrict__ dv) {
+  const int wave = (blockIdx.x * TB + threadIdx.x) >> 6, lane = threadIdx.x & 63;
+  if (wave >= M * heads) return;
+  const int t = wave / heads, h = wave - t * heads;
+  const size_t off = (size_t)t * heads * 64 + h * 64 + lane;
+  float s = o[off] * dout[off];
+  for (int k = 32; k > 0; k >>= 1) s += __shfl_xor(s, k);
+  if (lane == 0) dv[(size_t)h * ld + t] = s;
+}
+
+struct AttnBwdArgs {
+  const float* q;     // [heads][ld][64], scaled by log2(e) / 8
+  const float* k;     // [heads][ld][64]
+  const float* vt;    // [heads][64][ld]
+  const float* dout;  // [M][heads 64]
+  const float* lse;   // [heads][ld]
+  const float* dv;    // [heads][ld]
+  float* dqkv;        // [M][3 heads 64]: dq | dk | dv, head-major
+  int heads, ld;
+  const ReqDesc* reqs;
+  const int* work;    // (request << 16) | 64-row block
+  int nwork;
+};
+
+// Loads a 64 x 64 tile of a [rows][64] matrix (rows r0 .. r0+63, those at or
+// past rmax as zeros) into LDS [64][65].
+__device__ inline void load_rows(float (*t)[65], const float* __restrict__ src, int r0, int rmax) {
+  for (int i = threadIdx.x; i < 64 * 64; i += TB) {
+    const int r = i >> 6, c = i & 63;
+    t[r][c] = r0 + r < rmax ? src[(size_t)(r0 + r) * 64 + c] : 0.0f;
+  }
+}
+// V block from V^T [64][ld]: t[key][d] for keys c0 .. c0+63 below cmax
+__device__ inline void load_vt(float (*t)[65], const float* __restrict__ vt, int ld, int c0, int cmax) {
+  for (int i = threadIdx.x; i < 64 * 64; i += TB) {
+    const int d = i >> 6, c = i & 63;
+    t[c][d] = c0 + c < cmax ? vt[(size_t)d * ld + c0 + c] : 0.0f;
+  }
+}
+// dO block: t[row][d] from dout [M][heads 64] (head h)
+__device__ inline void load_dout(float (*t)[65], const float* __restrict__ dout, int heads, int h, int r0, int rmax) {
+  for (int i = threadIdx.x; i < 64 * 64; i += TB) {
+    const int r = i >> 6, c = i & 63;
+    t[r][c] = r0 + r < rmax ? dout[(size_t)(r0 + r) * heads * 64 + h * 64 + c] : 0.0f;
+  }
+}
+
+// P and dS of a 64 x 64 (query i, key j) tile into LDS (each thread a 4 x 4
+// piece: queries 4 ti .. +3, keys 4 tj .. +3); invalid rows/keys give 0.
+__device__ inline void tile_p_ds(float (*Qs)[65], float (*Ks)[65], float (*Vs)[65], float (*Ds)[65], const float* lse_s,
+                                 const float* dv_s, int nq, int nk, float (*Pt)[65], float (*dSt)[65]) {
+  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
+  float s[4][4] = {}, dp[4][4] = {};
+  for (int d = 0; d < 64; ++d) {
+    float qa[4], ka[4], oa[4], va[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      qa[a] = Qs[4 * ti + a][d];
+      oa[a] = Ds[4 * ti + a][d];
+      ka[a] = Ks[4 * tj + a][d];
+      va[a] = Vs[4 * tj + a][d];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        s[a][b] = fmaf(qa[a], ka[b], s[a][b]);
+        dp[a][b] = fmaf(oa[a], va[b], dp[a][b]);
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = 4 * ti + a, j = 4 * tj + b;
+      const bool ok = i < nq && j < nk;
+      const float p = ok ? __builtin_amdgcn_exp2f(s[a][b] - lse_s[i]) : 0.0f;
+      Pt[i][j] = p;
+      dSt[i][j] = ok ? p * (dp[a][b] - dv_s[i]) : 0.0f;
+    }
+}
+
+// dK and dV of one 64-key block of one (request, head), looping over the
+// request's query blocks.
+__global__ __launch_bounds__(TB) void attn_bwd_dkdv_kernel(const AttnBwdArgs a) {
+  __shared__ float Qs[64][65], Ks[64][65], Vs[64][65], Ds[64][65], Pt[64][65], dSt[64][65];
+  __shared__ float lse_s[64], dv_s[64];
+  const int h = blockIdx.y;
+  const int w = a.work[blockIdx.x];
+  const ReqDesc& d = a.reqs[w >> 16];
+  const int N = d.J * d.P, base = d.tok_off;
+  const int k0 = (w & 0xFFFF) * 64;
+  const int nk = min(64, N - k0);
+  const float* qh = a.q + (size_t)h * a.ld * 64;
+  load_rows(Ks, a.k + (size_t)h * a.ld * 64, base + k0, base + N);
+  load_vt(Vs, a.vt + (size_t)h * 64 * a.ld, a.ld, base + k0, base + N);
+  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;  // dK/dV piece: keys 4 ti .., dims 4 tj ..
+  float gk[4][4] = {}, gv[4][4] = {};
+  for (int q0 = 0; q0 < N; q0 += 64) {
+    const int nq = min(64, N - q0);
+    __syncthreads();
+    load_rows(Qs, qh, base + q0, base + N);
+    load_dout(Ds, a.dout, a.heads, h, base + q0, base + N);
+    if (threadIdx.x < 64) {
+      lse_s[threadIdx.x] = threadIdx.x < nq ? a.lse[(size_t)h * a.ld + base + q0 + threadIdx.x] : 0.0f;
+      dv_s[threadIdx.x] = threadIdx.x < nq ? a.dv[(size_t)h * a.ld + base + q0 + threadIdx.x] : 0.0f;
+    }
+    __syncthreads();
+    tile_p_ds(Qs, Ks, Vs, Ds, lse_s, dv_s, nq, nk, Pt, dSt);
+    __syncthreads();
+    for (int i = 0; i < 64; ++i) {
+      float p[4], ds[4], dov[4], qv[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        p[b] = Pt[i][4 * ti + b];
+        ds[b] = dSt[i][4 * ti + b];
+        dov[b] = Ds[i][4 * tj + b];
+        qv[b] = Qs[i][4 * tj + b];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          gv[x][y] = fmaf(p[x], dov[y], gv[x][y]);
+          gk[x][y] = fmaf(ds[x], qv[y], gk[x][y]);
+        }
+    }
+  }
+  const int D = a.heads * 64;
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int j = 4 * ti + x;
+    if (j >= nk) continue;
+    float* row = a.dqkv + (size_t)(base + k0 + j) * 3 * D;
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      row[D + h * 64 + 4 * tj + y] = gk[x][y] * 0.69314718055994531f;  // 1 / log2(e)
+      row[2 * D + h * 64 + 4 * tj + y] = gv[x][y];
+    }
+  }
+}
+
+// dQ of one 64-query block of one (request, head), looping over key blocks.
+__global__ __launch_bounds__(TB) void attn_bwd_dq_kernel(const AttnBwdArgs a) {
+  __shared__ float Qs[64][65], Ks[64][65], Vs[64][65], Ds[64][65], Pt[64][65], dSt[64][65];
+  __shared__ float lse_s[64], dv_s[64];
+  const int h = blockIdx.y;
+  const int w = a.work[blockIdx.x];
+  const ReqDesc& d = a.reqs[w >> 16];
+  const int N = d.J * d.P, base = d.tok_off;
+  const int q0 = (w & 0xFFFF) * 64;
+  const int nq = min(64, N - q0);
+  load_rows(Qs, a.q + (size_t)h * a.ld * 64, base + q0, base + N);
+  load_dout(Ds, a.dout, a.heads, h, base + q0, base + N);
+  if (threadIdx.x < 64) {
+    lse_s[threadIdx.x] = threadIdx.x < nq ? a.lse[(size_t)h * a.ld + base + q0 + threadIdx.x] : 0.0f;
+    dv_s[threadIdx.x] = threadIdx.x < nq ? a.dv[(size_t)h * a.ld + base + q0 + threadIdx.x] : 0.0f;
+  }
+  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;  // dQ piece: queries 4 ti .., dims 4 tj ..
+  float gq[4][4] = {};
+  for (int k0 = 0; k0 < N; k0 += 64) {
+    const int nk = min(64, N - k0);
+    __syncthreads();
+    load_rows(Ks, a.k + (size_t)h * a.ld * 64, base + k0, base + N);
+    load_vt(Vs, a.vt + (size_t)h * 64 * a.ld, a.ld, base + k0, base + N);
+    __syncthreads();
+    tile_p_ds(Qs, Ks, Vs, Ds, lse_s, dv_s, nq, nk, Pt, dSt);
+    __syncthreads();
+    for (int j = 0; j < 64; ++j) {
+      float ds[4], kv[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        ds[b] = dSt[4 * ti + b][j];
+        kv[b] = Ks[j][4 * tj + b];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) gq[x][y] = fmaf(ds[x], kv[y], gq[x][y]);
+    }
+  }
+  const int D = a.heads * 64;
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int i = 4 * ti + x;
+    if (i >= nq) continue;
+    float* row = a.dqkv + (size_t)(base + q0 + i) * 3 * D;
+#pragma unroll
+    for (int y = 0; y < 4; ++y) row[h * 64 + 4 * tj + y] = gq[x][y] * 0.125f;
+  }
+}
+
+// ---- Adam ---------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(TB) void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
+                                                  float* __restrict__ m, float* __restrict__ v, long long n, float lr,
+                                                  float b1, float b2, float eps, float bc1, float bc2) {
+  for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+  }
+}
+
+int grid_for(long long n) {
+  const long long b = (n + TB - 1) / TB;
+  return (int)(b < 65536 ? (b > 0 ? b : 1) : 65536);
+}
+
+int last() { return hipGetLastError() == hipSuccess ? 0 : -5; }
+
+}  // namespace
+
+int launch_transpose(const float* in, float* out, int rows, int cols, int ld_in, int ld_out, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return 0;
+  transpose_kernel<<<dim3(cdiv(cols, 64), cdiv(rows, 64)), TB, 0, s>>>(in, out, rows, cols, ld_in, ld_out);
+  return last();
+}
+
+int launch_colsum(const float* x, int rows, int cols, int ld, float* part, int max_chunks, float* out, hipStream_t s) {
+  if (cols <= 0) return 0;
+  const int chunk = 256;
+  const int nchunk = rows > 0 ? cdiv(rows, chunk) : 1;
+  if (nchunk > max_chunks) return -22;
+  colsum_part_kernel<<<dim3(cdiv(cols, 64), nchunk), TB, 0, s>>>(x, rows, cols, ld, chunk, part);
+  if (int e = last()) return e;
+  colsum_final_kernel<<<cdiv(cols, TB), TB, 0, s>>>(part, nchunk, cols, out);
+  return last();
+}
+
+int launch_gelu_fwd(const float* h, float* g, long long n, hipStream_t s) {
+  gelu_fwd_kernel<<<grid_for(n), TB, 0, s>>>(h, g, n);
+  return last();
+}
+
+int launch_gelu_bwd(const float* dg, const float* h, float* dh, long long n, hipStream_t s) {
+  gelu_bwd_kernel<<<grid_for(n), TB, 0, s>>>(dg, h, dh, n);
+  return last();
+}
+
+int launch_ln_bwd(const float* x, const float* g, const float* dy, float* dres, float* xdy, int rows, int D,
+                  const int* rowmap, hipStream_t s) {
+  if (D > 512 || rows < 0) return -22;
+  if (rows == 0) return 0;
+  ln_bwd_kernel<<<cdiv(rows, TB / 64), TB, 0, s>>>(x, g, dy, dres, xdy, rows, D, rowmap);
+  return last();
+}
+
+int launch_pretrain_loss(const float* pred, const void* gt, int B, int H, int W, int C, float alpha, float* dpred,
+                         double* part, int nblocks, hipStream_t s) {
+  pretrain_loss_kernel<<<nblocks, TB, 0, s>>>(pred, gt, B, H, W, C, alpha, dpred, part);
+  return last();
+}
+
+int launch_head_grad(const ReqDesc* reqs, int nreq, int Mh, int Mh_pad, int C, const float* dpred,
+                     long long frame_elems, float* dhead, hipStream_t s) {
+  head_grad_kernel<<<grid_for((long long)Mh_pad * 256 * C), TB, 0, s>>>(reqs, nreq, Mh, Mh_pad, C, dpred, frame_elems,
+                                                                       dhead);
+  return last();
+}
+
+int launch_attention_bwd(const float* q, const float* k, const float* vt, const float* o, const float* dout,
+                         const float* lse, float* dv, float* dqkv, int M, int heads, int ld, const ReqDesc* reqs,
+                         const int* work, int nwork, hipStream_t s) {
+  attn_bwd_dot_kernel<<<cdiv(M * heads, TB / 64), TB, 0, s>>>(o, dout, M, heads, ld, dv);
+  if (int e = last()) return e;
+  AttnBwdArgs a;
+  a.q = q; a.k = k; a.vt = vt; a.dout = dout; a.lse = lse; a.dv = dv; a.dqkv = dqkv;
+  a.heads = heads; a.ld = ld; a.reqs = reqs; a.work = work; a.nwork = nwork;
+  attn_bwd_dkdv_kernel<<<dim3(nwork, heads), TB, 0, s>>>(a);
+  if (int e = last()) return e;
+  attn_bwd_dq_kernel<<<dim3(nwork, heads), TB, 0, s>>>(a);
+  return last();
+}
+
+int launch_adam(float* p, const float* g, float* m, float* v, long long n, float lr, float b1, float b2, float eps,
+                float bc1, float bc2, hipStream_t s) {
+  adam_kernel<<<grid_for(n), TB, 0, s>>>(p, g, m, v, n, lr, b1, b2, eps, bc1, bc2);
+  return last();
+}
+
+}  // namespace revo

@@ -56,3 +56,14 @@ def test_null_arguments_are_rejected_without_a_device():
     assert pkg.lib.revo_recover_poll(None, None, 0, 0) == -22
     assert pkg.lib.revo_op_linear(7, 0, None, None, None, None, 1, 64, 64, None) == -95
     assert pkg.lib.revo_op_attention(1, None, None, None, None, 1, 1, 65, None) == -22
+
+
+def test_trainer_null_arguments_are_rejected_without_a_device():
+    import ctypes as C
+    import paper_2604_27441_amd as pkg
+    assert pkg.lib.revo_train_create(None, None) == -22
+    assert pkg.lib.revo_train_step(None, None, None) == -22
+    assert pkg.lib.revo_train_get_weights(None, None, 0) == -22
+    cfg = pkg._lib.RevoTrainConfig(channels=2, k=5, tubelet=2, batch=1, height=16, width=16)
+    h = C.c_void_p()
+    assert pkg.lib.revo_train_create(C.byref(cfg), C.byref(h)) == -22 and not h.value
