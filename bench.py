@@ -538,6 +538,68 @@ def attention_traffic():
     return rec["bytes_per_launch"]
 
 
+def train_flop_per_sample(N, P, C, T=2, De=384, Dd=192, ne=12, nd=4):
+    """Algorithmic FLOPs of one pretraining sample: the forward pass over all
+    tokens (no pruning: every block's queries are needed for the gradient of
+    the next), and the backward pass: two products (dX and dW) per forward
+    product, and five N x N x 64 products per head in attention (the scores
+    again, dP, dV, dK, dQ) against the forward's two."""
+    L = T * 256 * C
+    lin = 2.0 * N * L * De + ne * 24.0 * N * De * De + 2.0 * N * De * Dd + nd * 24.0 * N * Dd * Dd + 2.0 * P * Dd * 256 * C
+    att = ne * 4.0 * N * N * De + nd * 4.0 * N * N * Dd
+    return 3.0 * lin + 3.5 * att
+
+
+def train_bench(log, steps=5, warmup=1, batch=8, height=192, width=256):
+    """Pretraining step (Sec. 3.4.2 / Sec. 4): FP32 forward, L_RGB, backward of
+    every layer and Adam on seeded 256x192 frames with 30 % of the pixels
+    masked, batch 8, one trainer per modality, 12 + 4 blocks."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2604_27441_amd import Trainer
+
+    out = {"workload": f"{width}x{height} pretraining, batch {batch}, 12+4 blocks, FP32, L_RGB = MSE + 0.01 TV, "
+                       "Adam lr 2e-4, per-pixel masks p = 0.3",
+           "data": "synthetic"}
+    blobs = synth.make_weights(0)
+    gy, gx = -(-height // 16), -(-width // 16)
+    P = gy * gx
+    N = 3 * P
+    total_flop, total_s = 0.0, 0.0
+    for C, name in ((3, "rgb"), (1, "depth")):
+        batches = []
+        for i in range(warmup + steps):
+            sm = synth.make_pretrain_batch(100 + i, batch, height, width, C)
+            refs = np.stack([x["refs"] for x in sm])
+            tgt = np.stack([x["target"] for x in sm])
+            if C == 1:
+                refs, tgt = refs.view(np.int16), tgt.view(np.int16)
+            batches.append((torch.from_numpy(np.ascontiguousarray(refs)).cuda(),
+                            torch.from_numpy(np.ascontiguousarray(tgt)).cuda(),
+                            torch.from_numpy(np.ascontiguousarray(np.stack([x["mask"] for x in sm]))).cuda(),
+                            np.stack([x["ref_idx"] for x in sm]), np.array([x["t_target"] for x in sm])))
+        with Trainer(blobs[0 if C == 3 else 1], C, batch, height, width) as tr:
+            losses = [tr.step(*batches[i]) for i in range(warmup)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(steps):
+                losses.append(tr.step(*batches[warmup + i]))
+            dt = time.perf_counter() - t0
+        flop = train_flop_per_sample(N, P, C) * batch
+        total_flop += flop * steps
+        total_s += dt
+        out[name] = {"ms_per_step": 1e3 * dt / steps, "samples_per_s": batch * steps / dt,
+                     "tflops": flop * steps / dt / 1e12, "losses": losses}
+        log(f"train {name}: {1e3 * dt / steps:.2f} ms per step of {batch}, {flop * steps / dt / 1e12:.1f} TFLOP/s, "
+            f"losses {['%.4f' % v for v in losses]}")
+    out["flop_per_sample"] = {"rgb": train_flop_per_sample(N, P, 3), "depth": train_flop_per_sample(N, P, 1)}
+    out["tflops"] = total_flop / total_s / 1e12
+    out["frac_of_fp32_peak"] = out["tflops"] / FP32_PEAK_TFLOPS
+    return out
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -659,6 +721,8 @@ def main():
                     help="only time revo_op_attention on one encoder layer's work (attention profiles)")
     ap.add_argument("--linear-shapes", action="store_true",
                     help="only time the encoder/decoder products through revo_op_linear (GEMM profiles)")
+    ap.add_argument("--no-train", action="store_true", help="skip the pretraining step")
+    ap.add_argument("--train-only", action="store_true", help="only time the pretraining step (profiles)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -683,6 +747,9 @@ def main():
 
     if args.attention_only:
         print(json.dumps({"attention": attention_only_bench(log), "dtype": "bf16", "data": "synthetic"}), flush=True)
+        return
+    if args.train_only:
+        print(json.dumps({"train": train_bench(log), "dtype": "fp32", "data": "synthetic"}), flush=True)
         return
     if args.linear_shapes:
         print(json.dumps({"linear_shapes": linear_shapes_bench(log), "dtype": "bf16", "data": "synthetic"}), flush=True)
@@ -783,6 +850,8 @@ def main():
         out["fp8"] = fp8_bench(blobs, reqs, args.fp8_steps, log)
     if not args.no_sweep_kt:
         out["k_t_sweep"] = sweep_kt(log)
+    if not args.no_train:
+        out["train"] = train_bench(log)
     if not args.no_small:
         out["fp32_small"] = small_configs_bench(blobs, log, oracle_runs=not args.no_cpu_baseline)
     if args.serve_seconds > 0:

@@ -125,3 +125,21 @@ def test_shapes_and_arguments_are_checked():
         Trainer(blob, 2, 1, 32, 32, **TINY)               # channels 3 or 1
     with pytest.raises(RevoError):
         Trainer(blob, 3, 1, 32, 32, k=8, **TINY)          # k + 1 frames beyond the limit
+
+
+def test_step_at_the_benchmark_frame_size():
+    """256 x 192 frames (576 tokens: nine 64-key blocks, five 128-query
+    tiles), 12 + 4 blocks, the depth model, batch 2 (bench.py times batch 8
+    of the same frames)."""
+    from paper_2604_27441_amd import Trainer
+    arch = oracle.Arch(channels=1)
+    blob = synth.make_weights(0)[1]
+    samples = synth.make_pretrain_batch(30, 2, 192, 256, 1)
+    ref = ot.train_step(blob, samples, arch)
+    with Trainer(blob, 1, 2, 192, 256) as tr:
+        loss = tr.step(*_dev(samples, 1))
+        grad, new = tr.grads(), tr.weights()
+    assert abs(loss - ref["loss"]) <= 1e-5 * abs(ref["loss"])
+    worst = _check_grads(grad, ref["grad"], arch, rtol=2e-5)
+    print(f"256x192 depth: worst per-tensor gradient error {worst:.3g} of the tensor's max")
+    _check_update(new, ref["params"], ref["grad"], ot.ADAM_LR)
