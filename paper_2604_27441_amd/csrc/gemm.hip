@@ -508,8 +508,8 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
   const int nreq = a.dyn_nreq ? *a.dyn_nreq : a.nreq;
   if (m0 >= Mlive) return;  // grid sized for a capacity
   const int KT = a.K / BK;
-  const T* __restrict__ W = (const T*)a.W;
-  const T* __restrict__ X = (const T*)a.X;
+  const T* __restrict__ W = (const T*)a.W + (size_t)blockIdx.y * a.bsw;
+  const T* __restrict__ X = (const T*)a.X + (size_t)blockIdx.y * a.bsx;
 
   // gather: token coordinates of this thread's rows
   int g_req[XC], g_j[XC], g_y[XC], g_x[XC];
@@ -647,10 +647,20 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
   // kernel has no registers to hold them through it
   EpiCols<BN> cols;
   epi_load_cols<Op, BN>(a, n0, wn, half, cols);
-  if constexpr (EPI == EPI_HEAD)
+  if constexpr (EPI == EPI_HEAD) {
     gemm_epilogue<Op, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, lane, wave, cols);
-  else
+  } else if constexpr (EPI == EPI_STORE && XM == X_DENSE) {
+    if (blockIdx.y) {
+      // product blockIdx.y of a batch
+      GemmArgs ab = a;
+      ab.out = (OutT*)a.out + (size_t)blockIdx.y * a.bso;
+      gemm_epilogue_staged<Op, BN, EPI, OutT>(ab, acc, m0, n0, Mlive, nreq, tid, smem, cols);
+    } else {
+      gemm_epilogue_staged<Op, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, tid, smem, cols);
+    }
+  } else {
     gemm_epilogue_staged<Op, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, tid, smem, cols);
+  }
 }
 
 
@@ -839,13 +849,14 @@ int launch_t(const GemmArgs& a, hipStream_t s) {
   } else {
     // the gather loader's per-row token coordinates leave no registers for a
     // 128-wide tile with two prefetched stages
+    const int nb = a.batch > 1 ? a.batch : 1;
     if constexpr (XM == X_DENSE) {
       if (a.N % 128 == 0) {
-        gemm_kernel<Op, 128, EPI, XM, OutT><<<dim3(gm * (a.N / 128)), NT, 0, s>>>(a);
+        gemm_kernel<Op, 128, EPI, XM, OutT><<<dim3(gm * (a.N / 128), nb), NT, 0, s>>>(a);
         return hipGetLastError() == hipSuccess ? 0 : -5;
       }
     }
-    gemm_kernel<Op, 64, EPI, XM, OutT><<<dim3(gm * (a.N / 64)), NT, 0, s>>>(a);
+    gemm_kernel<Op, 64, EPI, XM, OutT><<<dim3(gm * (a.N / 64), nb), NT, 0, s>>>(a);
     return hipGetLastError() == hipSuccess ? 0 : -5;
   }
 }
@@ -900,6 +911,8 @@ int launch_tubelet_pack(Prec prec, const GemmArgs& a, void* out, hipStream_t s) 
 
 int launch_gemm(Prec prec, int epi, int xmode, const GemmArgs& a, hipStream_t s) {
   if (a.M <= 0) return 0;
+  // batches: plain FP32 stores of dense products only (the weight gradients)
+  if (a.batch > 1 && (prec != P_FP32 || epi != EPI_STORE || xmode != X_DENSE || a.batch > 65535)) return -22;
   if (a.N % 64 != 0) return -22;
   // the epilogue reads bias and row scales as 16-byte vectors
   if (((uintptr_t)a.bias | (uintptr_t)a.wscale) & 15) return -22;

@@ -6,7 +6,13 @@ namespace revo {
 
 // out[c][r] = in[r][c] for r < rows, c < cols.
 int launch_transpose(const float* in, float* out, int rows, int cols, int ld_in, int ld_out, hipStream_t s);
-// out[c] = sum over rows of x[r][c] (fixed order: 256-row chunks, then the
+// Split-K layout: row r of in [rows][cols] to out[r / kc][c][r % kc], the
+// last chunk's rows past `rows` zero (kc a multiple of 64, nchunk kc >= rows).
+int launch_transpose_chunked(const float* in, float* out, int rows, int cols, int ld_in, int kc, int nchunk,
+                             hipStream_t s);
+// out[i] = sum_b part[b n + i] for b = 0 .. nb-1 in order.
+int launch_sum_chunks(const float* part, int nb, long long n, float* out, hipStream_t s);
+// out[c] = sum over rows of x[r][c] (fixed order: 64-row chunks, then the
 // chunks); part holds max_chunks x cols floats.
 int launch_colsum(const float* x, int rows, int cols, int ld, float* part, int max_chunks, float* out, hipStream_t s);
 int launch_gelu_fwd(const float* h, float* g, long long n, hipStream_t s);

@@ -40,6 +40,37 @@ __global__ __launch_bounds__(TB) void transpose_kernel(const float* __restrict__
   }
 }
 
+// Chunked transpose for split-K products: row r of in [rows][cols] goes to
+// out[r / kc][c][r % kc]; rows rows .. nchunk kc - 1 of the last chunk are
+// zeros.  kc is a multiple of 64.
+__global__ __launch_bounds__(TB) void transpose_chunked_kernel(const float* __restrict__ in, float* __restrict__ out,
+                                                               int rows, int cols, int ld_in, int kc) {
+  __shared__ float t[64][65];
+  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int i = ty; i < 64; i += 4) {
+    const int r = r0 + i, c = c0 + tx;
+    t[i][tx] = (r < rows && c < cols) ? in[(size_t)r * ld_in + c] : 0.0f;
+  }
+  __syncthreads();
+  const int ch = r0 / kc, rr0 = r0 - ch * kc;
+  float* o = out + (size_t)ch * cols * kc;
+  for (int i = ty; i < 64; i += 4) {
+    const int c = c0 + i;
+    if (c < cols) o[(size_t)c * kc + rr0 + tx] = t[tx][i];
+  }
+}
+
+// out[i] = sum over b of part[b n + i], b in order
+__global__ __launch_bounds__(TB) void sum_chunks_kernel(const float* __restrict__ part, int nb, long long n,
+                                                        float* __restrict__ out) {
+  for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB) {
+    float s = 0.0f;
+    for (int b = 0; b < nb; ++b) s += part[(size_t)b * n + i];
+    out[i] = s;
+  }
+}
+
 // Partial column sums of x [rows][cols] over chunks of `chunk` rows:
 // part[blockIdx.y][c].  64 columns x 4 row lanes per block.
 __global__ __launch_bounds__(TB) void colsum_part_kernel(const float* __restrict__ x, int rows, int cols, int ld,
@@ -460,9 +491,21 @@ int launch_transpose(const float* in, float* out, int rows, int cols, int ld_in,
   return last();
 }
 
+int launch_transpose_chunked(const float* in, float* out, int rows, int cols, int ld_in, int kc, int nchunk,
+                             hipStream_t s) {
+  if (rows <= 0 || cols <= 0 || kc % 64 || (long long)nchunk * kc < rows) return -22;
+  transpose_chunked_kernel<<<dim3(cdiv(cols, 64), nchunk * kc / 64), TB, 0, s>>>(in, out, rows, cols, ld_in, kc);
+  return last();
+}
+
+int launch_sum_chunks(const float* part, int nb, long long n, float* out, hipStream_t s) {
+  sum_chunks_kernel<<<grid_for(n), TB, 0, s>>>(part, nb, n, out);
+  return last();
+}
+
 int launch_colsum(const float* x, int rows, int cols, int ld, float* part, int max_chunks, float* out, hipStream_t s) {
   if (cols <= 0) return 0;
-  const int chunk = 256;
+  const int chunk = 64;
   const int nchunk = rows > 0 ? cdiv(rows, chunk) : 1;
   if (nchunk > max_chunks) return -22;
   colsum_part_kernel<<<dim3(cdiv(cols, 64), nchunk), TB, 0, s>>>(x, rows, cols, ld, chunk, part);
