@@ -385,7 +385,7 @@ int setup(revo_trainer* t, const revo_train_config& c) {
   t->Mh_pad = align_up(t->Mh, 64);
   t->ld = t->Mpad + 64;
   t->loss_blocks = 256;
-  t->max_chunks = cdiv(t->Mpad > t->Mh_pad ? t->Mpad : t->Mh_pad, 64);
+  t->max_chunks = cdiv(t->Mpad > t->Mh_pad ? t->Mpad : t->Mh_pad, 128);
   const size_t n = t->L.count;
   if ((e = alloc_n(t, &t->theta, n)) || (e = alloc_n(t, &t->grad, n)) || (e = alloc_n(t, &t->mom, n)) ||
       (e = alloc_n(t, &t->vel, n)) || (e = alloc_n(t, &t->wT, n)) || (e = alloc_n(t, &t->zero, 4096)))

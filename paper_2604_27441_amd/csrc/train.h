@@ -12,7 +12,7 @@ int launch_transpose_chunked(const float* in, float* out, int rows, int cols, in
                              hipStream_t s);
 // out[i] = sum_b part[b n + i] for b = 0 .. nb-1 in order.
 int launch_sum_chunks(const float* part, int nb, long long n, float* out, hipStream_t s);
-// out[c] = sum over rows of x[r][c] (fixed order: 64-row chunks, then the
+// out[c] = sum over rows of x[r][c] (fixed order: 128-row chunks, then the
 // chunks); part holds max_chunks x cols floats.
 int launch_colsum(const float* x, int rows, int cols, int ld, float* part, int max_chunks, float* out, hipStream_t s);
 int launch_gelu_fwd(const float* h, float* g, long long n, hipStream_t s);

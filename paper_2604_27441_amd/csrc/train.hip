@@ -87,13 +87,19 @@ __global__ __launch_bounds__(TB) void colsum_part_kernel(const float* __restrict
     part[(size_t)blockIdx.y * cols + c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
+// out[c] = sum of the chunk partials: 64 columns x 4 lanes per block, lane
+// l taking chunks l, l + 4, ..., then the four lanes in order
 __global__ __launch_bounds__(TB) void colsum_final_kernel(const float* __restrict__ part, int nchunk, int cols,
                                                           float* __restrict__ out) {
-  const int c = blockIdx.x * TB + threadIdx.x;
-  if (c >= cols) return;
+  __shared__ float red[4][64];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63), l = threadIdx.x >> 6;
   float s = 0.0f;
-  for (int i = 0; i < nchunk; ++i) s += part[(size_t)i * cols + c];
-  out[c] = s;
+  if (c < cols)
+    for (int i = l; i < nchunk; i += 4) s += part[(size_t)i * cols + c];
+  red[l][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (l == 0 && c < cols)
+    out[c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
 // ---- elementwise ----------------------------------------------------------------
@@ -505,12 +511,12 @@ int launch_sum_chunks(const float* part, int nb, long long n, float* out, hipStr
 
 int launch_colsum(const float* x, int rows, int cols, int ld, float* part, int max_chunks, float* out, hipStream_t s) {
   if (cols <= 0) return 0;
-  const int chunk = 64;
+  const int chunk = 128;
   const int nchunk = rows > 0 ? cdiv(rows, chunk) : 1;
   if (nchunk > max_chunks) return -22;
   colsum_part_kernel<<<dim3(cdiv(cols, 64), nchunk), TB, 0, s>>>(x, rows, cols, ld, chunk, part);
   if (int e = last()) return e;
-  colsum_final_kernel<<<cdiv(cols, TB), TB, 0, s>>>(part, nchunk, cols, out);
+  colsum_final_kernel<<<cdiv(cols, 64), TB, 0, s>>>(part, nchunk, cols, out);
   return last();
 }
 
