@@ -446,7 +446,7 @@ def fp8_bench(blobs, c3, steps, log):
     res = {}
     outs = {}
     for prec, name in ((2, "fp8"), (1, "bf16")):
-        rec = Recoverer(blobs[0], blobs[1], precision=prec, device=0, max_batch_tokens=8 * 10800 + 64,
+        rec = Recoverer(blobs[0], blobs[1], precision=prec, device=0, max_batch_tokens=8 * 10816,
                         max_batch=8, max_streams=32, profile="attention" if prec == 2 else False)
         for s, r in enumerate(c4):
             push_refs(rec, s, r)

@@ -57,6 +57,22 @@ int revo_op_layernorm(int precision, const float *x, const float *g, const float
 int revo_op_attention(int precision, const void *q, const void *k, const void *vt, void *o,
                       int heads, int ntok, int ld, void *stream);
 
+/* FP8 attention of the FP8 form: the same softmax(q k^T / 8) v with OCP
+ * E4M3 operands and per-head power-of-two scales, q8 = E4M3(q log2(e) / 8 /
+ * 2^eq[h]), k8 = E4M3(k / 2^ek[h]), vt8 = E4M3(v^T / 2^ev[h]) (exps: host,
+ * eq[heads] then ek[heads] then ev[heads], each in -100 .. 100), applied
+ * exactly by the scaled FP8 products; probabilities E4M3 (unit scale,
+ * exp2 of the scores minus a running max raised only past 8 in log2
+ * units, so they stay below 2^8); FP32 accumulation and row sums (App. B.1
+ * item 4 attention; the FP8 form's precision).  q8, k8 [heads][ld][64]
+ * bytes; vt8 [heads][64][ld] bytes with the keys of each aligned group of 64
+ * in the order key t -> column (t & ~63) | ((t >> 2) & 1) << 5 |
+ * ((t >> 5) & 1) << 4 | ((t >> 3) & 3) << 2 | (t & 3); rows / columns ntok ..
+ * ld-1 zero.  o [ntok][heads 64] bfloat16.  ld % 64 == 0, ld >= ntok + 64.
+ * Synchronous (descriptors are allocated and freed per call). */
+int revo_op_attention_fp8(const void *q8, const void *k8, const void *vt8, void *o, int heads, int ntok, int ld,
+                          const int *exps, void *stream);
+
 /* revo_op_attention for callers that cannot allocate device memory: code
  * under HIP graph capture, serving loops that must not call hipMalloc, and
  * harnesses that forbid it.  Same arguments, layouts and result as

@@ -16,7 +16,7 @@ from .model import (
     Arch, unpack_weights, normalise, zero_fill, sequence_frames, tubelet_vectors,
     sinusoid, positional_embedding, linear, layer_norm, gelu, attention_head,
     self_attention, transformer_block, forward, place_target_slot, recover, composite, Rounding,
-    bf16_round, e4m3_round, FP8Rounding, AbsMaxRecorder,
+    bf16_round, e4m3_round, FP8Rounding, AbsMaxRecorder, pow2_scale, QK_LOG2,
 )
 from .metrics import (
     normalise_frame, gaussian_window, gaussian_filter_valid, ssim_map, ssim, total_variation, edge_loss,
@@ -29,7 +29,7 @@ __all__ = [
     "Arch", "unpack_weights", "normalise", "zero_fill", "sequence_frames", "tubelet_vectors",
     "sinusoid", "positional_embedding", "linear", "layer_norm", "gelu", "attention_head",
     "self_attention", "transformer_block", "forward", "place_target_slot", "recover", "composite", "Rounding",
-    "bf16_round", "e4m3_round", "FP8Rounding", "AbsMaxRecorder",
+    "bf16_round", "e4m3_round", "FP8Rounding", "AbsMaxRecorder", "pow2_scale", "QK_LOG2",
     "normalise_frame", "gaussian_window", "gaussian_filter_valid", "ssim_map", "ssim", "total_variation",
     "edge_loss", "frame_metrics", "METRIC_KEYS", "unproject", "project", "render_view",
 ]

@@ -153,23 +153,55 @@ class Rounding:
         return w if self.fn is None else self.fn(w)
 
 
+def pow2_scale(s):
+    """Smallest power of two >= s (1 for s <= 0): the attention operands'
+    scales, so that a scaled product is exact in the exponent."""
+    return 2.0 ** math.ceil(math.log2(s)) if s > 0 else 1.0
+
+
+QK_LOG2 = math.log2(math.e) / 8.0   # the kernels hold Q multiplied by log2(e) / sqrt(64)
+
+
 class FP8Rounding(Rounding):
     """The FP8 form: the four block products and the encoder-to-decoder
     projection take E4M3 operands, activations with a per-tensor scale
     (absmax over a calibration set / 448) and weights with a per-output-row
-    scale (row absmax / 448); the embedding, head and attention stay BF16."""
+    scale (row absmax / 448).  With fp8_attention, attention's Q, K and V
+    are E4M3 with per-head power-of-two scales (the smallest power of two
+    >= absmax / 448; Q as the kernels hold it, times log2(e) / 8) and the
+    probabilities exp(s - row max) E4M3 with unit scale.  Embedding and
+    head stay BF16 (and attention, without fp8_attention)."""
 
     FP8_KINDS = ("qkv", "proj", "fc1", "fc2", "e2d")
 
-    def __init__(self, act_scales):
+    def __init__(self, act_scales, fp8_attention=True):
         super().__init__(bf16_round)
         self.scales = dict(act_scales)
+        self.fp8_attention = fp8_attention
 
     @classmethod
     def is_fp8(cls, site):
         return site.rsplit(".", 1)[-1] in cls.FP8_KINDS
 
+    @staticmethod
+    def attn_operand(site):
+        """'q', 'k', 'v' or 'p' for an attention site ('<blk>.attn.q<h>', ...)."""
+        parts = site.rsplit(".", 2)
+        if len(parts) >= 2 and parts[-2] == "attn":
+            return parts[-1][0]
+        return None
+
     def act(self, x, site):
+        kind = self.attn_operand(site) if self.fp8_attention else None
+        if kind == "p":
+            return e4m3_round(x)
+        if kind in ("q", "k", "v"):
+            x = np.asarray(x)
+            if kind == "q":
+                s = pow2_scale(self.scales[site] * QK_LOG2)
+                return e4m3_round(x * QK_LOG2 / s) * s / QK_LOG2
+            s = pow2_scale(self.scales[site])
+            return e4m3_round(x / s) * s
         if not self.is_fp8(site):
             return bf16_round(x)
         s = self.scales[site]
@@ -307,9 +339,11 @@ def gelu(z):
     return 0.5 * z * (1.0 + erf(z / math.sqrt(2.0)))
 
 
-def attention_head(q, k, v, rnd=EXACT, chunk=2048):
+def attention_head(q, k, v, rnd=EXACT, chunk=2048, site="attn.p"):
     """softmax(q k^T / sqrt(d)) v over all keys, rows processed in chunks
-    (rows are independent, so chunking changes nothing)."""
+    (rows are independent, so chunking changes nothing).  The probabilities
+    exp(s - row max) are the product operand (call site `site`); the row sum
+    divides afterwards."""
     d = q.shape[1]
     out = np.empty((q.shape[0], v.shape[1]))
     for r0 in range(0, q.shape[0], chunk):
@@ -317,21 +351,26 @@ def attention_head(q, k, v, rnd=EXACT, chunk=2048):
         s -= s.max(axis=1, keepdims=True)
         e = np.exp(s)
         denom = e.sum(axis=1, keepdims=True)
-        out[r0:r0 + chunk] = (rnd.act(e, "attn") @ v) / denom
+        out[r0:r0 + chunk] = (rnd.act(e, site) @ v) / denom
     return out
 
 
 def self_attention(a, p, pre, heads, rnd=EXACT):
     """Multi-head self-attention: qkv projection (columns Q | K | V, each
-    head-major with contiguous heads), per-head attention, output projection."""
+    head-major with contiguous heads), per-head attention, output projection.
+    Each head's Q, K and V are product operands (call sites
+    '<blk>.attn.q<h>', '.k<h>', '.v<h>'), and so are its probabilities
+    ('<blk>.attn.p')."""
     N, D = a.shape
     dh = D // heads
     qkv = linear(a, p[pre + "qkv.w"], p[pre + "qkv.b"], rnd, pre + "qkv")
-    q, k, v = rnd.act(qkv[:, :D], "attn"), rnd.act(qkv[:, D:2 * D], "attn"), rnd.act(qkv[:, 2 * D:], "attn")
     o = np.empty((N, D))
     for h in range(heads):
         sl = slice(h * dh, (h + 1) * dh)
-        o[:, sl] = attention_head(q[:, sl], k[:, sl], v[:, sl], rnd)
+        q = rnd.act(qkv[:, sl], f"{pre}attn.q{h}")
+        k = rnd.act(qkv[:, D + h * dh:D + (h + 1) * dh], f"{pre}attn.k{h}")
+        v = rnd.act(qkv[:, 2 * D + h * dh:2 * D + (h + 1) * dh], f"{pre}attn.v{h}")
+        o[:, sl] = attention_head(q, k, v, rnd, site=f"{pre}attn.p")
     return linear(o, p[pre + "proj.w"], p[pre + "proj.b"], rnd, pre + "proj")
 
 

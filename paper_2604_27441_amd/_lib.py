@@ -93,6 +93,8 @@ _sigs = {
                                     C.c_void_p]),
     "revo_op_attention": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
                                     C.c_int, C.c_void_p]),
+    "revo_op_attention_fp8": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int,
+                                        C.c_void_p, C.c_void_p]),
     "revo_op_attention_noalloc": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
                                             C.c_int, C.c_int, C.c_void_p]),
     "revo_train_create": (C.c_int, [C.POINTER(RevoTrainConfig), C.POINTER(C.c_void_p)]),

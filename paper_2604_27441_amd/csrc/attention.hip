@@ -45,6 +45,18 @@ constexpr int KB = 64;    // keys per block
 constexpr float NEG_BIG = -1.0e30f;
 constexpr float LAZY = 8.0f;
 
+// One 16-byte-per-lane buffer load into LDS (lane L's bytes at lds + 16 L).
+__device__ __forceinline__ void dma16_att(__amdgpu_buffer_rsrc_t rs, const void* lds, int vo, int so) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)lds, 16, vo, so, 0, 0);
+}
+
+// s_waitcnt vmcnt(N_): at most N_ of this wave's vector memory loads in flight.
+template <int N_>
+__device__ __forceinline__ void wait_vm_att() {
+  static_assert(N_ >= 0 && N_ < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N_ & 15) | ((N_ >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
 // max / sum of a value and its partner lane (l ^ 32)
 __device__ __forceinline__ float xhalf_max(float x) {
   auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
@@ -489,12 +501,255 @@ __global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 3 : 2) void attn_
   }
 }
 
+// ---- FP8 form ----------------------------------------------------------------
+//
+// Q, K and V^T are OCP E4M3 with per-head power-of-two scales 2^eq, 2^ek,
+// 2^ev, applied exactly by the scaled 32x32x64 FP8 MFMA (E8M0 block scales),
+// so the score products come out in the BF16 kernel's units (log2 scale,
+// onto the -max register block).  The probabilities are E4M3 with unit
+// scale; the max is raised lazily as in the safe pass above, which keeps
+// them at most 2^8 (E4M3 holds up to 448).  The row sum adds the float
+// probabilities.  A head dimension of 64 is one product step: per 64-key
+// block a wave issues 2 score and 2 P V products.  K rows and V^T rows are
+// 64 bytes in LDS, 16-byte chunk c of row r at slot c ^ ((r >> 2) & 3), so
+// the 16 rows one read phase touches cover all banks.  V^T columns are in
+// fp8_vt_col order within each group of 64 keys (requests start on
+// 64-token boundaries), so a lane's probabilities are its 32 consecutive k.
+
+__device__ __forceinline__ int swz8(int row, int chunk) { return row * 64 + ((chunk ^ ((row >> 2) & 3)) << 4); }
+
+__device__ __forceinline__ f32x16 mfma_fp8(const i32x8& a, const i32x8& b, const f32x16& c, int sa, int sb) {
+  return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, sa, 0, sb);
+}
+
+__device__ __forceinline__ i32x8 load_frag8(const uint8_t* __restrict__ t, int row, int half) {
+  const uint4 lo = *reinterpret_cast<const uint4*>(t + swz8(row, 2 * half));
+  const uint4 hi = *reinterpret_cast<const uint4*>(t + swz8(row, 2 * half + 1));
+  return i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+}
+
+template <bool MASK, bool FIRST>
+__device__ __forceinline__ void fp8_block(const uint8_t* __restrict__ kt, const uint8_t* __restrict__ vt,
+                                          const i32x8& qf, f32x16 (&oacc)[2], f32x16& negm, float& m_run,
+                                          float& l_run, int lane, int kvalid, int eqk_q, int eqk_k, int ev) {
+  const int half = lane >> 5, l32 = lane & 31;
+  i32x8 kf[2];
+#pragma unroll
+  for (int st = 0; st < 2; ++st) kf[st] = load_frag8(kt, st * 32 + l32, half);
+  __builtin_amdgcn_sched_barrier(0);
+  f32x16 sacc[2];
+#pragma unroll
+  for (int st = 0; st < 2; ++st) sacc[st] = mfma_fp8(kf[st], qf, FIRST ? f32x16{} : negm, eqk_k, eqk_q);
+  if constexpr (MASK) {
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (st * 32 + acc_row(i, lane) >= kvalid) sacc[st][i] = NEG_BIG;
+  }
+  float m0 = fmaxf(fmaxf(sacc[0][0], sacc[0][1]), sacc[0][2]);
+  float m1 = fmaxf(fmaxf(sacc[1][0], sacc[1][1]), sacc[1][2]);
+#pragma unroll
+  for (int i = 3; i < 15; i += 2) {
+    m0 = fmaxf(fmaxf(m0, sacc[0][i]), sacc[0][i + 1]);
+    m1 = fmaxf(fmaxf(m1, sacc[1][i]), sacc[1][i + 1]);
+  }
+  const float mloc = xhalf_max(fmaxf(fmaxf(m0, sacc[0][15]), fmaxf(m1, sacc[1][15])));
+  if constexpr (FIRST) {
+    m_run = mloc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) negm[i] = -mloc;
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) sacc[st][i] -= mloc;
+  } else {
+    // mloc is relative to m_run: raise the max only past LAZY
+    const bool grow = mloc > LAZY;
+    if (__any(grow)) {
+      const float d = grow ? mloc : 0.0f;
+      const float alpha = __builtin_amdgcn_exp2f(-d);
+      m_run += d;
+      l_run *= alpha;
+      oacc[0] *= alpha;
+      oacc[1] *= alpha;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) negm[i] = -m_run;
+#pragma unroll
+      for (int st = 0; st < 2; ++st)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) sacc[st][i] -= d;
+      asm volatile("" : "+v"(oacc[0]), "+v"(oacc[1]), "+v"(sacc[0]), "+v"(sacc[1]), "+v"(negm));
+    }
+  }
+  // probabilities: byte j = 16 st + i of the lane's 32 (fp8_vt_col order)
+  i32x8 pf;
+  float ls0 = l_run, ls1 = 0.0f;
+#pragma unroll
+  for (int st = 0; st < 2; ++st)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      float p[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) p[e] = __builtin_amdgcn_exp2f(sacc[st][4 * g + e]);
+      ls0 += p[0] + p[2];
+      ls1 += p[1] + p[3];
+      pf[st * 4 + g] = (int)e4m3x4(p[0], p[1], p[2], p[3]);
+    }
+  l_run = ls0 + ls1;
+#pragma unroll
+  for (int ds = 0; ds < 2; ++ds) oacc[ds] = mfma_fp8(load_frag8(vt, ds * 32 + l32, half), pf, oacc[ds], ev, 127);
+}
+
+__global__ __launch_bounds__(NT, 3) void attn_fp8_kernel(const AttnArgs a) {
+  constexpr int TB = KB * 64;  // bytes per K or V^T tile
+  __shared__ __attribute__((aligned(16))) uint8_t kv[4 * TB];
+  uint8_t* ks = kv;
+  uint8_t* vs = kv + 2 * TB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int half = lane >> 5;
+  const int nwork = a.dyn_nwork ? *a.dyn_nwork : a.nwork;
+  const int G = nwork * a.heads;
+  const int L = blockIdx.x;
+  if (L >= G) return;
+  const int xcd = L & 7, per = G >> 3, rem = G & 7;
+  const int Lr = xcd * per + (xcd < rem ? xcd : rem) + (L >> 3);
+  const int hd = Lr / nwork;
+  const int w = a.work[Lr - hd * nwork];
+  const int r = w >> 16, qt = w & (ATTN_TARGET_TILE - 1);
+  const ReqDesc& d = a.reqs[r];
+  const int N = d.J * d.P;
+  const int base = d.tok_off;
+  const int q0 = (w & ATTN_TARGET_TILE) ? (d.J - 1) * d.P : 0;
+  const int q_local = q0 + qt * QT + wave * 32 + (lane & 31);
+  const int q = base + q_local;
+  // E8M0 scale operands (127 + e)
+  const int sq = a.qkv_exp[hd], sk = a.qkv_exp[a.heads + hd], sv = a.qkv_exp[2 * a.heads + hd];
+
+  const uint8_t* Kg = (const uint8_t*)a.k + ((size_t)hd * a.ldqk + base) * 64;
+  const uint8_t* Vg = (const uint8_t*)a.vt + (size_t)hd * 64 * a.ldv + base;
+  i32x8 qf;
+  {
+    const uint4* qp = reinterpret_cast<const uint4*>((const uint8_t*)a.q + ((size_t)hd * a.ldqk + (q_local < N ? q : base)) * 64 + half * 32);
+    const uint4 lo = qp[0], hi = qp[1];
+    qf = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+  }
+  const __amdgpu_buffer_rsrc_t krs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)Kg, (short)0, (a.ldqk - base) * 64, 0x00020000);
+  const __amdgpu_buffer_rsrc_t vrs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)Vg, (short)0, 64 * a.ldv - base, 0x00020000);
+  // wave w fills rows 16w .. 16w+15 of the K and V^T tiles (1 KB, 16 bytes
+  // per lane); lane L takes row 16w + L / 4 and the chunk whose swizzled
+  // slot is L % 4
+  const int rr = wave * 16 + (lane >> 2);
+  const int cc = (lane & 3) ^ ((rr >> 2) & 3);
+  const int kvo = rr * 64 + cc * 16;
+  const int vvo = rr * a.ldv + cc * 16;
+  auto fetch = [&](int kb, int buf) {
+    dma16_att(krs, ks + buf * TB + wave * 16 * 64, kvo, kb * 64);
+    dma16_att(vrs, vs + buf * TB + wave * 16 * 64, vvo, kb);
+  };
+  f32x16 oacc[2], negm;
+  oacc[0] = f32x16{};
+  oacc[1] = f32x16{};
+  negm = f32x16{};
+  float m_run = 0.0f, l_run = 0.0f;
+  const int nkb = (N + KB - 1) / KB;
+  const int nfull = N / KB;
+  fetch(0, 0);
+  wait_vm_att<0>();
+  __syncthreads();
+  if (nfull == 0) {
+    fp8_block<true, true>(ks, vs, qf, oacc, negm, m_run, l_run, lane, N, sq, sk, sv);
+  } else {
+    fetch(nkb > 1 ? KB : 0, 1);
+    fp8_block<false, true>(ks, vs, qf, oacc, negm, m_run, l_run, lane, KB, sq, sk, sv);
+    wait_vm_att<0>();
+    __syncthreads();
+    int b = 1;
+    for (; b + 1 < nfull; b += 2) {
+      fetch((b + 1) * KB, 0);
+      fp8_block<false, false>(ks + TB, vs + TB, qf, oacc, negm, m_run, l_run, lane, KB, sq, sk, sv);
+      wait_vm_att<0>();
+      __syncthreads();
+      fetch(b + 2 < nkb ? (b + 2) * KB : (b + 1) * KB, 1);
+      fp8_block<false, false>(ks, vs, qf, oacc, negm, m_run, l_run, lane, KB, sq, sk, sv);
+      wait_vm_att<0>();
+      __syncthreads();
+    }
+    if (b < nfull) {
+      fetch(b + 1 < nkb ? (b + 1) * KB : b * KB, 0);
+      fp8_block<false, false>(ks + TB, vs + TB, qf, oacc, negm, m_run, l_run, lane, KB, sq, sk, sv);
+      wait_vm_att<0>();
+      __syncthreads();
+    }
+    if (nfull < nkb)  // ragged last block, already in LDS
+      fp8_block<true, false>(ks + (nfull & 1) * TB, vs + (nfull & 1) * TB, qf, oacc, negm, m_run, l_run, lane,
+                             N - nfull * KB, sq, sk, sv);
+  }
+  // output through LDS in whole 64-dim rows (the tiles are free once every
+  // wave is past its last block)
+  const float l_tot = xhalf_sum(l_run);
+  const int ql = wave * 32 + (lane & 31);
+  uint8_t* st = kv;
+  __syncthreads();
+  if (a.o_scale) {
+    constexpr int RB = 64 + 16;
+    static_assert(QT * RB <= 4 * TB, "output tile fits the stages");
+    const float inv = 1.0f / (l_tot * *a.o_scale);
+#pragma unroll
+    for (int ds = 0; ds < 2; ++ds)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int dim = ds * 32 + g * 8 + half * 4;
+        *reinterpret_cast<uint32_t*>(st + ql * RB + dim) = e4m3x4(oacc[ds][4 * g] * inv, oacc[ds][4 * g + 1] * inv,
+                                                                  oacc[ds][4 * g + 2] * inv, oacc[ds][4 * g + 3] * inv);
+      }
+    __syncthreads();
+    for (int i = tid; i < QT * 4; i += NT) {
+      const int row = i >> 2, c = (i & 3) * 16;
+      const int qr = q0 + qt * QT + row;
+      if (qr < N)
+        *reinterpret_cast<uint4*>((uint8_t*)a.o + (size_t)(base + qr) * (a.heads * 64) + hd * 64 + c) =
+            *reinterpret_cast<const uint4*>(st + row * RB + c);
+    }
+  } else {
+    // BF16 output: two passes of 64 queries through the 16 KB of stages
+    constexpr int RB = 64 * 2 + 16;
+    const float inv = 1.0f / l_tot;
+    for (int pass = 0; pass < 2; ++pass) {
+      if ((wave >> 1) == pass) {
+        const int qp = ql - pass * 64;
+#pragma unroll
+        for (int ds = 0; ds < 2; ++ds)
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            const int dim = ds * 32 + g * 8 + half * 4;
+            *reinterpret_cast<bf16x4*>(reinterpret_cast<__bf16*>(st + qp * RB) + dim) =
+                bf16x4{(__bf16)(oacc[ds][4 * g] * inv), (__bf16)(oacc[ds][4 * g + 1] * inv),
+                       (__bf16)(oacc[ds][4 * g + 2] * inv), (__bf16)(oacc[ds][4 * g + 3] * inv)};
+          }
+      }
+      __syncthreads();
+      for (int i = tid; i < 64 * 8; i += NT) {
+        const int row = i >> 3, c = (i & 7) * 8;
+        const int qr = q0 + qt * QT + pass * 64 + row;
+        if (qr < N)
+          *reinterpret_cast<uint4*>((__bf16*)a.o + (size_t)(base + qr) * (a.heads * 64) + hd * 64 + c) =
+              *reinterpret_cast<const uint4*>(st + row * RB + c * 2);
+      }
+      __syncthreads();
+    }
+  }
+}
+
 }  // namespace
 
 int launch_attention(Prec prec, const AttnArgs& a, hipStream_t s) {
   if (a.nwork <= 0) return 0;
   dim3 grid(a.nwork * a.heads);
-  if (prec == P_BF16 || prec == P_FP8) attn_kernel<OpBF16><<<grid, NT, 0, s>>>(a);  // FP8 form: BF16 attention
+  if (prec == P_FP8 && a.qkv_exp) attn_fp8_kernel<<<grid, NT, 0, s>>>(a);
+  else if (prec == P_BF16 || prec == P_FP8) attn_kernel<OpBF16><<<grid, NT, 0, s>>>(a);  // uncalibrated FP8 form: BF16
   else if (prec == P_FP32 && !a.o_scale) attn_kernel<OpF32><<<grid, NT, 0, s>>>(a);
   else return -95;
   return hipGetLastError() == hipSuccess ? 0 : -5;

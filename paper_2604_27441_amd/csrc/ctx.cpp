@@ -505,7 +505,8 @@ void worker_main(revo_ctx* c) {
           e.tokens[q] = 0;
           if (m.present && !m.clean) {
             const int N = request_tokens(m.H, m.W, c->J);
-            e.tokens[q] = (N + 15) & ~15;  // rows start 16-aligned
+            const int al = c->cfg.precision == REVO_FP8 ? 64 : 16;  // rows start on a V^T key group
+            e.tokens[q] = (N + al - 1) / al * al;
             e.units += work_units(N);
           }
         }
@@ -739,7 +740,10 @@ int revo_recover_submit(revo_ctx* c, const revo_request* r, unsigned long long* 
   if (r->width < 16 || r->height < 16 || r->width > 4096 || r->height > 4096) return REVO_EINVAL;
   if (!r->rgb && !r->depth) return REVO_EINVAL;
   if ((r->mask_rgb && !r->rgb) || (r->mask_depth && !r->depth)) return REVO_EINVAL;
-  if (((request_tokens(r->height, r->width, c->J) + 15) & ~15) > c->cfg.max_batch_tokens) return REVO_EINVAL;
+  {
+    const int al = c->cfg.precision == REVO_FP8 ? 64 : 16;
+    if ((request_tokens(r->height, r->width, c->J) + al - 1) / al * al > c->cfg.max_batch_tokens) return REVO_EINVAL;
+  }
   {
     std::lock_guard<std::mutex> lk(c->mu);
     if (c->stop) return REVO_ESHUTDOWN;

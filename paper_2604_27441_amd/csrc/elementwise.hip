@@ -292,6 +292,50 @@ __global__ __launch_bounds__(256) void absmax_kernel(const __bf16* __restrict__ 
   if (lane == 0) atomicMax(slot, __float_as_uint(m));  // non-negative floats order as their bits
 }
 
+// one wave per token row of one head (grid.y): max |.| over the row's 64
+// values of Q and K and the token's V^T column
+__global__ __launch_bounds__(256) void attn_absmax_kernel(const __bf16* __restrict__ q, const __bf16* __restrict__ k,
+                                                          const __bf16* __restrict__ vt, int heads, int ld, int rows,
+                                                          const ReqDesc* __restrict__ reqs, int nreq,
+                                                          unsigned* __restrict__ slots) {
+  const int lane = threadIdx.x & 63, h = blockIdx.y;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= rows) return;
+  const ReqDesc& d = reqs[find_req_tok(reqs, nreq, t)];
+  if (t - d.tok_off >= d.J * d.P) return;  // alignment gap
+  const size_t row = ((size_t)h * ld + t) * 64 + lane;
+  const int col = (t & ~12) | ((t & 4) << 1) | ((t & 8) >> 1);  // bits 2 and 3 swapped
+  float mq = fabsf((float)q[row]), mk = fabsf((float)k[row]);
+  float mv = fabsf((float)vt[((size_t)h * 64 + lane) * ld + col]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    mq = fmaxf(mq, __shfl_xor(mq, o));
+    mk = fmaxf(mk, __shfl_xor(mk, o));
+    mv = fmaxf(mv, __shfl_xor(mv, o));
+  }
+  if (lane == 0) {
+    atomicMax(slots + h, __float_as_uint(mq));
+    atomicMax(slots + heads + h, __float_as_uint(mk));
+    atomicMax(slots + 2 * heads + h, __float_as_uint(mv));
+  }
+}
+
+__global__ void attn_scales_kernel(const unsigned* __restrict__ absmax, int* __restrict__ exps,
+                                   float* __restrict__ inv, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float x = __uint_as_float(absmax[i]) / 448.0f;
+  int e = 0;
+  if (x > 0.0f) {
+    // ceil(log2 x) from the bits: the exponent, plus one unless x is a power of two
+    const unsigned b = __float_as_uint(x);
+    const int E = (int)((b >> 23) & 0xFF);
+    e = E == 0 ? -126 : E - 127 + ((b & 0x7FFFFF) ? 1 : 0);
+  }
+  exps[i] = 127 + e;
+  inv[i] = ldexpf(1.0f, -e);
+}
+
 __global__ void scales_kernel(const unsigned* __restrict__ absmax, float* __restrict__ scale, int n) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < n) {
@@ -398,6 +442,19 @@ int launch_quantize_rows(const float* w, int rows, int cols, uint8_t* w8, float*
 int launch_absmax(const __bf16* x, int rows, int D, const ReqDesc* reqs, int nreq, unsigned* slot, hipStream_t s) {
   if (rows <= 0) return 0;
   absmax_kernel<<<cdiv(rows, 4), 256, 0, s>>>(x, rows, D, reqs, nreq, slot);
+  return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+int launch_attn_absmax(const __bf16* q, const __bf16* k, const __bf16* vt, int heads, int ld, int rows,
+                       const ReqDesc* reqs, int nreq, unsigned* slots, hipStream_t s) {
+  if (rows <= 0) return 0;
+  attn_absmax_kernel<<<dim3(cdiv(rows, 4), heads), 256, 0, s>>>(q, k, vt, heads, ld, rows, reqs, nreq, slots);
+  return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+int launch_attn_scales(const unsigned* absmax, int* exps, float* inv, int n, hipStream_t s) {
+  if (n <= 0) return 0;
+  attn_scales_kernel<<<cdiv(n, 256), 256, 0, s>>>(absmax, exps, inv, n);
   return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 

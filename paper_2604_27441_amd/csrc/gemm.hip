@@ -393,15 +393,19 @@ __device__ __forceinline__ void gemm_epilogue_staged(const GemmArgs& a, f32x16 (
 #pragma unroll
           for (int e = 0; e < 4; ++e) v[e] *= a.qscale;
         }
+        // E4M3 Q / K / V^T of the FP8 attention: each head's own scale
+        const float hinv = (EPI == EPI_QKV && sizeof(OutT) == 1) ? a.head_inv[part * a.heads + ((n % D) >> 6)] : oinv;
         if (vtile) {
           // 2-byte V^T (BF16 attention): within each group of 16 tokens the
           // column index has bits 2 and 3 swapped, the order in which a
-          // lane's eight probabilities meet the P V product
-          const int mc = sizeof(OutT) == 2 ? (ml & ~12) | ((ml & 4) << 1) | ((ml & 8) >> 1) : ml;
+          // lane's eight probabilities meet the P V product; 1-byte V^T (FP8
+          // attention): fp8_vt_col order within groups of 64
+          const int mc = sizeof(OutT) == 2 ? (ml & ~12) | ((ml & 4) << 1) | ((ml & 8) >> 1)
+                                           : (sizeof(OutT) == 1 ? fp8_vt_col(ml) : ml);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) reinterpret_cast<OutT*>(smem + (nl + e) * TPV)[mc] = out_cast<OutT>(v[e], 1.0f);
+          for (int e = 0; e < 4; ++e) reinterpret_cast<OutT*>(smem + (nl + e) * TPV)[mc] = out_cast<OutT>(v[e], hinv);
         } else {
-          Vec4<OutT>::store(reinterpret_cast<OutT*>(smem + ml * TPB) + nl, v, oinv);
+          Vec4<OutT>::store(reinterpret_cast<OutT*>(smem + ml * TPB) + nl, v, hinv);
         }
       }
     }
@@ -409,9 +413,10 @@ __device__ __forceinline__ void gemm_epilogue_staged(const GemmArgs& a, f32x16 (
   __syncthreads();
   if (vtile) {
     // V^T rows: EO consecutive columns per 16-byte chunk; a 2-byte chunk
-    // can hold permuted tokens up to the end of its group of 16, so it is
-    // written whole while its group starts below Mlive
-    const int Mcol = sizeof(OutT) == 2 ? (Mlive + 15) & ~15 : Mlive;
+    // can hold permuted tokens up to the end of its group of 16 (a 1-byte
+    // one up to the end of its group of 64), so it is written whole while
+    // its group starts below Mlive
+    const int Mcol = sizeof(OutT) == 2 ? (Mlive + 15) & ~15 : (sizeof(OutT) == 1 ? (Mlive + 63) & ~63 : Mlive);
     for (int i = tid; i < BN * (BM_ / EO); i += NT_) {
       const int nl = i / (BM_ / EO), c = (i - nl * (BM_ / EO)) * EO;
       const int m = m0 + c;
@@ -886,7 +891,10 @@ int launch_fp8(int epi, const GemmArgs& a, hipStream_t s) {
     case EPI_STORE: return launch_t<OpFP8, EPI_STORE, X_DENSE, __bf16>(a, s);
     case EPI_RESIDUAL: return launch_t<OpFP8, EPI_RESIDUAL, X_DENSE, float>(a, s);
     case EPI_GELU: return launch_t<OpFP8, EPI_GELU, X_DENSE, uint8_t>(a, s);
-    case EPI_QKV: return launch_t<OpFP8, EPI_QKV, X_DENSE, __bf16>(a, s);
+    case EPI_QKV:
+      // E4M3 Q / K / V^T for the FP8 attention, BF16 for the BF16 one
+      if (a.head_inv) return launch_t<OpFP8, EPI_QKV, X_DENSE, uint8_t>(a, s);
+      return launch_t<OpFP8, EPI_QKV, X_DENSE, __bf16>(a, s);
     case EPI_PE: return launch_t<OpFP8, EPI_PE, X_DENSE, float>(a, s);
   }
   return -22;

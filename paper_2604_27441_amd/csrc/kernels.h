@@ -59,6 +59,9 @@ struct GemmArgs {
   // FP8 operands: acc * wscale[n] * (*xscale) + bias[n]; an FP8 result is
   // stored as value / (*out_scale)
   const float* wscale; const float* xscale; const float* out_scale;
+  // EPI_QKV with E4M3 outputs (FP8 attention): per-head inverse scales
+  // 2^-e, [3][heads] (Q, K, V); V^T columns in fp8_vt_col order
+  const float* head_inv;
   // gather / PE / head
   const ReqDesc* reqs; int nreq; int channels;
   // batched FP32 products (EPI_STORE, dense): grid.y = batch, product b takes
@@ -83,7 +86,17 @@ struct AttnArgs {
   const int* dyn_nreq;   // nullable
   const float* o_scale;  // nullable: store o / (*o_scale) as FP8 E4M3
   float* lse;            // nullable (FP32): [heads][ldqk] base-2 log of each query's normaliser
+  // FP8 attention: E8M0 exponents (127 + e, scale 2^e) of Q, K, V, [3][heads]
+  const int* qkv_exp;
 };
+
+// Column position, within its aligned group of 64 keys, at which the FP8
+// attention kernel's V^T holds key t: the order in which a lane's 32
+// probabilities (two 32-key score subtiles, rows (i / 4) 8 + half 4 + i % 4)
+// meet the 32 consecutive k of its half of a 32x32x64 FP8 product.
+__host__ __device__ inline int fp8_vt_col(int t) {
+  return (t & ~63) | (((t >> 2) & 1) << 5) | (((t >> 5) & 1) << 4) | (((t >> 3) & 3) << 2) | (t & 3);
+}
 
 int launch_gemm(Prec prec, int epi, int xmode, const GemmArgs& a, hipStream_t s);
 // Tubelet vectors of the requests in a (reqs, nreq, M, K = tubelet length,
@@ -116,6 +129,15 @@ int launch_quantize_rows(const float* w, int rows, int cols, uint8_t* w8, float*
 int launch_absmax(const __bf16* x, int rows, int D, const ReqDesc* reqs, int nreq, unsigned* slot, hipStream_t s);
 // scale[i] = absmax[i] / 448 (1 where nothing was recorded).
 int launch_scales_from_absmax(const unsigned* absmax, float* scale, int n, hipStream_t s);
+// Calibration of the FP8 attention: raise slots[h], slots[heads + h],
+// slots[2 heads + h] to max |Q|, |K|, |V| of head h over the live tokens of
+// the BF16 buffers q, k [heads][ld][64] and vt [heads][64][ld] (V^T columns
+// in the BF16 kernel's bits-2-and-3 order).
+int launch_attn_absmax(const __bf16* q, const __bf16* k, const __bf16* vt, int heads, int ld, int rows,
+                       const ReqDesc* reqs, int nreq, unsigned* slots, hipStream_t s);
+// Power-of-two scales 2^e, e = ceil(log2(absmax / 448)) (0 where nothing was
+// recorded): exps[i] = 127 + e (E8M0), inv[i] = 2^-e.
+int launch_attn_scales(const unsigned* absmax, int* exps, float* inv, int n, hipStream_t s);
 int launch_composite(const ReqDesc* reqs, int nreq, int channels, int max_pixels, int composite, hipStream_t s,
                      const int* dyn_nreq = nullptr);
 int launch_convert(Prec prec, const float* src, void* dst, long long n, hipStream_t s);

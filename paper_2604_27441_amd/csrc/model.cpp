@@ -39,7 +39,11 @@ int model_load(ModelW& m, int C, int T, int ne, int nd, Prec p, const float* hos
     m.nact = 4 * (ne + nd) + 1;
     REVO_HIP_TRY(hipMalloc(&m.act_scale, m.nact * 4));
     REVO_HIP_TRY(hipMalloc(&m.act_absmax, m.nact * 4));
-    m.bytes += m.count + m.count / 64 * 4 + m.nact * 8;
+    m.nattn = 3 * (m.He * ne + m.Hd * nd);
+    REVO_HIP_TRY(hipMalloc(&m.attn_absmax, m.nattn * 4));
+    REVO_HIP_TRY(hipMalloc(&m.attn_exp, m.nattn * 4));
+    REVO_HIP_TRY(hipMalloc(&m.attn_inv, m.nattn * 4));
+    m.bytes += m.count + m.count / 64 * 4 + m.nact * 8 + m.nattn * 12;
     if ((rc = model_reset_calibration(m, s))) return rc;
   }
   REVO_HIP_TRY(hipStreamSynchronize(s));
@@ -93,14 +97,17 @@ int model_load(ModelW& m, int C, int T, int ne, int nd, Prec p, const float* hos
 int model_reset_calibration(ModelW& m, hipStream_t s) {
   if (m.prec != P_FP8) return -22;
   int rc = launch_fill_zero(m.act_absmax, m.nact * 4, s);
+  if (!rc) rc = launch_fill_zero(m.attn_absmax, m.nattn * 4, s);
   if (rc) return rc;
   m.calibrated = false;
-  return launch_scales_from_absmax(m.act_absmax, m.act_scale, m.nact, s);
+  rc = launch_scales_from_absmax(m.act_absmax, m.act_scale, m.nact, s);
+  return rc ? rc : launch_attn_scales(m.attn_absmax, m.attn_exp, m.attn_inv, m.nattn, s);
 }
 
 int model_finish_calibration(ModelW& m, hipStream_t s) {
   if (m.prec != P_FP8) return -22;
-  const int rc = launch_scales_from_absmax(m.act_absmax, m.act_scale, m.nact, s);
+  int rc = launch_scales_from_absmax(m.act_absmax, m.act_scale, m.nact, s);
+  if (!rc) rc = launch_attn_scales(m.attn_absmax, m.attn_exp, m.attn_inv, m.nattn, s);
   if (rc) return rc;
   REVO_HIP_TRY(hipStreamSynchronize(s));
   m.calibrated = true;
@@ -108,11 +115,12 @@ int model_finish_calibration(ModelW& m, hipStream_t s) {
 }
 
 void model_free(ModelW& m) {
-  void* p[] = {m.master, m.ops, m.ops8, m.wscale, m.act_scale, m.act_absmax};
+  void* p[] = {m.master, m.ops, m.ops8, m.wscale, m.act_scale, m.act_absmax, m.attn_absmax, m.attn_exp, m.attn_inv};
   for (void* q : p)
     if (q) (void)hipFree(q);
   m.master = nullptr; m.ops = nullptr; m.ops8 = nullptr; m.wscale = nullptr;
   m.act_scale = nullptr; m.act_absmax = nullptr;
+  m.attn_absmax = nullptr; m.attn_exp = nullptr; m.attn_inv = nullptr;
 }
 
 int prof_init(Prof& p, int events) {
@@ -305,14 +313,20 @@ int enqueue_net(const ModelW& m, Workspace& w, int Mg, int Mhg, int nworkg, int 
       q.X = w.a; q.K = D; q.N = 3 * D; q.W = fp8 ? (const void*)b.qkv_w8 : b.qkv_w; q.bias = b.qkv_b;
       q.q = w.q; q.k = w.k; q.vt = w.vt; q.heads = heads; q.ldqk = w.ld; q.ldv = w.ld;
       q.qscale = 1.4426950408889634f / 8.0f;  // log2(e) / sqrt(64)
-      if (fp8) { q.wscale = b.qkv_s; q.xscale = m.act_scale + sq; }
+      const int ao = m.attn_off(dec, bi);
+      // FP8: E4M3 Q / K / V^T with per-head power-of-two scales for the FP8 attention
+      if (fp8) { q.wscale = b.qkv_s; q.xscale = m.act_scale + sq; q.head_inv = m.attn_inv + ao; }
       if ((e = gemm(pg, EPI_QKV, X_DENSE, q, Mreal))) return e;
+      if (record && (e = launch_attn_absmax((const __bf16*)w.q, (const __bf16*)w.k, (const __bf16*)w.vt, heads, w.ld, Mg,
+                                            w.d_reqs, nrec, m.attn_absmax + ao, s)))
+        return e;
       // the last decoder block only needs the queries of the target tubelet:
       // its other tokens feed nothing after it (the head reads the target rows)
       const bool last = dec && bi == m.nd - 1;
       AttnArgs ab = at;
       ab.heads = heads;
       ab.o_scale = fp8 ? m.act_scale + sp : nullptr;
+      ab.qkv_exp = fp8 ? m.attn_exp + ao : nullptr;
       if (last) {
         ab.work = w.d_work + w.max_work;
         ab.nwork = nworkg_last;
@@ -391,7 +405,10 @@ int forward(const ModelW& m, Workspace& w, int slot, int nrec, int nall, int com
     d.P = d.gy * d.gx;
     if (d.H * d.W > max_pix) max_pix = d.H * d.W;
     if (r >= nrec) { d.tok_off = M; d.head_off = Mh; continue; }
-    M = (M + 15) & ~15;  // every request starts a V^T key group of 16 (and 16-byte aligned columns)
+    // every request starts a V^T key group (16 keys for BF16, 64 for FP8
+    // attention) with 16-byte aligned columns
+    const int al = token_align(m.prec);
+    M = (M + al - 1) / al * al;
     d.tok_off = M;
     d.head_off = Mh;
     const int N = d.J * d.P;

@@ -37,6 +37,13 @@ struct ModelW {
   float* act_scale = nullptr;     // [nact] per-tensor activation scales (device)
   unsigned* act_absmax = nullptr; // [nact] calibration maxima (float bits, device)
   int nact = 0;
+  // FP8 attention: per block [3][heads] (Q, K, V) calibration maxima,
+  // E8M0 exponents (127 + e) and inverse scales 2^-e of the E4M3 operands
+  unsigned* attn_absmax = nullptr;
+  int* attn_exp = nullptr;
+  float* attn_inv = nullptr;
+  int nattn = 0;
+  int attn_off(bool dec, int block) const { return dec ? 3 * He * ne + 3 * Hd * block : 3 * He * block; }
   bool calibrated = false;
   int tub_len() const { return T * REVO_PATCH * REVO_PATCH * C; }
   int act_slot(bool dec, int block, int kind) const { return 4 * ((dec ? ne : 0) + block) + kind; }
@@ -95,6 +102,9 @@ void workspace_free(Workspace& w);
 
 // Tokens of one request at frame size H x W.
 int request_tokens(int H, int W, int J);
+// Token rows a request starts on: a V^T key group of 16 (BF16 attention) or
+// of 64 (FP8 attention).
+inline int token_align(Prec p) { return p == P_FP8 ? 64 : 16; }
 
 // Runs the network for w.h_reqs_slot[slot][0 .. nrec) and the composite for
 // entries [0 .. nall) (entries nrec.. are clean frames: copy only).  The

@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <vector>
 
 #include "../../include/revo.h"
 #include "../../include/revo_ops.h"
@@ -104,6 +105,46 @@ int revo_op_attention(int precision, const void* q, const void* k, const void* v
   }
   (void)hipFree(d);
   (void)hipFree(work);
+  return rc;
+}
+
+int revo_op_attention_fp8(const void* q8, const void* k8, const void* vt8, void* o, int heads, int ntok, int ld,
+                          const int* exps, void* stream) {
+  if (heads <= 0 || heads > 64 || ntok <= 0 || ld < ntok + 64 || !q8 || !k8 || !vt8 || !o || !exps) return REVO_EINVAL;
+  if (ld % 64) return REVO_EINVAL;  // whole 64-key groups of V^T, 16-byte aligned rows
+  for (int i = 0; i < 3 * heads; ++i)
+    if (exps[i] < -100 || exps[i] > 100) return REVO_EINVAL;
+  const int ntile = (ntok + 127) / 128;
+  if (ntile >= ATTN_TARGET_TILE) return REVO_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  ReqDesc h;
+  memset(&h, 0, sizeof(h));
+  h.J = 1; h.P = ntok; h.gy = 1; h.gx = ntok; h.H = 1; h.W = ntok; h.nframes = 1;
+  std::vector<int> hw(ntile);
+  for (int i = 0; i < ntile; ++i) hw[i] = i;
+  std::vector<int> he(3 * heads);
+  for (int i = 0; i < 3 * heads; ++i) he[i] = 127 + exps[i];
+  ReqDesc* d = nullptr;
+  int *work = nullptr, *de = nullptr;
+  int rc = 0;
+  if (hipMalloc(&d, sizeof(ReqDesc)) != hipSuccess || hipMalloc(&work, ntile * sizeof(int)) != hipSuccess ||
+      hipMalloc(&de, 3 * heads * sizeof(int)) != hipSuccess)
+    rc = REVO_ENOMEM;
+  if (!rc && (hipMemcpy(d, &h, sizeof(h), hipMemcpyHostToDevice) != hipSuccess ||
+              hipMemcpy(work, hw.data(), ntile * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+              hipMemcpy(de, he.data(), 3 * heads * sizeof(int), hipMemcpyHostToDevice) != hipSuccess))
+    rc = REVO_EDEVICE;
+  if (!rc) {
+    AttnArgs a;
+    memset(&a, 0, sizeof(a));
+    a.q = q8; a.k = k8; a.vt = vt8; a.o = o; a.heads = heads; a.ldqk = ld; a.ldv = ld;
+    a.reqs = d; a.nreq = 1; a.work = work; a.nwork = ntile; a.qkv_exp = de;
+    rc = launch_attention(P_FP8, a, s);
+    if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = REVO_EDEVICE;
+  }
+  if (d) (void)hipFree(d);
+  if (work) (void)hipFree(work);
+  if (de) (void)hipFree(de);
   return rc;
 }
 

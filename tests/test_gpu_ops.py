@@ -300,3 +300,61 @@ def test_linear_fp8(M, N, K, epi):
     if epi == 0:
         tol = tol + 4e-3 * np.abs(ref)
     assert np.all(np.abs(got - ref) <= tol + 1e-7), float(np.abs(got - ref).max())
+
+
+def _fp8_vt_col(t):
+    """Column of key t in the FP8 attention kernel's V^T (a permutation inside
+    each aligned group of 64 keys)."""
+    t = np.asarray(t)
+    return (t & ~63) | (((t >> 2) & 1) << 5) | (((t >> 5) & 1) << 4) | (((t >> 3) & 3) << 2) | (t & 3)
+
+
+def _e4m3_bytes(x):
+    return torch.tensor(np.asarray(x, np.float32)).to(torch.float8_e4m3fn).view(torch.uint8)
+
+
+@pytest.mark.parametrize("heads,ntok", [(1, 64), (3, 130), (2, 1000), (1, 4099)])
+def test_attention_fp8(heads, ntok):
+    """FP8 attention (the FP8 form) against FP64 on the exact operands, within
+    the error budget of the FP8-rounding oracle (E4M3 Q, K, V with per-head
+    power-of-two scales, E4M3 probabilities): twice its MSE, four times its
+    max error."""
+    rng = np.random.default_rng(4242 + ntok)
+    c = oracle.QK_LOG2
+    ld = (ntok + 64 + 63) // 64 * 64
+    q = rng.standard_normal((heads, ntok, 64)) * 1.5
+    k = rng.standard_normal((heads, ntok, 64)) * 1.5
+    v = rng.standard_normal((heads, ntok, 64))
+    q8 = torch.zeros((heads, ld, 64), dtype=torch.uint8)
+    k8 = torch.zeros((heads, ld, 64), dtype=torch.uint8)
+    vt8 = torch.zeros((heads, 64, ld), dtype=torch.uint8)
+    exps, rounded = [], []
+    for h in range(heads):
+        sq = oracle.pow2_scale(np.abs(q[h] * c).max() / 448)
+        sk = oracle.pow2_scale(np.abs(k[h]).max() / 448)
+        sv = oracle.pow2_scale(np.abs(v[h]).max() / 448)
+        exps.append((int(round(math.log2(sq))), int(round(math.log2(sk))), int(round(math.log2(sv)))))
+        q8[h, :ntok] = _e4m3_bytes(q[h] * c / sq)
+        k8[h, :ntok] = _e4m3_bytes(k[h] / sk)
+        vb = _e4m3_bytes(v[h] / sv)                               # [ntok][64]
+        vt8[h][:, torch.from_numpy(_fp8_vt_col(np.arange(ntok)))] = vb.T.contiguous()
+        rounded.append((oracle.e4m3_round(q[h] * c / sq) * sq / c, oracle.e4m3_round(k[h] / sk) * sk,
+                        oracle.e4m3_round(v[h] / sv) * sv))
+    ex = np.array([e[0] for e in exps] + [e[1] for e in exps] + [e[2] for e in exps], dtype=np.int32)
+    o = torch.zeros((ntok, heads * 64), dtype=torch.bfloat16).cuda()
+    qd, kd, vd = q8.cuda(), k8.cuda(), vt8.cuda()
+    rc = _lib().revo_op_attention_fp8(qd.data_ptr(), kd.data_ptr(), vd.data_ptr(), o.data_ptr(), heads, ntok, ld,
+                                      ex.ctypes.data, None)
+    assert rc == 0
+    got = o.double().cpu().numpy()
+    p_round = oracle.FP8Rounding({})
+    for h in range(heads):
+        exact = oracle.attention_head(q[h], k[h], v[h])
+        emu = oracle.attention_head(*rounded[h], rnd=p_round, site="x.attn.p")
+        g = got[:, h * 64:(h + 1) * 64]
+        e_gpu, e_emu = g - exact, emu - exact
+        rms, rms_emu = np.sqrt(np.mean(e_gpu ** 2)), np.sqrt(np.mean(e_emu ** 2))
+        print(f"fp8 attention heads {heads} ntok {ntok} h {h}: rms {rms:.3g} (oracle {rms_emu:.3g}), "
+              f"max {np.abs(e_gpu).max():.3g} (oracle {np.abs(e_emu).max():.3g})")
+        assert rms <= np.sqrt(2.0) * rms_emu, (h, rms, rms_emu)
+        assert np.abs(e_gpu).max() <= 4.0 * np.abs(e_emu).max(), h

@@ -194,8 +194,33 @@ def test_fp8_rounding_scales():
     assert np.all(np.abs(wq - w) <= np.abs(w).max(axis=1, keepdims=True) / 448 * 16 + 1e-15)
     x = RNG.standard_normal((5, 33))
     assert np.array_equal(r.act(x, "enc0.qkv"), oracle.e4m3_round(x / 0.01) * 0.01)
-    assert np.array_equal(r.act(x, "attn"), oracle.bf16_round(x))           # attention stays bf16
     assert np.array_equal(r.weight(w, "head"), oracle.bf16_round(w))
+    # without FP8 attention, attention operands stay bf16
+    r16 = oracle.FP8Rounding({"enc0.attn.k1": 0.01}, fp8_attention=False)
+    assert np.array_equal(r16.act(x, "enc0.attn.k1"), oracle.bf16_round(x))
+    assert np.array_equal(r16.act(np.abs(x), "enc0.attn.p"), oracle.bf16_round(np.abs(x)))
+
+
+def test_fp8_attention_operand_rounding():
+    """Attention operands of the FP8 form: per-head power-of-two scales (the
+    smallest power of two >= absmax / 448), Q rounded as the kernels hold it
+    (times log2(e) / 8), probabilities with unit scale."""
+    assert oracle.pow2_scale(0.3) == 0.5 and oracle.pow2_scale(0.25) == 0.25 and oracle.pow2_scale(0.0) == 1.0
+    assert oracle.pow2_scale(3.0) == 4.0 and oracle.pow2_scale(1e-3) == 2.0 ** -9
+    x = RNG.standard_normal((6, 64)) * 3
+    sc = {"dec0.attn.q2": 2.9 / 448, "dec0.attn.k2": 5.0 / 448, "dec0.attn.v2": 0.7 / 448}
+    r = oracle.FP8Rounding(sc)
+    c = oracle.QK_LOG2
+    sq = 2.0 ** math.ceil(math.log2(2.9 / 448 * c))
+    assert np.array_equal(r.act(x, "dec0.attn.q2"), oracle.e4m3_round(x * c / sq) * sq / c)
+    sk = 2.0 ** math.ceil(math.log2(5.0 / 448))
+    assert np.array_equal(r.act(x, "dec0.attn.k2"), oracle.e4m3_round(x / sk) * sk)
+    assert sk == 2.0 ** -6                                                 # 5/448 = 0.01116 -> 1/64
+    sv = 2.0 ** -9                                                         # 0.7/448 = 0.00156 -> 1/512
+    assert np.array_equal(r.act(x, "dec0.attn.v2"), oracle.e4m3_round(x / sv) * sv)
+    p = np.exp(-np.abs(x))
+    assert np.array_equal(r.act(p, "dec0.attn.p"), oracle.e4m3_round(p))
+    assert r.attn_operand("enc11.attn.q5") == "q" and r.attn_operand("enc11.qkv") is None
 
 
 def test_absmax_recorder_sites():
@@ -205,8 +230,9 @@ def test_absmax_recorder_sites():
     rec = oracle.AbsMaxRecorder()
     oracle.recover(req, blobs, enc_depth=2, dec_depth=1, rnd=rec, modalities=("rgb",))
     sites = set(rec.absmax)
-    want = {"emb", "e2d", "head", "attn"} | {f"{b}{i}.{k}" for b, n in (("enc", 2), ("dec", 1))
-                                            for i in range(n) for k in ("qkv", "proj", "fc1", "fc2")}
+    blocks = [(f"enc{i}.", 6) for i in range(2)] + [("dec0.", 3)]
+    want = {"emb", "e2d", "head"} | {f"{b}{k}" for b, _ in blocks for k in ("qkv", "proj", "fc1", "fc2", "attn.p")}
+    want |= {f"{b}attn.{t}{h}" for b, heads in blocks for t in "qkv" for h in range(heads)}
     assert sites == want
     assert all(v > 0 for v in rec.absmax.values())
     exact = oracle.recover(req, blobs, enc_depth=2, dec_depth=1, modalities=("rgb",))
