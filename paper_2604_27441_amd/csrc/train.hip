@@ -322,43 +322,19 @@ __device__ inline void load_dout(float (*t)[65], const float* __restrict__ dout,
   }
 }
 
-// P and dS of a 64 x 64 (query i, key j) tile into LDS (each thread a 4 x 4
-// piece: queries 4 ti .. +3, keys 4 tj .. +3); invalid rows/keys give 0.
-__device__ inline void tile_p_ds(float (*Qs)[65], float (*Ks)[65], float (*Vs)[65], float (*Ds)[65], const float* lse_s,
-                                 const float* dv_s, int nq, int nk, float (*Pt)[65], float (*dSt)[65]) {
-  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
-  float s[4][4] = {}, dp[4][4] = {};
-  for (int d = 0; d < 64; ++d) {
-    float qa[4], ka[4], oa[4], va[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      qa[a] = Qs[4 * ti + a][d];
-      oa[a] = Ds[4 * ti + a][d];
-      ka[a] = Ks[4 * tj + a][d];
-      va[a] = Vs[4 * tj + a][d];
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        s[a][b] = fmaf(qa[a], ka[b], s[a][b]);
-        dp[a][b] = fmaf(oa[a], va[b], dp[a][b]);
-      }
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int i = 4 * ti + a, j = 4 * tj + b;
-      const bool ok = i < nq && j < nk;
-      const float p = ok ? __builtin_amdgcn_exp2f(s[a][b] - lse_s[i]) : 0.0f;
-      Pt[i][j] = p;
-      dSt[i][j] = ok ? p * (dp[a][b] - dv_s[i]) : 0.0f;
-    }
+__device__ __forceinline__ f32x16 mfma_f32(float a, float b, const f32x16& c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
+// The tiles are products of 64 x 64 blocks over 64 (head dimension, queries
+// or keys), on FP32 32x32x2 MFMAs: lane l supplies A[l % 32][k] and B[k][l %
+// 32] for k = 2 step + l / 32, and holds C[row(i, l)][l % 32] (acc_row).
+// Each of the 4 waves takes one 32 x 32 tile per product.
+
 // dK and dV of one 64-key block of one (request, head), looping over the
-// request's query blocks.
+// request's query blocks.  Per block: wave (qc, kt) forms the 32 x 32 piece
+// of S = Qs K^T and dP = dO V^T, then P and dS go through LDS; wave (kt, dt)
+// accumulates dV += P^T dO and dK += dS^T Qs over the block's 64 queries.
 __global__ __launch_bounds__(TB) void attn_bwd_dkdv_kernel(const AttnBwdArgs a) {
   __shared__ float Qs[64][65], Ks[64][65], Vs[64][65], Ds[64][65], Pt[64][65], dSt[64][65];
   __shared__ float lse_s[64], dv_s[64];
@@ -371,8 +347,10 @@ __global__ __launch_bounds__(TB) void attn_bwd_dkdv_kernel(const AttnBwdArgs a) 
   const float* qh = a.q + (size_t)h * a.ld * 64;
   load_rows(Ks, a.k + (size_t)h * a.ld * 64, base + k0, base + N);
   load_vt(Vs, a.vt + (size_t)h * 64 * a.ld, a.ld, base + k0, base + N);
-  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;  // dK/dV piece: keys 4 ti .., dims 4 tj ..
-  float gk[4][4] = {}, gv[4][4] = {};
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, l32 = lane & 31;
+  const int qc = wave & 1, kt = wave >> 1;   // S / dP piece: queries 32 qc .., keys 32 kt ..
+  const int kt2 = wave >> 1, dt = wave & 1;  // dK / dV piece: keys 32 kt2 .., dims 32 dt ..
+  f32x16 gk = {}, gv = {};
   for (int q0 = 0; q0 < N; q0 += 64) {
     const int nq = min(64, N - q0);
     __syncthreads();
@@ -383,43 +361,44 @@ __global__ __launch_bounds__(TB) void attn_bwd_dkdv_kernel(const AttnBwdArgs a) 
       dv_s[threadIdx.x] = threadIdx.x < nq ? a.dv[(size_t)h * a.ld + base + q0 + threadIdx.x] : 0.0f;
     }
     __syncthreads();
-    tile_p_ds(Qs, Ks, Vs, Ds, lse_s, dv_s, nq, nk, Pt, dSt);
+    f32x16 sc = {}, dp = {};
+    for (int st = 0; st < 32; ++st) {
+      const int dd = 2 * st + half;
+      sc = mfma_f32(Qs[32 * qc + l32][dd], Ks[32 * kt + l32][dd], sc);
+      dp = mfma_f32(Ds[32 * qc + l32][dd], Vs[32 * kt + l32][dd], dp);
+    }
+    const int kl = 32 * kt + l32;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int ql = 32 * qc + acc_row(i, lane);
+      const bool ok = ql < nq && kl < nk;
+      const float pv = ok ? __builtin_amdgcn_exp2f(sc[i] - lse_s[ql]) : 0.0f;
+      Pt[ql][kl] = pv;
+      dSt[ql][kl] = ok ? pv * (dp[i] - dv_s[ql]) : 0.0f;
+    }
     __syncthreads();
-    for (int i = 0; i < 64; ++i) {
-      float p[4], ds[4], dov[4], qv[4];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        p[b] = Pt[i][4 * ti + b];
-        ds[b] = dSt[i][4 * ti + b];
-        dov[b] = Ds[i][4 * tj + b];
-        qv[b] = Qs[i][4 * tj + b];
-      }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          gv[x][y] = fmaf(p[x], dov[y], gv[x][y]);
-          gk[x][y] = fmaf(ds[x], qv[y], gk[x][y]);
-        }
+    for (int st = 0; st < 32; ++st) {
+      const int qq = 2 * st + half;
+      gv = mfma_f32(Pt[qq][32 * kt2 + l32], Ds[qq][32 * dt + l32], gv);
+      gk = mfma_f32(dSt[qq][32 * kt2 + l32], Qs[qq][32 * dt + l32], gk);
     }
   }
   const int D = a.heads * 64;
 #pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    const int j = 4 * ti + x;
-    if (j >= nk) continue;
-    float* row = a.dqkv + (size_t)(base + k0 + j) * 3 * D;
-#pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      row[D + h * 64 + 4 * tj + y] = gk[x][y] * 0.69314718055994531f;  // 1 / log2(e)
-      row[2 * D + h * 64 + 4 * tj + y] = gv[x][y];
-    }
+  for (int i = 0; i < 16; ++i) {
+    const int key = 32 * kt2 + acc_row(i, lane);
+    if (key >= nk) continue;
+    float* row = a.dqkv + (size_t)(base + k0 + key) * 3 * D;
+    row[D + h * 64 + 32 * dt + l32] = gk[i] * 0.69314718055994531f;  // 1 / log2(e)
+    row[2 * D + h * 64 + 32 * dt + l32] = gv[i];
   }
 }
 
 // dQ of one 64-query block of one (request, head), looping over key blocks.
+// Per block: wave (kt, qc) forms S^T = K Qs^T and dP^T = V dO^T (keys as
+// rows), dS^T goes through LDS; wave (dt, qc2) accumulates dQ^T += K^T dS^T.
 __global__ __launch_bounds__(TB) void attn_bwd_dq_kernel(const AttnBwdArgs a) {
-  __shared__ float Qs[64][65], Ks[64][65], Vs[64][65], Ds[64][65], Pt[64][65], dSt[64][65];
+  __shared__ float Qs[64][65], Ks[64][65], Vs[64][65], Ds[64][65], dSt[64][65];
   __shared__ float lse_s[64], dv_s[64];
   const int h = blockIdx.y;
   const int w = a.work[blockIdx.x];
@@ -433,37 +412,42 @@ __global__ __launch_bounds__(TB) void attn_bwd_dq_kernel(const AttnBwdArgs a) {
     lse_s[threadIdx.x] = threadIdx.x < nq ? a.lse[(size_t)h * a.ld + base + q0 + threadIdx.x] : 0.0f;
     dv_s[threadIdx.x] = threadIdx.x < nq ? a.dv[(size_t)h * a.ld + base + q0 + threadIdx.x] : 0.0f;
   }
-  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;  // dQ piece: queries 4 ti .., dims 4 tj ..
-  float gq[4][4] = {};
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, l32 = lane & 31;
+  const int kt = wave >> 1, qc = wave & 1;   // S^T piece: keys 32 kt .., queries 32 qc ..
+  const int dt = wave >> 1, qc2 = wave & 1;  // dQ^T piece: dims 32 dt .., queries 32 qc2 ..
+  f32x16 gq = {};
   for (int k0 = 0; k0 < N; k0 += 64) {
     const int nk = min(64, N - k0);
     __syncthreads();
     load_rows(Ks, a.k + (size_t)h * a.ld * 64, base + k0, base + N);
     load_vt(Vs, a.vt + (size_t)h * 64 * a.ld, a.ld, base + k0, base + N);
     __syncthreads();
-    tile_p_ds(Qs, Ks, Vs, Ds, lse_s, dv_s, nq, nk, Pt, dSt);
+    f32x16 sc = {}, dp = {};
+    for (int st = 0; st < 32; ++st) {
+      const int dd = 2 * st + half;
+      sc = mfma_f32(Ks[32 * kt + l32][dd], Qs[32 * qc + l32][dd], sc);
+      dp = mfma_f32(Vs[32 * kt + l32][dd], Ds[32 * qc + l32][dd], dp);
+    }
+    const int ql = 32 * qc + l32;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int kl = 32 * kt + acc_row(i, lane);
+      const bool ok = ql < nq && kl < nk;
+      const float pv = ok ? __builtin_amdgcn_exp2f(sc[i] - lse_s[ql]) : 0.0f;
+      dSt[kl][ql] = ok ? pv * (dp[i] - dv_s[ql]) : 0.0f;
+    }
     __syncthreads();
-    for (int j = 0; j < 64; ++j) {
-      float ds[4], kv[4];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        ds[b] = dSt[4 * ti + b][j];
-        kv[b] = Ks[j][4 * tj + b];
-      }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) gq[x][y] = fmaf(ds[x], kv[y], gq[x][y]);
+    for (int st = 0; st < 32; ++st) {
+      const int kk = 2 * st + half;
+      gq = mfma_f32(Ks[kk][32 * dt + l32], dSt[kk][32 * qc2 + l32], gq);
     }
   }
   const int D = a.heads * 64;
+  const int q = 32 * qc2 + l32;
+  if (q < nq) {
+    float* row = a.dqkv + (size_t)(base + q0 + q) * 3 * D + h * 64 + 32 * dt;
 #pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    const int i = 4 * ti + x;
-    if (i >= nq) continue;
-    float* row = a.dqkv + (size_t)(base + q0 + i) * 3 * D;
-#pragma unroll
-    for (int y = 0; y < 4; ++y) row[h * 64 + 4 * tj + y] = gq[x][y] * 0.125f;
+    for (int i = 0; i < 16; ++i) row[acc_row(i, lane)] = gq[i] * 0.125f;
   }
 }
 
