@@ -276,48 +276,75 @@ __global__ __launch_bounds__(256) void quantize_rows_kernel(const float* __restr
   for (int c = threadIdx.x; c < cols; c += 256) w8[(size_t)blockIdx.x * cols + c] = e4m3(wr[c] * inv);
 }
 
-__global__ __launch_bounds__(256) void absmax_kernel(const __bf16* __restrict__ x, int rows, int D,
-                                                     const ReqDesc* __restrict__ reqs, int nreq,
-                                                     unsigned* __restrict__ slot) {
-  const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= rows) return;
-  const ReqDesc& d = reqs[find_req_tok(reqs, nreq, row)];
-  if (row - d.tok_off >= d.J * d.P) return;  // alignment gap
-  const __bf16* xr = x + (size_t)row * D;
-  float m = 0.0f;
-  for (int c = lane; c < D; c += 64) m = fmaxf(m, fabsf((float)xr[c]));
+// max |x| of 256 threads into one atomicMax per block (non-negative floats
+// order as their bits)
+__device__ inline void block_max_to(float m, unsigned* __restrict__ slot) {
+  __shared__ float red[4];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-  if (lane == 0) atomicMax(slot, __float_as_uint(m));  // non-negative floats order as their bits
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(slot, __float_as_uint(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]))));
 }
 
-// one wave per token row of one head (grid.y): max |.| over the row's 64
-// values of Q and K and the token's V^T column
+__device__ inline float absmax8(const uint4& u, float m) {
+  const unsigned w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    m = fmaxf(m, fabsf(__uint_as_float(w[i] << 16)));
+    m = fmaxf(m, fabsf(__uint_as_float(w[i] & 0xFFFF0000u)));
+  }
+  return m;
+}
+
+// max |x| over the live rows of every request (the alignment gaps between
+// requests are skipped): 16-byte loads over each request's contiguous rows,
+// grid-stride, one atomic per block.  D is a multiple of 8.
+__global__ __launch_bounds__(256) void absmax_kernel(const __bf16* __restrict__ x, int D,
+                                                     const ReqDesc* __restrict__ reqs, int nreq,
+                                                     unsigned* __restrict__ slot) {
+  float m = 0.0f;
+  const long long stride = (long long)gridDim.x * 256;
+  for (int r = 0; r < nreq; ++r) {
+    const uint4* p = reinterpret_cast<const uint4*>(x + (size_t)reqs[r].tok_off * D);
+    const long long n = (long long)reqs[r].J * reqs[r].P * D / 8;
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += stride) m = absmax8(p[i], m);
+  }
+  block_max_to(m, slot);
+}
+
+// Per head (grid.y): max |.| of Q and K over the live token rows, and of V
+// over the same tokens' V^T columns (BF16 V^T rows keep keys with bits 2
+// and 3 swapped).  slots: Q maxima [heads], then K, then V.
 __global__ __launch_bounds__(256) void attn_absmax_kernel(const __bf16* __restrict__ q, const __bf16* __restrict__ k,
-                                                          const __bf16* __restrict__ vt, int heads, int ld, int rows,
+                                                          const __bf16* __restrict__ vt, int heads, int ld,
                                                           const ReqDesc* __restrict__ reqs, int nreq,
                                                           unsigned* __restrict__ slots) {
-  const int lane = threadIdx.x & 63, h = blockIdx.y;
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (t >= rows) return;
-  const ReqDesc& d = reqs[find_req_tok(reqs, nreq, t)];
-  if (t - d.tok_off >= d.J * d.P) return;  // alignment gap
-  const size_t row = ((size_t)h * ld + t) * 64 + lane;
-  const int col = (t & ~12) | ((t & 4) << 1) | ((t & 8) >> 1);  // bits 2 and 3 swapped
-  float mq = fabsf((float)q[row]), mk = fabsf((float)k[row]);
-  float mv = fabsf((float)vt[((size_t)h * 64 + lane) * ld + col]);
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    mq = fmaxf(mq, __shfl_xor(mq, o));
-    mk = fmaxf(mk, __shfl_xor(mk, o));
-    mv = fmaxf(mv, __shfl_xor(mv, o));
+  const int h = blockIdx.y;
+  float mq = 0.0f, mk = 0.0f, mv = 0.0f;
+  const long long stride = (long long)gridDim.x * 256;
+  for (int r = 0; r < nreq; ++r) {
+    const int t0 = reqs[r].tok_off, N = reqs[r].J * reqs[r].P;
+    const size_t off = ((size_t)h * ld + t0) * 64;
+    const uint4* qp = reinterpret_cast<const uint4*>(q + off);
+    const uint4* kp = reinterpret_cast<const uint4*>(k + off);
+    const long long n8 = (long long)N * 8;  // 16-byte chunks of N rows of 64
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n8; i += stride) {
+      mq = absmax8(qp[i], mq);
+      mk = absmax8(kp[i], mk);
+    }
+    const __bf16* vh = vt + (size_t)h * 64 * ld;
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < 64LL * N; i += stride) {
+      const int d = (int)(i / N), t = t0 + (int)(i - (long long)d * N);
+      const int col = (t & ~12) | ((t & 4) << 1) | ((t & 8) >> 1);
+      mv = fmaxf(mv, fabsf((float)vh[(size_t)d * ld + col]));
+    }
   }
-  if (lane == 0) {
-    atomicMax(slots + h, __float_as_uint(mq));
-    atomicMax(slots + heads + h, __float_as_uint(mk));
-    atomicMax(slots + 2 * heads + h, __float_as_uint(mv));
-  }
+  block_max_to(mq, slots + h);
+  __syncthreads();
+  block_max_to(mk, slots + heads + h);
+  __syncthreads();
+  block_max_to(mv, slots + 2 * heads + h);
 }
 
 __global__ void attn_scales_kernel(const unsigned* __restrict__ absmax, int* __restrict__ exps,
@@ -441,14 +468,16 @@ int launch_quantize_rows(const float* w, int rows, int cols, uint8_t* w8, float*
 
 int launch_absmax(const __bf16* x, int rows, int D, const ReqDesc* reqs, int nreq, unsigned* slot, hipStream_t s) {
   if (rows <= 0) return 0;
-  absmax_kernel<<<cdiv(rows, 4), 256, 0, s>>>(x, rows, D, reqs, nreq, slot);
+  if (D % 8) return -22;
+  absmax_kernel<<<cdiv(rows, 256) < 1024 ? cdiv(rows, 256) : 1024, 256, 0, s>>>(x, D, reqs, nreq, slot);
   return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 
 int launch_attn_absmax(const __bf16* q, const __bf16* k, const __bf16* vt, int heads, int ld, int rows,
                        const ReqDesc* reqs, int nreq, unsigned* slots, hipStream_t s) {
   if (rows <= 0) return 0;
-  attn_absmax_kernel<<<dim3(cdiv(rows, 4), heads), 256, 0, s>>>(q, k, vt, heads, ld, rows, reqs, nreq, slots);
+  attn_absmax_kernel<<<dim3(cdiv(rows, 256) < 256 ? cdiv(rows, 256) : 256, heads), 256, 0, s>>>(q, k, vt, heads, ld,
+                                                                                            reqs, nreq, slots);
   return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 

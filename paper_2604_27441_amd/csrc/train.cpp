@@ -98,9 +98,9 @@ struct revo_trainer {
   float *U = nullptr, *xe = nullptr, *ae = nullptr, *zd = nullptr, *ahead = nullptr, *pred = nullptr, *G = nullptr;
   std::vector<BlockAct> act;  // ne encoder blocks, then nd decoder blocks
   float *dpred = nullptr, *dhead = nullptr, *dahead = nullptr, *xdy = nullptr, *dxe = nullptr, *dz = nullptr;
-  float *dG = nullptr, *dH1 = nullptr, *da = nullptr, *dO = nullptr, *dqkv = nullptr, *trA = nullptr, *trB = nullptr;
+  float *dG = nullptr, *dH1 = nullptr, *da = nullptr, *dO = nullptr, *dqkv = nullptr;
   float *part = nullptr, *dvec = nullptr, *splitk = nullptr;
-  size_t splitk_elems = 0, tr_elems = 0;
+  size_t splitk_elems = 0;
   double* loss_part = nullptr;
   std::vector<double> h_loss_part;
 };
@@ -129,36 +129,23 @@ int mm(revo_trainer* t, const float* x, const float* w, float* out, int M, int N
 
 // dW [out][in] = dY^T X over Mrows rows (dY [Mrows][out], X [Mrows][in]),
 // db = column sums of dY.  The contraction runs over the token rows, and
-// out x in is only a few output tiles, so it is split along the rows: S
-// products of kc rows each (one batched launch over chunked transposes),
-// then their sum.
+// out x in is only a few output tiles, so it is split along the rows into S
+// chunks of kc rows (one launch, grid.y = chunk) whose partial products are
+// then summed in chunk order.
 int weight_grad(revo_trainer* t, const float* dy, const float* x, int Mrows, const Lin& l, float* gblob) {
   int e;
-  const int nblk = Mrows / 64;
-  const int tiles = cdiv(l.out, 128) * (l.in % 128 == 0 ? l.in / 128 : cdiv(l.in, 64));
+  const int tiles = cdiv(l.out, 128) * cdiv(l.in, 128);
   int S = 512 / tiles;
-  if (S > nblk / 2) S = nblk / 2;
-  if (S < 2) {
-    if ((e = launch_transpose(dy, t->trA, Mrows, l.out, l.out, Mrows, t->s))) return e;
-    if ((e = launch_transpose(x, t->trB, Mrows, l.in, l.in, Mrows, t->s))) return e;
-    if ((e = mm(t, t->trA, t->trB, gblob + l.w, l.out, l.in, Mrows, l.in))) return e;
-  } else {
-    const int g = cdiv(nblk, S), kc = 64 * g;
-    S = cdiv(nblk, g);
-    if ((size_t)S * l.out * l.in > t->splitk_elems ||
-        (size_t)S * kc * (l.out > l.in ? l.out : l.in) > t->tr_elems)
-      return -22;
-    if ((e = launch_transpose_chunked(dy, t->trA, Mrows, l.out, l.out, kc, S, t->s))) return e;
-    if ((e = launch_transpose_chunked(x, t->trB, Mrows, l.in, l.in, kc, S, t->s))) return e;
-    GemmArgs a;
-    memset(&a, 0, sizeof(a));
-    a.M = l.out; a.N = l.in; a.K = kc; a.X = t->trA; a.W = t->trB; a.bias = t->zero; a.out = t->splitk;
-    a.ldo = l.in;
-    a.batch = S; a.bsx = (long long)l.out * kc; a.bsw = (long long)l.in * kc; a.bso = (long long)l.out * l.in;
-    if ((e = launch_gemm(P_FP32, EPI_STORE, X_DENSE, a, t->s))) return e;
-    if ((e = launch_sum_chunks(t->splitk, S, (long long)l.out * l.in, gblob + l.w, t->s))) return e;
-  }
-  return launch_colsum(dy, Mrows, l.out, l.out, t->part, t->max_chunks, gblob + l.b, t->s);
+  if (S > Mrows / 256) S = Mrows / 256;  // at least 256 rows (16 stages) per chunk
+  if (S < 1) S = 1;
+  const int kc = align_up(cdiv(Mrows, S), 16);
+  S = cdiv(Mrows, kc);
+  if (S == 1)
+    return launch_wgrad(dy, x, Mrows, l.out, l.in, l.out, l.in, kc, 1, gblob + l.w, gblob + l.b, t->s);
+  if ((size_t)S * l.out * l.in > t->splitk_elems || S > t->max_chunks) return -22;
+  if ((e = launch_wgrad(dy, x, Mrows, l.out, l.in, l.out, l.in, kc, S, t->splitk, t->part, t->s))) return e;
+  if ((e = launch_sum_chunks(t->splitk, S, (long long)l.out * l.in, gblob + l.w, t->s))) return e;
+  return launch_sum_chunks(t->part, S, l.out, gblob + l.b, t->s);
 }
 
 // dX [Mrows][in] = dY W (dY [Mrows][out]) on the transposed weights
@@ -427,14 +414,11 @@ int setup(revo_trainer* t, const revo_train_config& c) {
   }
   const size_t Mx = Mp > (size_t)t->Mh_pad ? Mp : (size_t)t->Mh_pad;
   const size_t widest = (size_t)(t->Lt > 4 * De ? t->Lt : 4 * De);
-  // transposed operands: split-K chunks round the rows up by less than half
-  t->tr_elems = widest * (Mx * 3 / 2 + 64);
   if ((e = alloc_n(t, &t->dpred, (size_t)t->B * t->H * t->W * t->C)) ||
       (e = alloc_n(t, &t->dhead, (size_t)t->Mh_pad * 256 * t->C)) || (e = alloc_n(t, &t->dahead, (size_t)t->Mh_pad * Dd)) ||
       (e = alloc_n(t, &t->xdy, Mx * De)) || (e = alloc_n(t, &t->dxe, Mp * De)) || (e = alloc_n(t, &t->dz, Mp * Dd)) ||
       (e = alloc_n(t, &t->dG, Mp * 4 * De)) || (e = alloc_n(t, &t->dH1, Mp * 4 * De)) || (e = alloc_n(t, &t->da, Mp * De)) ||
       (e = alloc_n(t, &t->dO, Mp * De)) || (e = alloc_n(t, &t->dqkv, Mp * 3 * De)) ||
-      (e = alloc_n(t, &t->trA, t->tr_elems)) || (e = alloc_n(t, &t->trB, t->tr_elems)) ||
       (e = alloc_n(t, &t->part, (size_t)t->max_chunks * widest)) || (e = alloc_n(t, &t->dvec, (size_t)6 * t->ld)) ||
       (e = alloc_n(t, &t->loss_part, t->loss_blocks)))
     return e;

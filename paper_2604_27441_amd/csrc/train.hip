@@ -40,27 +40,6 @@ __global__ __launch_bounds__(TB) void transpose_kernel(const float* __restrict__
   }
 }
 
-// Chunked transpose for split-K products: row r of in [rows][cols] goes to
-// out[r / kc][c][r % kc]; rows rows .. nchunk kc - 1 of the last chunk are
-// zeros.  kc is a multiple of 64.
-__global__ __launch_bounds__(TB) void transpose_chunked_kernel(const float* __restrict__ in, float* __restrict__ out,
-                                                               int rows, int cols, int ld_in, int kc) {
-  __shared__ float t[64][65];
-  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int i = ty; i < 64; i += 4) {
-    const int r = r0 + i, c = c0 + tx;
-    t[i][tx] = (r < rows && c < cols) ? in[(size_t)r * ld_in + c] : 0.0f;
-  }
-  __syncthreads();
-  const int ch = r0 / kc, rr0 = r0 - ch * kc;
-  float* o = out + (size_t)ch * cols * kc;
-  for (int i = ty; i < 64; i += 4) {
-    const int c = c0 + i;
-    if (c < cols) o[(size_t)c * kc + rr0 + tx] = t[tx][i];
-  }
-}
-
 // out[i] = sum over b of part[b n + i], b in order
 __global__ __launch_bounds__(TB) void sum_chunks_kernel(const float* __restrict__ part, int nb, long long n,
                                                         float* __restrict__ out) {
@@ -100,6 +79,111 @@ __global__ __launch_bounds__(TB) void colsum_final_kernel(const float* __restric
   __syncthreads();
   if (l == 0 && c < cols)
     out[c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+// ---- weight gradients ------------------------------------------------------------
+
+// part[c][o][i] = sum over the rows m of chunk c (rows c kc .. c kc + kc - 1
+// below `rows`) of dy[m][o] x[m][i], c = blockIdx.y; with bpart, the tiles of
+// the first input columns also write bpart[c][o] = the same rows' sum of
+// dy[m][o].  Both operands are read as they lie (token rows, features
+// contiguous), so no transposed copies are made.  Tile 128 (o) x 128 (i) on
+// 4 waves of 64 x 64 (2 x 2 FP32 32x32x2 MFMA blocks); stages of 16 rows of
+// each operand double-buffered in LDS, the next stage fetched into registers
+// during the current one's products.
+struct WgradArgs {
+  const float* dy;
+  const float* x;
+  int rows, nout, nin, ldy, ldx, kc;
+  float* part;
+  float* bpart;
+};
+
+__global__ __launch_bounds__(TB, 2) void wgrad_kernel(const WgradArgs a) {
+  constexpr int R = 16, P = 160;  // rows per stage; row pitch (half-waves read rows 2s and 2s + 1 on disjoint banks)
+  __shared__ __attribute__((aligned(16))) float sy[2][R][P], sx[2][R][P];
+  const int gi = (a.nin + 127) / 128;
+  const int o0 = (blockIdx.x / gi) * 128, i0 = (blockIdx.x - (blockIdx.x / gi) * gi) * 128;
+  const int m0 = blockIdx.y * a.kc, m1 = min(a.rows, m0 + a.kc);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5, l32 = lane & 31;
+  const int wo = wave >> 1, wi = wave & 1;
+  // loader: row tid / 16 of the stage, columns 8 (tid % 16) .. +7 of the tile
+  const int lr = tid >> 4, lc = (tid & 15) * 8;
+  const bool yok = o0 + lc < a.nout, xok = i0 + lc < a.nin;  // the column counts are multiples of 8
+  const float* yp = a.dy + o0 + lc;
+  const float* xp = a.x + i0 + lc;
+  const bool bias = a.bpart && i0 == 0;
+  float4 ry[2], rx[2];
+  float bs[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  auto fetch = [&](int r0) {
+    const int m = r0 + lr;
+    const bool live = m < m1;
+    const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    ry[0] = live && yok ? *reinterpret_cast<const float4*>(yp + (size_t)m * a.ldy) : z;
+    ry[1] = live && yok ? *reinterpret_cast<const float4*>(yp + (size_t)m * a.ldy + 4) : z;
+    rx[0] = live && xok ? *reinterpret_cast<const float4*>(xp + (size_t)m * a.ldx) : z;
+    rx[1] = live && xok ? *reinterpret_cast<const float4*>(xp + (size_t)m * a.ldx + 4) : z;
+  };
+  auto put = [&](int b) {
+    *reinterpret_cast<float4*>(&sy[b][lr][lc]) = ry[0];
+    *reinterpret_cast<float4*>(&sy[b][lr][lc + 4]) = ry[1];
+    *reinterpret_cast<float4*>(&sx[b][lr][lc]) = rx[0];
+    *reinterpret_cast<float4*>(&sx[b][lr][lc + 4]) = rx[1];
+    if (bias) {
+      bs[0] += ry[0].x; bs[1] += ry[0].y; bs[2] += ry[0].z; bs[3] += ry[0].w;
+      bs[4] += ry[1].x; bs[5] += ry[1].y; bs[6] += ry[1].z; bs[7] += ry[1].w;
+    }
+  };
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) { acc[u][0] = f32x16{}; acc[u][1] = f32x16{}; }
+  const int nst = (m1 - m0 + R - 1) / R;
+  if (nst > 0) {
+    fetch(m0);
+    put(0);
+  }
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int b = st & 1;
+    if (st + 1 < nst) fetch(m0 + (st + 1) * R);
+#pragma unroll
+    for (int k = 0; k < R / 2; ++k) {
+      const int r = 2 * k + half;
+      const float y0 = sy[b][r][64 * wo + l32], y1 = sy[b][r][64 * wo + 32 + l32];
+      const float x0 = sx[b][r][64 * wi + l32], x1 = sx[b][r][64 * wi + 32 + l32];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(y0, x0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(y0, x1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(y1, x0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(y1, x1, acc[1][1], 0, 0, 0);
+    }
+    if (st + 1 < nst) put(b ^ 1);
+    __syncthreads();
+  }
+  float* out = a.part + (size_t)blockIdx.y * a.nout * a.nin;
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int i = i0 + 64 * wi + 32 * v + l32;
+      if (i >= a.nin) continue;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int o = o0 + 64 * wo + 32 * u + acc_row(j, lane);
+        if (o < a.nout) out[(size_t)o * a.nin + i] = acc[u][v][j];
+      }
+    }
+  if (bias) {
+    // the 16 loader rows' sums of each column, added in row order
+    float* red = &sx[0][0][0];  // [16][128]: free after the last barrier
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[lr * 128 + lc + e] = bs[e];
+    __syncthreads();
+    if (tid < 128 && o0 + tid < a.nout) {
+      float t = 0.0f;
+      for (int r = 0; r < R; ++r) t += red[r * 128 + tid];
+      a.bpart[(size_t)blockIdx.y * a.nout + o0 + tid] = t;
+    }
+  }
 }
 
 // ---- elementwise ----------------------------------------------------------------
@@ -329,14 +413,47 @@ __device__ __forceinline__ f32x16 mfma_f32(float a, float b, const f32x16& c) {
 // The tiles are products of 64 x 64 blocks over 64 (head dimension, queries
 // or keys), on FP32 32x32x2 MFMAs: lane l supplies A[l % 32][k] and B[k][l %
 // 32] for k = 2 step + l / 32, and holds C[row(i, l)][l % 32] (acc_row).
-// Each of the 4 waves takes one 32 x 32 tile per product.
+// Each of the 4 waves takes one 32 x 32 tile per product.  The operand a
+// wave reuses for every block of the loop stays in registers (32 values per
+// matrix); the loop's next block is fetched into registers while the current
+// one is multiplied, and stored to LDS once the current one is consumed.
+
+// 16 values per thread of a 64 x 64 tile of a [rows][pitch] matrix (row
+// offset r0, rows at or past rmax read as zeros): thread t takes rows
+// t / 64 + 4 j, column t % 64.
+__device__ __forceinline__ void fetch_rows(float (&r)[16], const float* __restrict__ src, size_t pitch, int r0, int rmax) {
+  const int c = threadIdx.x & 63, rb = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int row = r0 + rb + 4 * j;
+    r[j] = row < rmax ? src[(size_t)row * pitch + c] : 0.0f;
+  }
+}
+__device__ __forceinline__ void store_rows(float (*t)[65], const float (&r)[16]) {
+  const int c = threadIdx.x & 63, rb = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) t[rb + 4 * j][c] = r[j];
+}
+// The same from V^T [64][ld]: thread t takes dimensions t / 64 + 4 j of key
+// c0 + t % 64 (keys at or past cmax as zeros); store_cols writes t[key][d].
+__device__ __forceinline__ void fetch_cols(float (&r)[16], const float* __restrict__ vt, int ld, int c0, int cmax) {
+  const int c = threadIdx.x & 63, db = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) r[j] = c0 + c < cmax ? vt[(size_t)(db + 4 * j) * ld + c0 + c] : 0.0f;
+}
+__device__ __forceinline__ void store_cols(float (*t)[65], const float (&r)[16]) {
+  const int c = threadIdx.x & 63, db = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) t[c][db + 4 * j] = r[j];
+}
 
 // dK and dV of one 64-key block of one (request, head), looping over the
 // request's query blocks.  Per block: wave (qc, kt) forms the 32 x 32 piece
-// of S = Qs K^T and dP = dO V^T, then P and dS go through LDS; wave (kt, dt)
-// accumulates dV += P^T dO and dK += dS^T Qs over the block's 64 queries.
-__global__ __launch_bounds__(TB) void attn_bwd_dkdv_kernel(const AttnBwdArgs a) {
-  __shared__ float Qs[64][65], Ks[64][65], Vs[64][65], Ds[64][65], Pt[64][65], dSt[64][65];
+// of S = Qs K^T and dP = dO V^T (K and V rows of its keys in registers), P
+// and dS go through LDS; wave (kt, dt) accumulates dV += P^T dO and
+// dK += dS^T Qs over the block's 64 queries.
+__global__ __launch_bounds__(TB, 2) void attn_bwd_dkdv_kernel(const AttnBwdArgs a) {
+  __shared__ float Qs[64][65], Ds[64][65], Pt[64][65], dSt[64][65];
   __shared__ float lse_s[64], dv_s[64];
   const int h = blockIdx.y;
   const int w = a.work[blockIdx.x];
@@ -345,27 +462,59 @@ __global__ __launch_bounds__(TB) void attn_bwd_dkdv_kernel(const AttnBwdArgs a) 
   const int k0 = (w & 0xFFFF) * 64;
   const int nk = min(64, N - k0);
   const float* qh = a.q + (size_t)h * a.ld * 64;
-  load_rows(Ks, a.k + (size_t)h * a.ld * 64, base + k0, base + N);
-  load_vt(Vs, a.vt + (size_t)h * 64 * a.ld, a.ld, base + k0, base + N);
+  const float* doh = a.dout + h * 64;
+  const size_t dpitch = (size_t)a.heads * 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, l32 = lane & 31;
   const int qc = wave & 1, kt = wave >> 1;   // S / dP piece: queries 32 qc .., keys 32 kt ..
   const int kt2 = wave >> 1, dt = wave & 1;  // dK / dV piece: keys 32 kt2 .., dims 32 dt ..
+
+  // K and V rows of this wave's keys into registers (through LDS)
+  float kr[32], vr[32];
+  {
+    float t0[16], t1[16];
+    fetch_rows(t0, a.k + (size_t)h * a.ld * 64, 64, base + k0, base + N);
+    fetch_cols(t1, a.vt + (size_t)h * 64 * a.ld, a.ld, base + k0, base + N);
+    store_rows(Pt, t0);
+    store_cols(dSt, t1);
+  }
+  float pq[16], pd[16], plse = 0.0f, pdv = 0.0f;
+  fetch_rows(pq, qh, 64, base, base + N);
+  fetch_rows(pd, doh, dpitch, base, base + N);
+  if (threadIdx.x < 64 && threadIdx.x < N) {
+    plse = a.lse[(size_t)h * a.ld + base + threadIdx.x];
+    pdv = a.dv[(size_t)h * a.ld + base + threadIdx.x];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int st = 0; st < 32; ++st) {
+    kr[st] = Pt[32 * kt + l32][2 * st + half];
+    vr[st] = dSt[32 * kt + l32][2 * st + half];
+  }
   f32x16 gk = {}, gv = {};
   for (int q0 = 0; q0 < N; q0 += 64) {
     const int nq = min(64, N - q0);
-    __syncthreads();
-    load_rows(Qs, qh, base + q0, base + N);
-    load_dout(Ds, a.dout, a.heads, h, base + q0, base + N);
+    __syncthreads();  // the previous block's Qs, Ds, Pt, dSt are consumed
+    store_rows(Qs, pq);
+    store_rows(Ds, pd);
     if (threadIdx.x < 64) {
-      lse_s[threadIdx.x] = threadIdx.x < nq ? a.lse[(size_t)h * a.ld + base + q0 + threadIdx.x] : 0.0f;
-      dv_s[threadIdx.x] = threadIdx.x < nq ? a.dv[(size_t)h * a.ld + base + q0 + threadIdx.x] : 0.0f;
+      lse_s[threadIdx.x] = plse;
+      dv_s[threadIdx.x] = pdv;
     }
     __syncthreads();
+    if (q0 + 64 < N) {
+      fetch_rows(pq, qh, 64, base + q0 + 64, base + N);
+      fetch_rows(pd, doh, dpitch, base + q0 + 64, base + N);
+      if (threadIdx.x < 64 && q0 + 64 + (int)threadIdx.x < N) {
+        plse = a.lse[(size_t)h * a.ld + base + q0 + 64 + threadIdx.x];
+        pdv = a.dv[(size_t)h * a.ld + base + q0 + 64 + threadIdx.x];
+      }
+    }
     f32x16 sc = {}, dp = {};
+#pragma unroll
     for (int st = 0; st < 32; ++st) {
       const int dd = 2 * st + half;
-      sc = mfma_f32(Qs[32 * qc + l32][dd], Ks[32 * kt + l32][dd], sc);
-      dp = mfma_f32(Ds[32 * qc + l32][dd], Vs[32 * kt + l32][dd], dp);
+      sc = mfma_f32(Qs[32 * qc + l32][dd], kr[st], sc);
+      dp = mfma_f32(Ds[32 * qc + l32][dd], vr[st], dp);
     }
     const int kl = 32 * kt + l32;
 #pragma unroll
@@ -377,6 +526,7 @@ __global__ __launch_bounds__(TB) void attn_bwd_dkdv_kernel(const AttnBwdArgs a) 
       dSt[ql][kl] = ok ? pv * (dp[i] - dv_s[ql]) : 0.0f;
     }
     __syncthreads();
+#pragma unroll 8
     for (int st = 0; st < 32; ++st) {
       const int qq = 2 * st + half;
       gv = mfma_f32(Pt[qq][32 * kt2 + l32], Ds[qq][32 * dt + l32], gv);
@@ -396,47 +546,70 @@ __global__ __launch_bounds__(TB) void attn_bwd_dkdv_kernel(const AttnBwdArgs a) 
 
 // dQ of one 64-query block of one (request, head), looping over key blocks.
 // Per block: wave (kt, qc) forms S^T = K Qs^T and dP^T = V dO^T (keys as
-// rows), dS^T goes through LDS; wave (dt, qc2) accumulates dQ^T += K^T dS^T.
-__global__ __launch_bounds__(TB) void attn_bwd_dq_kernel(const AttnBwdArgs a) {
-  __shared__ float Qs[64][65], Ks[64][65], Vs[64][65], Ds[64][65], dSt[64][65];
-  __shared__ float lse_s[64], dv_s[64];
+// rows; Q and dO rows of its queries in registers), dS^T goes through LDS;
+// wave (dt, qc2) accumulates dQ^T += K^T dS^T.
+__global__ __launch_bounds__(TB, 2) void attn_bwd_dq_kernel(const AttnBwdArgs a) {
+  __shared__ float Ks[64][65], Vs[64][65], dSt[64][65];
   const int h = blockIdx.y;
   const int w = a.work[blockIdx.x];
   const ReqDesc& d = a.reqs[w >> 16];
   const int N = d.J * d.P, base = d.tok_off;
   const int q0 = (w & 0xFFFF) * 64;
   const int nq = min(64, N - q0);
-  load_rows(Qs, a.q + (size_t)h * a.ld * 64, base + q0, base + N);
-  load_dout(Ds, a.dout, a.heads, h, base + q0, base + N);
-  if (threadIdx.x < 64) {
-    lse_s[threadIdx.x] = threadIdx.x < nq ? a.lse[(size_t)h * a.ld + base + q0 + threadIdx.x] : 0.0f;
-    dv_s[threadIdx.x] = threadIdx.x < nq ? a.dv[(size_t)h * a.ld + base + q0 + threadIdx.x] : 0.0f;
-  }
+  const float* kh = a.k + (size_t)h * a.ld * 64;
+  const float* vth = a.vt + (size_t)h * 64 * a.ld;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, l32 = lane & 31;
   const int kt = wave >> 1, qc = wave & 1;   // S^T piece: keys 32 kt .., queries 32 qc ..
   const int dt = wave >> 1, qc2 = wave & 1;  // dQ^T piece: dims 32 dt .., queries 32 qc2 ..
+  const int ql = 32 * qc + l32;
+
+  // Q and dO rows of this wave's queries into registers (through LDS)
+  float qr[32], dr[32];
+  {
+    float t0[16], t1[16];
+    fetch_rows(t0, a.q + (size_t)h * a.ld * 64, 64, base + q0, base + N);
+    fetch_rows(t1, a.dout + h * 64, (size_t)a.heads * 64, base + q0, base + N);
+    store_rows(Ks, t0);
+    store_rows(Vs, t1);
+  }
+  const float lse = ql < nq ? a.lse[(size_t)h * a.ld + base + q0 + ql] : 0.0f;
+  const float dvq = ql < nq ? a.dv[(size_t)h * a.ld + base + q0 + ql] : 0.0f;
+  float pk[16], pv[16];
+  fetch_rows(pk, kh, 64, base, base + N);
+  fetch_cols(pv, vth, a.ld, base, base + N);
+  __syncthreads();
+#pragma unroll
+  for (int st = 0; st < 32; ++st) {
+    qr[st] = Ks[ql][2 * st + half];
+    dr[st] = Vs[ql][2 * st + half];
+  }
   f32x16 gq = {};
   for (int k0 = 0; k0 < N; k0 += 64) {
     const int nk = min(64, N - k0);
+    __syncthreads();  // the previous block's Ks, Vs, dSt are consumed
+    store_rows(Ks, pk);
+    store_cols(Vs, pv);
     __syncthreads();
-    load_rows(Ks, a.k + (size_t)h * a.ld * 64, base + k0, base + N);
-    load_vt(Vs, a.vt + (size_t)h * 64 * a.ld, a.ld, base + k0, base + N);
-    __syncthreads();
+    if (k0 + 64 < N) {
+      fetch_rows(pk, kh, 64, base + k0 + 64, base + N);
+      fetch_cols(pv, vth, a.ld, base + k0 + 64, base + N);
+    }
     f32x16 sc = {}, dp = {};
+#pragma unroll
     for (int st = 0; st < 32; ++st) {
       const int dd = 2 * st + half;
-      sc = mfma_f32(Ks[32 * kt + l32][dd], Qs[32 * qc + l32][dd], sc);
-      dp = mfma_f32(Vs[32 * kt + l32][dd], Ds[32 * qc + l32][dd], dp);
+      sc = mfma_f32(Ks[32 * kt + l32][dd], qr[st], sc);
+      dp = mfma_f32(Vs[32 * kt + l32][dd], dr[st], dp);
     }
-    const int ql = 32 * qc + l32;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int kl = 32 * kt + acc_row(i, lane);
       const bool ok = ql < nq && kl < nk;
-      const float pv = ok ? __builtin_amdgcn_exp2f(sc[i] - lse_s[ql]) : 0.0f;
-      dSt[kl][ql] = ok ? pv * (dp[i] - dv_s[ql]) : 0.0f;
+      const float p = ok ? __builtin_amdgcn_exp2f(sc[i] - lse) : 0.0f;
+      dSt[kl][ql] = ok ? p * (dp[i] - dvq) : 0.0f;
     }
     __syncthreads();
+#pragma unroll 8
     for (int st = 0; st < 32; ++st) {
       const int kk = 2 * st + half;
       gq = mfma_f32(Ks[kk][32 * dt + l32], dSt[kk][32 * qc2 + l32], gq);
@@ -481,13 +654,6 @@ int launch_transpose(const float* in, float* out, int rows, int cols, int ld_in,
   return last();
 }
 
-int launch_transpose_chunked(const float* in, float* out, int rows, int cols, int ld_in, int kc, int nchunk,
-                             hipStream_t s) {
-  if (rows <= 0 || cols <= 0 || kc % 64 || (long long)nchunk * kc < rows) return -22;
-  transpose_chunked_kernel<<<dim3(cdiv(cols, 64), nchunk * kc / 64), TB, 0, s>>>(in, out, rows, cols, ld_in, kc);
-  return last();
-}
-
 int launch_sum_chunks(const float* part, int nb, long long n, float* out, hipStream_t s) {
   sum_chunks_kernel<<<grid_for(n), TB, 0, s>>>(part, nb, n, out);
   return last();
@@ -501,6 +667,19 @@ int launch_colsum(const float* x, int rows, int cols, int ld, float* part, int m
   colsum_part_kernel<<<dim3(cdiv(cols, 64), nchunk), TB, 0, s>>>(x, rows, cols, ld, chunk, part);
   if (int e = last()) return e;
   colsum_final_kernel<<<cdiv(cols, 64), TB, 0, s>>>(part, nchunk, cols, out);
+  return last();
+}
+
+int launch_wgrad(const float* dy, const float* x, int rows, int nout, int nin, int ldy, int ldx, int kc, int nchunk,
+                 float* part, float* bpart, hipStream_t s) {
+  if (nout % 8 || nin % 8 || ldy % 4 || ldx % 4 || kc <= 0 || nchunk <= 0 || nchunk > 65535 ||
+      (size_t)(nchunk - 1) * kc >= (size_t)(rows > 0 ? rows : 1) ||
+      (((uintptr_t)dy | (uintptr_t)x) & 15))
+    return -22;
+  WgradArgs a;
+  a.dy = dy; a.x = x; a.rows = rows; a.nout = nout; a.nin = nin; a.ldy = ldy; a.ldx = ldx; a.kc = kc;
+  a.part = part; a.bpart = bpart;
+  wgrad_kernel<<<dim3(cdiv(nout, 128) * cdiv(nin, 128), nchunk), TB, 0, s>>>(a);
   return last();
 }
 
