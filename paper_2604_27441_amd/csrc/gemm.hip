@@ -853,10 +853,11 @@ int launch_t(const GemmArgs& a, hipStream_t s) {
     return -22;  // not reached: every BF16 dense product takes the ring
   } else {
     // the gather loader's per-row token coordinates leave no registers for a
-    // 128-wide tile with two prefetched stages
+    // 128-wide tile with two prefetched stages; products with fewer 128-wide
+    // tiles than CUs (short token counts) take 64-wide tiles, twice as many
     const int nb = a.batch > 1 ? a.batch : 1;
     if constexpr (XM == X_DENSE) {
-      if (a.N % 128 == 0) {
+      if (a.N % 128 == 0 && (long long)gm * (a.N / 128) * nb >= 256) {
         gemm_kernel<Op, 128, EPI, XM, OutT><<<dim3(gm * (a.N / 128), nb), NT, 0, s>>>(a);
         return hipGetLastError() == hipSuccess ? 0 : -5;
       }

@@ -136,7 +136,7 @@ int weight_grad(revo_trainer* t, const float* dy, const float* x, int Mrows, con
   int e;
   const int tiles = cdiv(l.out, 128) * cdiv(l.in, 128);
   int S = 512 / tiles;
-  if (S > Mrows / 256) S = Mrows / 256;  // at least 256 rows (16 stages) per chunk
+  if (S > Mrows / 64) S = Mrows / 64;  // at least 64 rows (4 stages) per chunk
   if (S < 1) S = 1;
   const int kc = align_up(cdiv(Mrows, S), 16);
   S = cdiv(Mrows, kc);
@@ -372,7 +372,7 @@ int setup(revo_trainer* t, const revo_train_config& c) {
   t->Mh_pad = align_up(t->Mh, 64);
   t->ld = t->Mpad + 64;
   t->loss_blocks = 256;
-  t->max_chunks = cdiv(t->Mpad > t->Mh_pad ? t->Mpad : t->Mh_pad, 128);
+  t->max_chunks = cdiv(t->Mpad > t->Mh_pad ? t->Mpad : t->Mh_pad, 64);  // 128-row column-sum chunks, 64-row dW chunks
   const size_t n = t->L.count;
   if ((e = alloc_n(t, &t->theta, n)) || (e = alloc_n(t, &t->grad, n)) || (e = alloc_n(t, &t->mom, n)) ||
       (e = alloc_n(t, &t->vel, n)) || (e = alloc_n(t, &t->wT, n)) || (e = alloc_n(t, &t->zero, 4096)))
