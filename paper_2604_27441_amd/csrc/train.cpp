@@ -140,11 +140,20 @@ int weight_grad(revo_trainer* t, const float* dy, const float* x, int Mrows, con
   if (S < 1) S = 1;
   const int kc = align_up(cdiv(Mrows, S), 16);
   S = cdiv(Mrows, kc);
-  if (S == 1)
-    return launch_wgrad(dy, x, Mrows, l.out, l.in, l.out, l.in, kc, 1, gblob + l.w, gblob + l.b, t->s);
-  if ((size_t)S * l.out * l.in > t->splitk_elems || S > t->max_chunks) return -22;
-  if ((e = launch_wgrad(dy, x, Mrows, l.out, l.in, l.out, l.in, kc, S, t->splitk, t->part, t->s))) return e;
-  if ((e = launch_sum_chunks(t->splitk, S, (long long)l.out * l.in, gblob + l.w, t->s))) return e;
+  const long long nw = (long long)l.out * l.in;
+  if (S == 1) return launch_wgrad(dy, x, Mrows, l.out, l.in, l.out, l.in, kc, 1, gblob + l.w, nw, gblob + l.b, 0, t->s);
+  if (l.b == l.w + (size_t)nw) {
+    // the blob keeps a layer's bias right after its weights: chunk c's
+    // partial dW and db are laid out the same way, and one sum covers both
+    if ((size_t)S * (nw + l.out) > t->splitk_elems) return -22;
+    if ((e = launch_wgrad(dy, x, Mrows, l.out, l.in, l.out, l.in, kc, S, t->splitk, nw + l.out, t->splitk + nw,
+                          nw + l.out, t->s)))
+      return e;
+    return launch_sum_chunks(t->splitk, S, nw + l.out, gblob + l.w, t->s);
+  }
+  if ((size_t)S * nw > t->splitk_elems || S > t->max_chunks) return -22;
+  if ((e = launch_wgrad(dy, x, Mrows, l.out, l.in, l.out, l.in, kc, S, t->splitk, nw, t->part, l.out, t->s))) return e;
+  if ((e = launch_sum_chunks(t->splitk, S, nw, gblob + l.w, t->s))) return e;
   return launch_sum_chunks(t->part, S, l.out, gblob + l.b, t->s);
 }
 

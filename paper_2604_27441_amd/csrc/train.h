@@ -11,12 +11,13 @@ int launch_sum_chunks(const float* part, int nb, long long n, float* out, hipStr
 // out[c] = sum over rows of x[r][c] (fixed order: 128-row chunks, then the
 // chunks); part holds max_chunks x cols floats.
 int launch_colsum(const float* x, int rows, int cols, int ld, float* part, int max_chunks, float* out, hipStream_t s);
-// Weight-gradient chunks: part[c][o][i] = sum over rows m of chunk c (rows
-// c kc .. c kc + kc - 1 below rows) of dy[m][o] x[m][i]; with bpart, also
-// bpart[c][o] = the chunk's sum of dy[m][o].  Column counts multiple of 8,
-// row pitches of 4, operands 16-byte aligned; every chunk holds rows.
+// Weight-gradient chunks: part[c pstride + o nin + i] = sum over rows m of
+// chunk c (rows c kc .. c kc + kc - 1 below rows) of dy[m][o] x[m][i]; with
+// bpart, also bpart[c bstride + o] = the chunk's sum of dy[m][o].  Column
+// counts multiple of 8, row pitches of 4, operands 16-byte aligned; every
+// chunk holds rows.
 int launch_wgrad(const float* dy, const float* x, int rows, int nout, int nin, int ldy, int ldx, int kc, int nchunk,
-                 float* part, float* bpart, hipStream_t s);
+                 float* part, long long pstride, float* bpart, long long bstride, hipStream_t s);
 int launch_gelu_fwd(const float* h, float* g, long long n, hipStream_t s);
 int launch_gelu_bwd(const float* dg, const float* h, float* dh, long long n, hipStream_t s);
 // LayerNorm backward (y = LN(x) g + b, eps 1e-6): dres[row] += dL/dx,

@@ -97,6 +97,7 @@ struct WgradArgs {
   int rows, nout, nin, ldy, ldx, kc;
   float* part;
   float* bpart;
+  long long pstride, bstride;  // elements from one chunk's part / bpart to the next
 };
 
 __global__ __launch_bounds__(TB, 2) void wgrad_kernel(const WgradArgs a) {
@@ -159,7 +160,7 @@ __global__ __launch_bounds__(TB, 2) void wgrad_kernel(const WgradArgs a) {
     if (st + 1 < nst) put(b ^ 1);
     __syncthreads();
   }
-  float* out = a.part + (size_t)blockIdx.y * a.nout * a.nin;
+  float* out = a.part + (size_t)blockIdx.y * a.pstride;
 #pragma unroll
   for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(TB, 2) void wgrad_kernel(const WgradArgs a) {
     if (tid < 128 && o0 + tid < a.nout) {
       float t = 0.0f;
       for (int r = 0; r < R; ++r) t += red[r * 128 + tid];
-      a.bpart[(size_t)blockIdx.y * a.nout + o0 + tid] = t;
+      a.bpart[(size_t)blockIdx.y * a.bstride + o0 + tid] = t;
     }
   }
 }
@@ -671,14 +672,15 @@ int launch_colsum(const float* x, int rows, int cols, int ld, float* part, int m
 }
 
 int launch_wgrad(const float* dy, const float* x, int rows, int nout, int nin, int ldy, int ldx, int kc, int nchunk,
-                 float* part, float* bpart, hipStream_t s) {
+                 float* part, long long pstride, float* bpart, long long bstride, hipStream_t s) {
   if (nout % 8 || nin % 8 || ldy % 4 || ldx % 4 || kc <= 0 || nchunk <= 0 || nchunk > 65535 ||
+      (nchunk > 1 && (pstride < (long long)nout * nin || (bpart && bstride < nout))) ||
       (size_t)(nchunk - 1) * kc >= (size_t)(rows > 0 ? rows : 1) ||
       (((uintptr_t)dy | (uintptr_t)x) & 15))
     return -22;
   WgradArgs a;
   a.dy = dy; a.x = x; a.rows = rows; a.nout = nout; a.nin = nin; a.ldy = ldy; a.ldx = ldx; a.kc = kc;
-  a.part = part; a.bpart = bpart;
+  a.part = part; a.bpart = bpart; a.pstride = pstride; a.bstride = bstride;
   wgrad_kernel<<<dim3(cdiv(nout, 128) * cdiv(nin, 128), nchunk), TB, 0, s>>>(a);
   return last();
 }
