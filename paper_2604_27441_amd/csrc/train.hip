@@ -108,22 +108,26 @@ __global__ __launch_bounds__(TB, 2) void wgrad_kernel(const WgradArgs a) {
   const int m0 = blockIdx.y * a.kc, m1 = min(a.rows, m0 + a.kc);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5, l32 = lane & 31;
   const int wo = wave >> 1, wi = wave & 1;
-  // loader: row tid / 16 of the stage, columns 8 (tid % 16) .. +7 of the tile
+  // loader: row tid / 16 of the stage, columns 8 (tid % 16) .. +7 of the
+  // tile.  Buffer loads: the descriptors end at the chunk's last row, so rows
+  // past it read as zeros without a branch.  Columns past the matrix (a
+  // partial last tile) read the next row or zeros; they only reach outputs
+  // and bias sums that are not stored.
   const int lr = tid >> 4, lc = (tid & 15) * 8;
-  const bool yok = o0 + lc < a.nout, xok = i0 + lc < a.nin;  // the column counts are multiples of 8
-  const float* yp = a.dy + o0 + lc;
-  const float* xp = a.x + i0 + lc;
+  const __amdgpu_buffer_rsrc_t yrs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)a.dy, (short)0, m1 * a.ldy * (int)sizeof(float), 0x00020000);
+  const __amdgpu_buffer_rsrc_t xrs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)a.x, (short)0, m1 * a.ldx * (int)sizeof(float), 0x00020000);
   const bool bias = a.bpart && i0 == 0;
   float4 ry[2], rx[2];
   float bs[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   auto fetch = [&](int r0) {
     const int m = r0 + lr;
-    const bool live = m < m1;
-    const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    ry[0] = live && yok ? *reinterpret_cast<const float4*>(yp + (size_t)m * a.ldy) : z;
-    ry[1] = live && yok ? *reinterpret_cast<const float4*>(yp + (size_t)m * a.ldy + 4) : z;
-    rx[0] = live && xok ? *reinterpret_cast<const float4*>(xp + (size_t)m * a.ldx) : z;
-    rx[1] = live && xok ? *reinterpret_cast<const float4*>(xp + (size_t)m * a.ldx + 4) : z;
+    const int yo = (m * a.ldy + o0 + lc) * (int)sizeof(float), xo = (m * a.ldx + i0 + lc) * (int)sizeof(float);
+    ry[0] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(yrs, yo, 0, 0));
+    ry[1] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(yrs, yo + 16, 0, 0));
+    rx[0] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(xrs, xo, 0, 0));
+    rx[1] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(xrs, xo + 16, 0, 0));
   };
   auto put = [&](int b) {
     *reinterpret_cast<float4*>(&sy[b][lr][lc]) = ry[0];
@@ -673,7 +677,9 @@ int launch_colsum(const float* x, int rows, int cols, int ld, float* part, int m
 
 int launch_wgrad(const float* dy, const float* x, int rows, int nout, int nin, int ldy, int ldx, int kc, int nchunk,
                  float* part, long long pstride, float* bpart, long long bstride, hipStream_t s) {
-  if (nout % 8 || nin % 8 || ldy % 4 || ldx % 4 || kc <= 0 || nchunk <= 0 || nchunk > 65535 ||
+  // buffer-load byte offsets are 32-bit
+  if ((long long)rows * (ldy > ldx ? ldy : ldx) * 4 + 64 >= (1LL << 31)) return -22;
+  if (nout % 8 || nin % 8 || ldy % 4 || ldx % 4 || ldy < nout || ldx < nin || kc <= 0 || nchunk <= 0 || nchunk > 65535 ||
       (nchunk > 1 && (pstride < (long long)nout * nin || (bpart && bstride < nout))) ||
       (size_t)(nchunk - 1) * kc >= (size_t)(rows > 0 ? rows : 1) ||
       (((uintptr_t)dy | (uintptr_t)x) & 15))
