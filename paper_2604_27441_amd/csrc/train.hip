@@ -425,14 +425,15 @@ __device__ __forceinline__ f32x16 mfma_f32(float a, float b, const f32x16& c) {
 
 // 16 values per thread of a 64 x 64 tile of a [rows][pitch] matrix (row
 // offset r0, rows at or past rmax read as zeros): thread t takes rows
-// t / 64 + 4 j, column t % 64.
-__device__ __forceinline__ void fetch_rows(float (&r)[16], const float* __restrict__ src, size_t pitch, int r0, int rmax) {
+// t / 64 + 4 j, column t % 64.  Buffer loads whose descriptor ends at row
+// rmax give the zeros without a branch.
+__device__ __forceinline__ void fetch_rows(float (&r)[16], const float* __restrict__ src, int pitch, int r0, int rmax) {
   const int c = threadIdx.x & 63, rb = threadIdx.x >> 6;
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)src, (short)0, rmax * pitch * (int)sizeof(float), 0x00020000);
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int row = r0 + rb + 4 * j;
-    r[j] = row < rmax ? src[(size_t)row * pitch + c] : 0.0f;
-  }
+  for (int j = 0; j < 16; ++j)
+    r[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, ((r0 + rb + 4 * j) * pitch + c) * 4, 0, 0));
 }
 __device__ __forceinline__ void store_rows(float (*t)[65], const float (&r)[16]) {
   const int c = threadIdx.x & 63, rb = threadIdx.x >> 6;
@@ -440,11 +441,16 @@ __device__ __forceinline__ void store_rows(float (*t)[65], const float (&r)[16])
   for (int j = 0; j < 16; ++j) t[rb + 4 * j][c] = r[j];
 }
 // The same from V^T [64][ld]: thread t takes dimensions t / 64 + 4 j of key
-// c0 + t % 64 (keys at or past cmax as zeros); store_cols writes t[key][d].
-__device__ __forceinline__ void fetch_cols(float (&r)[16], const float* __restrict__ vt, int ld, int c0, int cmax) {
+// c0 + t % 64; store_cols writes t[key][d].  Keys past the request read
+// what the padded V^T holds there (zeros or other requests' finite values):
+// every product that takes them is masked by a select.
+__device__ __forceinline__ void fetch_cols(float (&r)[16], const float* __restrict__ vt, int ld, int c0) {
   const int c = threadIdx.x & 63, db = threadIdx.x >> 6;
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)vt, (short)0, 64 * ld * (int)sizeof(float), 0x00020000);
 #pragma unroll
-  for (int j = 0; j < 16; ++j) r[j] = c0 + c < cmax ? vt[(size_t)(db + 4 * j) * ld + c0 + c] : 0.0f;
+  for (int j = 0; j < 16; ++j)
+    r[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, ((db + 4 * j) * ld + c0 + c) * 4, 0, 0));
 }
 __device__ __forceinline__ void store_cols(float (*t)[65], const float (&r)[16]) {
   const int c = threadIdx.x & 63, db = threadIdx.x >> 6;
@@ -468,7 +474,7 @@ __global__ __launch_bounds__(TB, 2) void attn_bwd_dkdv_kernel(const AttnBwdArgs 
   const int nk = min(64, N - k0);
   const float* qh = a.q + (size_t)h * a.ld * 64;
   const float* doh = a.dout + h * 64;
-  const size_t dpitch = (size_t)a.heads * 64;
+  const int dpitch = a.heads * 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, l32 = lane & 31;
   const int qc = wave & 1, kt = wave >> 1;   // S / dP piece: queries 32 qc .., keys 32 kt ..
   const int kt2 = wave >> 1, dt = wave & 1;  // dK / dV piece: keys 32 kt2 .., dims 32 dt ..
@@ -478,7 +484,7 @@ __global__ __launch_bounds__(TB, 2) void attn_bwd_dkdv_kernel(const AttnBwdArgs 
   {
     float t0[16], t1[16];
     fetch_rows(t0, a.k + (size_t)h * a.ld * 64, 64, base + k0, base + N);
-    fetch_cols(t1, a.vt + (size_t)h * 64 * a.ld, a.ld, base + k0, base + N);
+    fetch_cols(t1, a.vt + (size_t)h * 64 * a.ld, a.ld, base + k0);
     store_rows(Pt, t0);
     store_cols(dSt, t1);
   }
@@ -573,7 +579,7 @@ __global__ __launch_bounds__(TB, 2) void attn_bwd_dq_kernel(const AttnBwdArgs a)
   {
     float t0[16], t1[16];
     fetch_rows(t0, a.q + (size_t)h * a.ld * 64, 64, base + q0, base + N);
-    fetch_rows(t1, a.dout + h * 64, (size_t)a.heads * 64, base + q0, base + N);
+    fetch_rows(t1, a.dout + h * 64, a.heads * 64, base + q0, base + N);
     store_rows(Ks, t0);
     store_rows(Vs, t1);
   }
@@ -581,7 +587,7 @@ __global__ __launch_bounds__(TB, 2) void attn_bwd_dq_kernel(const AttnBwdArgs a)
   const float dvq = ql < nq ? a.dv[(size_t)h * a.ld + base + q0 + ql] : 0.0f;
   float pk[16], pv[16];
   fetch_rows(pk, kh, 64, base, base + N);
-  fetch_cols(pv, vth, a.ld, base, base + N);
+  fetch_cols(pv, vth, a.ld, base);
   __syncthreads();
 #pragma unroll
   for (int st = 0; st < 32; ++st) {
@@ -597,7 +603,7 @@ __global__ __launch_bounds__(TB, 2) void attn_bwd_dq_kernel(const AttnBwdArgs a)
     __syncthreads();
     if (k0 + 64 < N) {
       fetch_rows(pk, kh, 64, base + k0 + 64, base + N);
-      fetch_cols(pv, vth, a.ld, base + k0 + 64, base + N);
+      fetch_cols(pv, vth, a.ld, base + k0 + 64);
     }
     f32x16 sc = {}, dp = {};
 #pragma unroll
@@ -725,6 +731,9 @@ int launch_head_grad(const ReqDesc* reqs, int nreq, int Mh, int Mh_pad, int C, c
 int launch_attention_bwd(const float* q, const float* k, const float* vt, const float* o, const float* dout,
                          const float* lse, float* dv, float* dqkv, int M, int heads, int ld, const ReqDesc* reqs,
                          const int* work, int nwork, hipStream_t s) {
+  // the block loaders' buffer offsets are 32-bit byte offsets into one head's
+  // Q / K / V^T slab or into dout
+  if ((long long)ld * 64 * 4 >= (1LL << 31) || (long long)ld * heads * 64 * 4 >= (1LL << 31) || M > ld) return -22;
   attn_bwd_dot_kernel<<<cdiv(M * heads, TB / 64), TB, 0, s>>>(o, dout, M, heads, ld, dv);
   if (int e = last()) return e;
   AttnBwdArgs a;
