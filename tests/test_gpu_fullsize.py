@@ -104,8 +104,6 @@ def test_fullsize_fp8_samples():
     oracle calibrated on, request 0 of the batch of 8 stays within the
     FP8-rounding oracle's error budget against FP64."""
     from paper_2604_27441_amd import Recoverer
-    if not os.path.exists(GOLDEN_FP8):
-        pytest.skip("tests/golden/c4_720p_fp8_samples.json not generated yet (tests/golden/make_golden.py c4fp8)")
     g = json.load(open(GOLDEN_FP8))
     req = synth.make_batch("c4", n=1)[0]
     calib = synth.make_calibration_set(720, 1280, n=8)
