@@ -508,9 +508,10 @@ __global__ __launch_bounds__(NT, sizeof(typename Op::T) == 2 ? 3 : 2) void attn_
 // so the score products come out in the BF16 kernel's units (log2 scale,
 // onto the -max register block).  The probabilities are E4M3 with unit
 // scale; the max is raised lazily as in the safe pass above, which keeps
-// them at most 2^8 (E4M3 holds up to 448).  The row sum adds the float
-// probabilities.  A head dimension of 64 is one product step: per 64-key
-// block a wave issues 2 score and 2 P V products.  K rows and V^T rows are
+// them at most 2^8 (E4M3 holds up to 448).  The row sums are those of the
+// E4M3 probabilities, taken by one more product per block (a ones row
+// against P^T) instead of VALU adds.  A head dimension of 64 is one product
+// step: per 64-key block a wave issues 2 score, 2 P V and 1 row-sum products.  K rows and V^T rows are
 // 64 bytes in LDS, 16-byte chunk c of row r at slot c ^ ((r >> 2) & 3), so
 // the 16 rows one read phase touches cover all banks.  V^T columns are in
 // fp8_vt_col order within each group of 64 keys (requests start on
@@ -530,8 +531,9 @@ __device__ __forceinline__ i32x8 load_frag8(const uint8_t* __restrict__ t, int r
 
 template <bool MASK, bool FIRST>
 __device__ __forceinline__ void fp8_block(const uint8_t* __restrict__ kt, const uint8_t* __restrict__ vt,
-                                          const i32x8& qf, f32x16 (&oacc)[2], f32x16& negm, float& m_run,
-                                          float& l_run, int lane, int kvalid, int eqk_q, int eqk_k, int ev) {
+                                          const i32x8& qf, const i32x8& ones, f32x16 (&oacc)[2], f32x16& lacc,
+                                          f32x16& negm, float& m_run, int lane, int kvalid, int eqk_q, int eqk_k,
+                                          int ev) {
   const int half = lane >> 5, l32 = lane & 31;
   i32x8 kf[2];
 #pragma unroll
@@ -570,21 +572,20 @@ __device__ __forceinline__ void fp8_block(const uint8_t* __restrict__ kt, const 
       const float d = grow ? mloc : 0.0f;
       const float alpha = __builtin_amdgcn_exp2f(-d);
       m_run += d;
-      l_run *= alpha;
       oacc[0] *= alpha;
       oacc[1] *= alpha;
+      lacc *= alpha;
 #pragma unroll
       for (int i = 0; i < 16; ++i) negm[i] = -m_run;
 #pragma unroll
       for (int st = 0; st < 2; ++st)
 #pragma unroll
         for (int i = 0; i < 16; ++i) sacc[st][i] -= d;
-      asm volatile("" : "+v"(oacc[0]), "+v"(oacc[1]), "+v"(sacc[0]), "+v"(sacc[1]), "+v"(negm));
+      asm volatile("" : "+v"(oacc[0]), "+v"(oacc[1]), "+v"(lacc), "+v"(sacc[0]), "+v"(sacc[1]), "+v"(negm));
     }
   }
   // probabilities: byte j = 16 st + i of the lane's 32 (fp8_vt_col order)
   i32x8 pf;
-  float ls0 = l_run, ls1 = 0.0f;
 #pragma unroll
   for (int st = 0; st < 2; ++st)
 #pragma unroll
@@ -592,13 +593,13 @@ __device__ __forceinline__ void fp8_block(const uint8_t* __restrict__ kt, const 
       float p[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) p[e] = __builtin_amdgcn_exp2f(sacc[st][4 * g + e]);
-      ls0 += p[0] + p[2];
-      ls1 += p[1] + p[3];
       pf[st * 4 + g] = (int)e4m3x4(p[0], p[1], p[2], p[3]);
     }
-  l_run = ls0 + ls1;
 #pragma unroll
   for (int ds = 0; ds < 2; ++ds) oacc[ds] = mfma_fp8(load_frag8(vt, ds * 32 + l32, half), pf, oacc[ds], ev, 127);
+  // row sums of the E4M3 probabilities on the matrix core: a block whose
+  // row 0 is all ones (the other rows zero) times P^T
+  lacc = mfma_fp8(ones, pf, lacc, 127, 127);
 }
 
 __global__ __launch_bounds__(NT, 3) void attn_fp8_kernel(const AttnArgs a) {
@@ -649,47 +650,53 @@ __global__ __launch_bounds__(NT, 3) void attn_fp8_kernel(const AttnArgs a) {
     dma16_att(krs, ks + buf * TB + wave * 16 * 64, kvo, kb * 64);
     dma16_att(vrs, vs + buf * TB + wave * 16 * 64, vvo, kb);
   };
-  f32x16 oacc[2], negm;
+  f32x16 oacc[2], lacc, negm;
   oacc[0] = f32x16{};
   oacc[1] = f32x16{};
+  lacc = f32x16{};
   negm = f32x16{};
-  float m_run = 0.0f, l_run = 0.0f;
+  float m_run = 0.0f;
+  // row 0 of the row-sum block: E4M3 ones (0x38) from lanes 0 and 32
+  const int one8 = (lane & 31) == 0 ? 0x38383838 : 0;
+  const i32x8 ones = {one8, one8, one8, one8, one8, one8, one8, one8};
   const int nkb = (N + KB - 1) / KB;
   const int nfull = N / KB;
   fetch(0, 0);
   wait_vm_att<0>();
   __syncthreads();
   if (nfull == 0) {
-    fp8_block<true, true>(ks, vs, qf, oacc, negm, m_run, l_run, lane, N, sq, sk, sv);
+    fp8_block<true, true>(ks, vs, qf, ones, oacc, lacc, negm, m_run, lane, N, sq, sk, sv);
   } else {
     fetch(nkb > 1 ? KB : 0, 1);
-    fp8_block<false, true>(ks, vs, qf, oacc, negm, m_run, l_run, lane, KB, sq, sk, sv);
+    fp8_block<false, true>(ks, vs, qf, ones, oacc, lacc, negm, m_run, lane, KB, sq, sk, sv);
     wait_vm_att<0>();
     __syncthreads();
     int b = 1;
     for (; b + 1 < nfull; b += 2) {
       fetch((b + 1) * KB, 0);
-      fp8_block<false, false>(ks + TB, vs + TB, qf, oacc, negm, m_run, l_run, lane, KB, sq, sk, sv);
+      fp8_block<false, false>(ks + TB, vs + TB, qf, ones, oacc, lacc, negm, m_run, lane, KB, sq, sk, sv);
       wait_vm_att<0>();
       __syncthreads();
       fetch(b + 2 < nkb ? (b + 2) * KB : (b + 1) * KB, 1);
-      fp8_block<false, false>(ks, vs, qf, oacc, negm, m_run, l_run, lane, KB, sq, sk, sv);
+      fp8_block<false, false>(ks, vs, qf, ones, oacc, lacc, negm, m_run, lane, KB, sq, sk, sv);
       wait_vm_att<0>();
       __syncthreads();
     }
     if (b < nfull) {
       fetch(b + 1 < nkb ? (b + 1) * KB : b * KB, 0);
-      fp8_block<false, false>(ks + TB, vs + TB, qf, oacc, negm, m_run, l_run, lane, KB, sq, sk, sv);
+      fp8_block<false, false>(ks + TB, vs + TB, qf, ones, oacc, lacc, negm, m_run, lane, KB, sq, sk, sv);
       wait_vm_att<0>();
       __syncthreads();
     }
     if (nfull < nkb)  // ragged last block, already in LDS
-      fp8_block<true, false>(ks + (nfull & 1) * TB, vs + (nfull & 1) * TB, qf, oacc, negm, m_run, l_run, lane,
+      fp8_block<true, false>(ks + (nfull & 1) * TB, vs + (nfull & 1) * TB, qf, ones, oacc, lacc, negm, m_run, lane,
                              N - nfull * KB, sq, sk, sv);
   }
   // output through LDS in whole 64-dim rows (the tiles are free once every
   // wave is past its last block)
-  const float l_tot = xhalf_sum(l_run);
+  // the row sum of query l % 32 sits in register 0 of lane l % 32 (row 0 of
+  // the block); lanes 32..63 hold rows 4..7, all zero
+  const float l_tot = xhalf_sum(lane < 32 ? lacc[0] : 0.0f);
   const int ql = wave * 32 + (lane & 31);
   uint8_t* st = kv;
   __syncthreads();

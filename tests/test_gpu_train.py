@@ -143,3 +143,22 @@ def test_step_at_the_benchmark_frame_size():
     worst = _check_grads(grad, ref["grad"], arch, rtol=2e-5)
     print(f"256x192 depth: worst per-tensor gradient error {worst:.3g} of the tensor's max")
     _check_update(new, ref["params"], ref["grad"], ot.ADAM_LR)
+
+
+@pytest.mark.parametrize("C,k,T", [(3, 2, 1), (1, 4, 3)])
+def test_tubelet_variants_match_the_oracle(C, k, T):
+    """T = 1 (the head's target slot is the whole head, so its weight and
+    bias gradients share one chunk sum like every other layer) and T = 3 with
+    k + 1 = 5 frames padded to 6 with the oldest reference."""
+    from paper_2604_27441_amd import Trainer
+    arch = oracle.Arch(channels=C, k=k, tubelet=T, **TINY)
+    blob = synth.make_weights(13, tubelet=T, perturb_seed=14, **TINY)[0 if C == 3 else 1]
+    samples = synth.make_pretrain_batch(15, 2, 64, 80, C, k=k)
+    ref = ot.train_step(blob, samples, arch)
+    with Trainer(blob, C, 2, 64, 80, k=k, tubelet=T, **TINY) as tr:
+        loss = tr.step(*_dev(samples, C))
+        grad, new = tr.grads(), tr.weights()
+    assert abs(loss - ref["loss"]) <= 1e-5 * abs(ref["loss"])
+    worst = _check_grads(grad, ref["grad"], arch, rtol=2e-5)
+    print(f"C={C} k={k} T={T}: worst per-tensor gradient error {worst:.3g} of the tensor's max")
+    _check_update(new, ref["params"], ref["grad"], ot.ADAM_LR)
