@@ -853,11 +853,14 @@ int launch_t(const GemmArgs& a, hipStream_t s) {
     return -22;  // not reached: every BF16 dense product takes the ring
   } else {
     // the gather loader's per-row token coordinates leave no registers for a
-    // 128-wide tile with two prefetched stages; products with fewer 128-wide
-    // tiles than CUs (short token counts) take 64-wide tiles, twice as many
+    // 128-wide tile with two prefetched stages.  Dense products take 128-wide
+    // tiles unless 64-wide ones (twice as many, half the work each) spread
+    // better over the 256 CUs: the busiest CU then holds fewer feature columns
     const int nb = a.batch > 1 ? a.batch : 1;
     if constexpr (XM == X_DENSE) {
-      if (a.N % 128 == 0 && (long long)gm * (a.N / 128) * nb >= 256) {
+      const long long t128 = (long long)gm * (a.N / 128) * nb;
+      const bool wide = a.N % 128 == 0 && (2 * t128 + 255) / 256 >= 2 * ((t128 + 255) / 256);
+      if (wide) {
         gemm_kernel<Op, 128, EPI, XM, OutT><<<dim3(gm * (a.N / 128), nb), NT, 0, s>>>(a);
         return hipGetLastError() == hipSuccess ? 0 : -5;
       }
