@@ -75,7 +75,7 @@ Layout make_layout(int C, int T, int ne, int nd) {
 
 // saved activations of one Transformer block
 struct BlockAct {
-  float *xin, *a1, *q, *k, *vt, *lse, *o, *xmid, *a2, *h1;
+  float *xin, *a1, *q, *k, *vt, *lse, *o, *xmid, *a2, *h1, *g;  // g = GELU(h1), FC2's input
 };
 
 }  // namespace
@@ -95,7 +95,7 @@ struct revo_trainer {
   ReqDesc* d_reqs = nullptr;
   std::vector<ReqDesc> h_reqs;
   int *d_work_f = nullptr, *d_work_b = nullptr, *d_rowmap = nullptr;
-  float *U = nullptr, *xe = nullptr, *ae = nullptr, *zd = nullptr, *ahead = nullptr, *pred = nullptr, *G = nullptr;
+  float *U = nullptr, *xe = nullptr, *ae = nullptr, *zd = nullptr, *ahead = nullptr, *pred = nullptr;
   std::vector<BlockAct> act;  // ne encoder blocks, then nd decoder blocks
   float *dpred = nullptr, *dhead = nullptr, *dahead = nullptr, *xdy = nullptr, *dxe = nullptr, *dz = nullptr;
   float *dG = nullptr, *dH1 = nullptr, *da = nullptr, *dO = nullptr, *dqkv = nullptr;
@@ -202,9 +202,9 @@ int block_fwd(revo_trainer* t, const BlockL& b, BlockAct& A, float* x, int D, in
   f1.X = A.a2; f1.K = D; f1.N = 4 * D; f1.W = t->theta + b.fc1.w; f1.bias = t->theta + b.fc1.b; f1.out = A.h1;
   f1.ldo = 4 * D;
   if ((e = launch_gemm(P_FP32, EPI_STORE, X_DENSE, f1, s))) return e;
-  if ((e = launch_gelu_fwd(A.h1, t->G, (long long)t->Mpad * 4 * D, s))) return e;
+  if ((e = launch_gelu_fwd(A.h1, A.g, (long long)t->Mpad * 4 * D, s))) return e;
   GemmArgs f2 = g;
-  f2.X = t->G; f2.K = 4 * D; f2.N = D; f2.W = t->theta + b.fc2.w; f2.bias = t->theta + b.fc2.b; f2.out = x; f2.ldo = D;
+  f2.X = A.g; f2.K = 4 * D; f2.N = D; f2.W = t->theta + b.fc2.w; f2.bias = t->theta + b.fc2.b; f2.out = x; f2.ldo = D;
   return launch_gemm(P_FP32, EPI_RESIDUAL, X_DENSE, f2, s);
 }
 
@@ -215,8 +215,7 @@ int block_bwd(revo_trainer* t, const BlockL& b, const BlockAct& A, float* dx, in
   const int M = t->Mpad;
   // x_out = xmid + FC2(GELU(FC1(LN2(xmid))))
   if ((e = input_grad(t, dx, b.fc2, t->dG, M))) return e;                        // dG = dx W2
-  if ((e = launch_gelu_fwd(A.h1, t->G, (long long)M * 4 * D, s))) return e;      // G again
-  if ((e = weight_grad(t, dx, t->G, M, b.fc2, t->grad))) return e;
+  if ((e = weight_grad(t, dx, A.g, M, b.fc2, t->grad))) return e;
   if ((e = launch_gelu_bwd(t->dG, A.h1, t->dH1, (long long)M * 4 * D, s))) return e;
   if ((e = input_grad(t, t->dH1, b.fc1, t->da, M))) return e;                     // da2 = dH1 W1
   if ((e = weight_grad(t, t->dH1, A.a2, M, b.fc1, t->grad))) return e;
@@ -408,7 +407,7 @@ int setup(revo_trainer* t, const revo_train_config& c) {
   const size_t Mp = t->Mpad;
   if ((e = alloc_n(t, &t->U, Mp * t->Lt)) || (e = alloc_n(t, &t->xe, Mp * De)) || (e = alloc_n(t, &t->ae, Mp * De)) ||
       (e = alloc_n(t, &t->zd, Mp * Dd)) || (e = alloc_n(t, &t->ahead, (size_t)t->Mh_pad * Dd)) ||
-      (e = alloc_n(t, &t->pred, (size_t)t->B * t->H * t->W * t->C)) || (e = alloc_n(t, &t->G, Mp * 4 * De)))
+      (e = alloc_n(t, &t->pred, (size_t)t->B * t->H * t->W * t->C)))
     return e;
   t->act.resize(t->ne + t->nd);
   for (int i = 0; i < t->ne + t->nd; ++i) {
@@ -418,7 +417,7 @@ int setup(revo_trainer* t, const revo_train_config& c) {
         (e = alloc_n(t, &A.q, (size_t)heads * t->ld * 64)) || (e = alloc_n(t, &A.k, (size_t)heads * t->ld * 64)) ||
         (e = alloc_n(t, &A.vt, (size_t)heads * t->ld * 64)) || (e = alloc_n(t, &A.lse, (size_t)heads * t->ld)) ||
         (e = alloc_n(t, &A.o, Mp * D)) || (e = alloc_n(t, &A.xmid, Mp * D)) || (e = alloc_n(t, &A.a2, Mp * D)) ||
-        (e = alloc_n(t, &A.h1, Mp * 4 * D)))
+        (e = alloc_n(t, &A.h1, Mp * 4 * D)) || (e = alloc_n(t, &A.g, Mp * 4 * D)))
       return e;
   }
   const size_t Mx = Mp > (size_t)t->Mh_pad ? Mp : (size_t)t->Mh_pad;
