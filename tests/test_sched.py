@@ -37,8 +37,10 @@ def plan(tmp_path_factory):
                     'extern "C" double units(int n) { return revo::work_units(n); }\n'
                     'extern "C" int sizes(void) { return sizeof(revo::SchedJob) * 100 + sizeof(revo::SchedParams); }\n')
     lib = d / "libsched.so"
-    subprocess.run(["g++", "-O1", "-std=c++17", "-shared", "-fPIC", f"-I{CSRC}", str(shim),
-                    os.path.join(CSRC, "sched.cpp"), "-o", str(lib)], check=True)
+    # undefined-behaviour checks on (out-of-bounds shifts, signed overflow,
+    # bad indexes into fixed arrays): any report aborts the test process
+    subprocess.run(["g++", "-O1", "-std=c++17", "-shared", "-fPIC", "-fsanitize=undefined", "-fno-sanitize-recover=all",
+                    f"-I{CSRC}", str(shim), os.path.join(CSRC, "sched.cpp"), "-o", str(lib)], check=True)
     so = C.CDLL(str(lib))
     so.units.restype = C.c_double
     assert so.sizes() == C.sizeof(Job) * 100 + C.sizeof(Params)
