@@ -92,7 +92,7 @@ def test_ragged_sizes_fp32(H, W):
 
 
 @pytest.mark.parametrize("k,T,n_ref", [(5, 2, 2), (4, 2, None), (5, 3, None), (3, 1, None), (7, 2, 5), (7, 3, None),
-                                       (6, 3, 4)])
+                                       (6, 3, 4), (1, 2, None), (1, 1, None), (2, 3, None)])
 def test_history_and_tubelet_variants(k, T, n_ref):
     req = synth.make_request(41, 42, 48, 64, k=k, loss=("stripes", 0.5))
     out, ref = _small(FP32, req, k=k, T=T, n_ref=n_ref)
