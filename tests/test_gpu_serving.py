@@ -214,3 +214,34 @@ def test_input_copies_follow_the_callers_stream():
     g = _np(o)
     for key in ("rgb", "depth", "rgb_f", "depth_f"):
         assert np.array_equal(g[key], alone[key]), key
+
+
+def test_malformed_requests_are_refused_and_the_context_stays_usable():
+    """REVO_EINVAL at submit for a request with no frame, a mask without its
+    frame, a stream id past max_streams, a frame below 16 x 16, and host
+    memory passed as device pointers; none of them disturbs a later recovery."""
+    from paper_2604_27441_amd._lib import RevoError
+    blobs = synth.make_weights(3, **SMALL)
+    req = synth.make_request(85, 86, H, W, loss=("stripes", 0.5))
+    rgb, mask = dev(req["rgb"]), dev(req["mask_rgb"])
+    bad = [
+        dict(stream_id=0, width=W, height=H),                                          # no frame at all
+        dict(stream_id=0, width=W, height=H, mask_depth=mask),                         # mask without its frame
+        dict(stream_id=64, width=W, height=H, rgb=rgb, mask_rgb=mask),                 # stream id >= max_streams
+        dict(stream_id=0, width=15, height=H, rgb=rgb, mask_rgb=mask),                 # narrower than one patch
+        dict(stream_id=0, width=W, height=H, rgb=req["rgb"], mask_rgb=req["mask_rgb"]),  # host memory
+    ]
+    with _rec(blobs, max_streams=64) as rec:
+        push_refs(rec, 0, req)
+        for kw in bad:
+            sid, w_, h_ = kw.pop("stream_id"), kw.pop("width"), kw.pop("height")
+            with pytest.raises(RevoError) as e:
+                rec.submit(sid, int(req["t_target"]), w_, h_, device_ptrs=True, **kw)
+            assert e.value.code == -22, (kw.keys(), e.value.code)
+        o = _outs()
+        t = _submit(rec, 0, req, o)
+        c = rec.wait([t])[t]
+        assert c.status == 0
+        ref = oracle.recover(req, blobs, **SMALL)
+        g = _np(o)
+        assert np.abs(g["rgb_f"].astype(np.float64) - ref["rgb"][1]).max() <= 1e-4
