@@ -162,3 +162,26 @@ def test_tubelet_variants_match_the_oracle(C, k, T):
     worst = _check_grads(grad, ref["grad"], arch, rtol=2e-5)
     print(f"C={C} k={k} T={T}: worst per-tensor gradient error {worst:.3g} of the tensor's max")
     _check_update(new, ref["params"], ref["grad"], ot.ADAM_LR)
+
+
+def test_batch_gradient_is_the_mean_of_its_halves():
+    """At batch 16 (9216 token rows, past what the oracle can check in a
+    test), the loss is the batch mean, so the step's loss and gradient equal
+    the means of the two half batches' losses and gradients, each half run
+    on its own trainer from the same weights (FP32 summation order aside)."""
+    from paper_2604_27441_amd import Trainer
+    blob = synth.make_weights(17)[1]
+    samples = synth.make_pretrain_batch(40, 16, 192, 256, 1)
+    with Trainer(blob, 1, 16, 192, 256) as tr:
+        loss = tr.step(*_dev(samples, 1))
+        g = tr.grads().astype(np.float64)
+    parts = []
+    for half in (samples[:8], samples[8:]):
+        with Trainer(blob, 1, 8, 192, 256) as tr:
+            parts.append((tr.step(*_dev(half, 1)), tr.grads().astype(np.float64)))
+    want_loss = 0.5 * (parts[0][0] + parts[1][0])
+    want = 0.5 * (parts[0][1] + parts[1][1])
+    assert abs(loss - want_loss) <= 1e-5 * abs(want_loss), (loss, want_loss)
+    arch = oracle.Arch(channels=1)
+    worst = _check_grads(g.astype(np.float32), want, arch, rtol=1e-4)
+    print(f"batch 16 against the mean of its halves: worst per-tensor gradient error {worst:.3g} of the tensor's max")
