@@ -388,29 +388,6 @@ struct AttnBwdArgs {
   int nwork;
 };
 
-// Loads a 64 x 64 tile of a [rows][64] matrix (rows r0 .. r0+63, those at or
-// past rmax as zeros) into LDS [64][65].
-__device__ inline void load_rows(float (*t)[65], const float* __restrict__ src, int r0, int rmax) {
-  for (int i = threadIdx.x; i < 64 * 64; i += TB) {
-    const int r = i >> 6, c = i & 63;
-    t[r][c] = r0 + r < rmax ? src[(size_t)(r0 + r) * 64 + c] : 0.0f;
-  }
-}
-// V block from V^T [64][ld]: t[key][d] for keys c0 .. c0+63 below cmax
-__device__ inline void load_vt(float (*t)[65], const float* __restrict__ vt, int ld, int c0, int cmax) {
-  for (int i = threadIdx.x; i < 64 * 64; i += TB) {
-    const int d = i >> 6, c = i & 63;
-    t[c][d] = c0 + c < cmax ? vt[(size_t)d * ld + c0 + c] : 0.0f;
-  }
-}
-// dO block: t[row][d] from dout [M][heads 64] (head h)
-__device__ inline void load_dout(float (*t)[65], const float* __restrict__ dout, int heads, int h, int r0, int rmax) {
-  for (int i = threadIdx.x; i < 64 * 64; i += TB) {
-    const int r = i >> 6, c = i & 63;
-    t[r][c] = r0 + r < rmax ? dout[(size_t)(r0 + r) * heads * 64 + h * 64 + c] : 0.0f;
-  }
-}
-
 __device__ __forceinline__ f32x16 mfma_f32(float a, float b, const f32x16& c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
