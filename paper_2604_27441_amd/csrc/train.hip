@@ -293,7 +293,6 @@ __global__ __launch_bounds__(TB) void pretrain_loss_kernel(const float* __restri
   double acc = 0.0;
   for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB) {
     const long long f = i / per, r = i - f * per;
-    const int ch = (int)(r % C);
     const long long px = r / C;
     const int y = (int)(px / W), x = (int)(px - (long long)y * W);
     const float p = pred[i];
