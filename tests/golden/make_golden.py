@@ -7,6 +7,10 @@ weights from seed 0, k=5, T=2, 12 + 4 blocks, both modalities.
          BF16 batch (scene 1003, Gilbert-Elliott loss 20 %, burst 4).
   c3r1   tests/golden/c3_720p_request1_samples.json: request 1 of that batch
          (scene 1004, mask 2004).
+  s540   tests/golden/s540_bf16_samples.json: one 960x540 pair (6120 tokens;
+         the last patch row is 12 pixels high), 2 + 1 blocks with the perturbed
+         seed-3 weights (non-zero biases and gains), Gilbert-Elliott loss 30 %,
+         under the BF16-rounding oracle: the serving loop's 540p shape.
   c4fp8  tests/golden/c4_720p_fp8_samples.json: request 0 of the eight-request
          FP8 batch (scene 1007, loss 30 %), under the FP8-rounding oracle whose
          activation scales come from its own calibration pass (per-site absmax
@@ -19,7 +23,7 @@ the oracle's float output there, the rounding oracle's float output there
 (BF16 rounding for c3/c3r1, FP8 rounding for c4fp8), and full-frame error
 figures of the rounding oracle against the exact one.
 
-Run: python tests/golden/make_golden.py [c3|c3r1|c4fp8 ...]
+Run: python tests/golden/make_golden.py [c3|c3r1|s540|c4fp8 ...]
 (several minutes per 1280x720 forward on 8 cores; c4fp8 runs ten)
 """
 import json
@@ -91,6 +95,18 @@ def c3(index, path, seed):
     _write(path, _samples(req, exact, emu, seed, "oracle_bf16_rounding", wl))
 
 
+def s540(path, seed):
+    small = dict(enc_depth=2, dec_depth=1)
+    req = synth.make_request(501, 502, 540, 960, loss=("ge", 0.3))
+    blobs = synth.make_weights(3, perturb_seed=4, **small)
+    exact = _timed("fp64 oracle", lambda: oracle.recover(req, blobs, **small))
+    emu = _timed("bf16-rounding oracle", lambda: oracle.recover(req, blobs, rnd=oracle.Rounding(oracle.bf16_round),
+                                                                **small))
+    wl = ("960x540 pair: scene 501, mask 502, G-E loss 30% burst 4, weights synth.make_weights(3, perturb_seed=4), "
+          "k=5, T=2, 2+1 blocks")
+    _write(path, _samples(req, exact, emu, seed, "oracle_bf16_rounding", wl))
+
+
 def c4fp8(path, seed):
     req = synth.make_batch("c4", n=1)[0]
     blobs = synth.make_weights(0)
@@ -115,12 +131,14 @@ def c4fp8(path, seed):
 
 
 def main(argv):
-    jobs = argv or ["c3", "c3r1", "c4fp8"]
+    jobs = argv or ["c3", "c3r1", "s540", "c4fp8"]
     for j in jobs:
         if j == "c3":
             c3(0, os.path.join(HERE, "c3_720p_samples.json"), 424242)
         elif j == "c3r1":
             c3(1, os.path.join(HERE, "c3_720p_request1_samples.json"), 424243)
+        elif j == "s540":
+            s540(os.path.join(HERE, "s540_bf16_samples.json"), 424245)
         elif j == "c4fp8":
             c4fp8(os.path.join(HERE, "c4_720p_fp8_samples.json"), 424244)
         else:

@@ -124,6 +124,27 @@ def test_fullsize_fp8_samples():
     _within_rounding_budget(_sample_errors(g, out, "oracle_fp8_rounding"), "fp8 720p")
 
 
+def test_540p_bf16_samples():
+    """The serving loop's 960x540 shape in BF16 (6120 tokens, a 12-pixel last
+    patch row), 2 + 1 blocks, batched beside a 1280x720 request as the
+    serving loop mixes them, against sampled oracle outputs precomputed by
+    tests/golden/make_golden.py (s540)."""
+    from paper_2604_27441_amd import Recoverer
+    g = json.load(open(os.path.join(GOLDEN_DIR, "s540_bf16_samples.json")))
+    small = dict(enc_depth=2, dec_depth=1)
+    req = synth.make_request(501, 502, 540, 960, loss=("ge", 0.3))
+    other = synth.make_request(503, 504, 720, 1280, loss=("ge", 0.3))
+    blobs = synth.make_weights(3, perturb_seed=4, **small)
+    with Recoverer(blobs[0], blobs[1], precision=1, max_batch_tokens=6120 + 10800 + 64, max_batch=4, **small) as rec:
+        push_refs(rec, 0, req)
+        push_refs(rec, 1, other)
+        out, o2 = recover(rec, [(0, req), (1, other)])
+    assert out["completion"].status == 0 and o2["completion"].status == 0
+    check_received_and_codes(req, out)
+    check_received_and_codes(other, o2)
+    _within_rounding_budget(_sample_errors(g, out), "bf16 540p")
+
+
 def test_fullsize_batch_members_are_independent(c3):
     """Every request of the 720p batch equals the same request run alone."""
     from paper_2604_27441_amd import Recoverer
