@@ -108,35 +108,36 @@ __global__ __launch_bounds__(TB, 2) void wgrad_kernel(const WgradArgs a) {
   const int m0 = blockIdx.y * a.kc, m1 = min(a.rows, m0 + a.kc);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5, l32 = lane & 31;
   const int wo = wave >> 1, wi = wave & 1;
-  // loader: row tid / 16 of the stage, columns 8 (tid % 16) .. +7 of the
-  // tile.  Buffer loads: the descriptors end at the chunk's last row, so rows
-  // past it read as zeros without a branch.  Columns past the matrix (a
-  // partial last tile) read the next row or zeros; they only reach outputs
-  // and bias sums that are not stored.
-  const int lr = tid >> 4, lc = (tid & 15) * 8;
+  // loader: rows tid / 32 and tid / 32 + 8 of the stage, columns 4 (tid %
+  // 32) .. +3 of the tile, so the 32 lanes of a half-wave move 512
+  // contiguous bytes of one row (coalesced loads, conflict-free LDS stores).
+  // Buffer loads: the descriptors end at the chunk's last row, so rows past
+  // it read as zeros without a branch.  Columns past the matrix (a partial
+  // last tile) read the next row or zeros; they only reach outputs and bias
+  // sums that are not stored.
+  const int lr = tid >> 5, lc = (tid & 31) * 4;
   const __amdgpu_buffer_rsrc_t yrs =
       __builtin_amdgcn_make_buffer_rsrc((void*)a.dy, (short)0, m1 * a.ldy * (int)sizeof(float), 0x00020000);
   const __amdgpu_buffer_rsrc_t xrs =
       __builtin_amdgcn_make_buffer_rsrc((void*)a.x, (short)0, m1 * a.ldx * (int)sizeof(float), 0x00020000);
   const bool bias = a.bpart && i0 == 0;
   float4 ry[2], rx[2];
-  float bs[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  float bs[4] = {0.0f, 0.0f, 0.0f, 0.0f};
   auto fetch = [&](int r0) {
-    const int m = r0 + lr;
-    const int yo = (m * a.ldy + o0 + lc) * (int)sizeof(float), xo = (m * a.ldx + i0 + lc) * (int)sizeof(float);
-    ry[0] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(yrs, yo, 0, 0));
-    ry[1] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(yrs, yo + 16, 0, 0));
-    rx[0] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(xrs, xo, 0, 0));
-    rx[1] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(xrs, xo + 16, 0, 0));
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int m = r0 + lr + 8 * h;
+      const int yo = (m * a.ldy + o0 + lc) * (int)sizeof(float), xo = (m * a.ldx + i0 + lc) * (int)sizeof(float);
+      ry[h] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(yrs, yo, 0, 0));
+      rx[h] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(xrs, xo, 0, 0));
+    }
   };
   auto put = [&](int b) {
-    *reinterpret_cast<float4*>(&sy[b][lr][lc]) = ry[0];
-    *reinterpret_cast<float4*>(&sy[b][lr][lc + 4]) = ry[1];
-    *reinterpret_cast<float4*>(&sx[b][lr][lc]) = rx[0];
-    *reinterpret_cast<float4*>(&sx[b][lr][lc + 4]) = rx[1];
-    if (bias) {
-      bs[0] += ry[0].x; bs[1] += ry[0].y; bs[2] += ry[0].z; bs[3] += ry[0].w;
-      bs[4] += ry[1].x; bs[5] += ry[1].y; bs[6] += ry[1].z; bs[7] += ry[1].w;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      *reinterpret_cast<float4*>(&sy[b][lr + 8 * h][lc]) = ry[h];
+      *reinterpret_cast<float4*>(&sx[b][lr + 8 * h][lc]) = rx[h];
+      if (bias) { bs[0] += ry[h].x; bs[1] += ry[h].y; bs[2] += ry[h].z; bs[3] += ry[h].w; }
     }
   };
   f32x16 acc[2][2];
@@ -178,14 +179,15 @@ __global__ __launch_bounds__(TB, 2) void wgrad_kernel(const WgradArgs a) {
       }
     }
   if (bias) {
-    // the 16 loader rows' sums of each column, added in row order
-    float* red = &sx[0][0][0];  // [16][128]: free after the last barrier
+    // the 8 loader rows' sums of each column (rows r and r + 8 of every
+    // stage), added in row order
+    float* red = &sx[0][0][0];  // [8][128]: free after the last barrier
 #pragma unroll
-    for (int e = 0; e < 8; ++e) red[lr * 128 + lc + e] = bs[e];
+    for (int e = 0; e < 4; ++e) red[lr * 128 + lc + e] = bs[e];
     __syncthreads();
     if (tid < 128 && o0 + tid < a.nout) {
       float t = 0.0f;
-      for (int r = 0; r < R; ++r) t += red[r * 128 + tid];
+      for (int r = 0; r < 8; ++r) t += red[r * 128 + tid];
       a.bpart[(size_t)blockIdx.y * a.bstride + o0 + tid] = t;
     }
   }
