@@ -86,7 +86,7 @@ struct revo_trainer {
   int C = 3, T = 2, k = 5, ne = 12, nd = 4, B = 1, H = 0, W = 0;
   int J = 0, gy = 0, gx = 0, P = 0, N = 0, Nal = 0, nfr = 0, Lt = 0;
   int M = 0, Mpad = 0, Mh = 0, Mh_pad = 0, ld = 0;
-  int nwork_f = 0, nwork_b = 0, loss_blocks = 0, max_chunks = 0;
+  int nwork_f = 0, nwork_b = 0, loss_blocks = 0, max_chunks = 0, ln_blocks = 0;
   float lr = 2e-4f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f, alpha = 0.01f;
   long long step = 0;
   Layout L;
@@ -97,7 +97,7 @@ struct revo_trainer {
   int *d_work_f = nullptr, *d_work_b = nullptr, *d_rowmap = nullptr;
   float *U = nullptr, *xe = nullptr, *ae = nullptr, *zd = nullptr, *ahead = nullptr, *pred = nullptr;
   std::vector<BlockAct> act;  // ne encoder blocks, then nd decoder blocks
-  float *dpred = nullptr, *dhead = nullptr, *dahead = nullptr, *xdy = nullptr, *dxe = nullptr, *dz = nullptr;
+  float *dpred = nullptr, *dhead = nullptr, *dahead = nullptr, *lnpart = nullptr, *dxe = nullptr, *dz = nullptr;
   float *dG = nullptr, *dH1 = nullptr, *da = nullptr, *dO = nullptr, *dqkv = nullptr;
   float *part = nullptr, *dvec = nullptr, *splitk = nullptr;
   size_t splitk_elems = 0;
@@ -166,10 +166,8 @@ int input_grad(revo_trainer* t, const float* dy, const Lin& l, float* dx, int Mr
 // gain and shift gradients
 int ln_grad(revo_trainer* t, const float* x, size_t g_off, size_t b_off, const float* dy, float* dres, int rows, int D,
             const int* rowmap) {
-  int e;
-  if ((e = launch_ln_bwd(x, t->theta + g_off, dy, dres, t->xdy, rows, D, rowmap, t->s))) return e;
-  if ((e = launch_colsum(t->xdy, rows, D, D, t->part, t->max_chunks, t->grad + g_off, t->s))) return e;
-  return launch_colsum(dy, rows, D, D, t->part, t->max_chunks, t->grad + b_off, t->s);
+  if (b_off != g_off + (size_t)D) return -22;  // one sum writes both vectors
+  return launch_ln_bwd(x, t->theta + g_off, dy, dres, t->lnpart, t->ln_blocks, rows, D, rowmap, t->grad + g_off, t->s);
 }
 
 // forward of one block on the residual stream x (updated in place), saving
@@ -380,7 +378,7 @@ int setup(revo_trainer* t, const revo_train_config& c) {
   t->Mh_pad = align_up(t->Mh, 64);
   t->ld = t->Mpad + 64;
   t->loss_blocks = 256;
-  t->max_chunks = cdiv(t->Mpad > t->Mh_pad ? t->Mpad : t->Mh_pad, 64);  // 128-row column-sum chunks, 64-row dW chunks
+  t->max_chunks = cdiv(t->Mpad > t->Mh_pad ? t->Mpad : t->Mh_pad, 64);  // 64-row dW chunks
   const size_t n = t->L.count;
   if ((e = alloc_n(t, &t->theta, n)) || (e = alloc_n(t, &t->grad, n)) || (e = alloc_n(t, &t->mom, n)) ||
       (e = alloc_n(t, &t->vel, n)) || (e = alloc_n(t, &t->wT, n)) || (e = alloc_n(t, &t->zero, 4096)))
@@ -421,10 +419,11 @@ int setup(revo_trainer* t, const revo_train_config& c) {
       return e;
   }
   const size_t Mx = Mp > (size_t)t->Mh_pad ? Mp : (size_t)t->Mh_pad;
+  t->ln_blocks = ln_bwd_blocks((int)Mx);
   const size_t widest = (size_t)(t->Lt > 4 * De ? t->Lt : 4 * De);
   if ((e = alloc_n(t, &t->dpred, (size_t)t->B * t->H * t->W * t->C)) ||
       (e = alloc_n(t, &t->dhead, (size_t)t->Mh_pad * 256 * t->C)) || (e = alloc_n(t, &t->dahead, (size_t)t->Mh_pad * Dd)) ||
-      (e = alloc_n(t, &t->xdy, Mx * De)) || (e = alloc_n(t, &t->dxe, Mp * De)) || (e = alloc_n(t, &t->dz, Mp * Dd)) ||
+      (e = alloc_n(t, &t->lnpart, (size_t)t->ln_blocks * 2 * 512)) || (e = alloc_n(t, &t->dxe, Mp * De)) || (e = alloc_n(t, &t->dz, Mp * Dd)) ||
       (e = alloc_n(t, &t->dG, Mp * 4 * De)) || (e = alloc_n(t, &t->dH1, Mp * 4 * De)) || (e = alloc_n(t, &t->da, Mp * De)) ||
       (e = alloc_n(t, &t->dO, Mp * De)) || (e = alloc_n(t, &t->dqkv, Mp * 3 * De)) ||
       (e = alloc_n(t, &t->part, (size_t)t->max_chunks * widest)) || (e = alloc_n(t, &t->dvec, (size_t)6 * t->ld)) ||

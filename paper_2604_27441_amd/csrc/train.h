@@ -8,9 +8,6 @@ namespace revo {
 int launch_transpose(const float* in, float* out, int rows, int cols, int ld_in, int ld_out, hipStream_t s);
 // out[i] = sum_b part[b n + i] for b = 0 .. nb-1 in order.
 int launch_sum_chunks(const float* part, int nb, long long n, float* out, hipStream_t s);
-// out[c] = sum over rows of x[r][c] (fixed order: 128-row chunks, then the
-// chunks); part holds max_chunks x cols floats.
-int launch_colsum(const float* x, int rows, int cols, int ld, float* part, int max_chunks, float* out, hipStream_t s);
 // Weight-gradient chunks: part[c pstride + o nin + i] = sum over rows m of
 // chunk c (rows c kc .. c kc + kc - 1 below rows) of dy[m][o] x[m][i]; with
 // bpart, also bpart[c bstride + o] = the chunk's sum of dy[m][o].  Column
@@ -20,10 +17,14 @@ int launch_wgrad(const float* dy, const float* x, int rows, int nout, int nin, i
                  float* part, long long pstride, float* bpart, long long bstride, hipStream_t s);
 int launch_gelu_fwd(const float* h, float* g, long long n, hipStream_t s);
 int launch_gelu_bwd(const float* dg, const float* h, float* dh, long long n, hipStream_t s);
-// LayerNorm backward (y = LN(x) g + b, eps 1e-6): dres[row] += dL/dx,
-// xdy = xhat * dy; with rowmap, dy row i belongs to x / dres row rowmap[i].
-int launch_ln_bwd(const float* x, const float* g, const float* dy, float* dres, float* xdy, int rows, int D,
-                  const int* rowmap, hipStream_t s);
+// LayerNorm backward (y = LN(x) g + b, eps 1e-6) of rows [0, rows):
+// dres[row] += dL/dx, gb[0, D) = the gain gradient and gb[D, 2D) the shift
+// gradient (column sums over the rows; zeros for rows == 0).  part holds
+// ln_bwd_blocks(rows) <= max_blocks partial rows of 2D floats.  With rowmap,
+// dy row i belongs to x / dres row rowmap[i].
+int ln_bwd_blocks(int rows);
+int launch_ln_bwd(const float* x, const float* g, const float* dy, float* dres, float* part, int max_blocks, int rows,
+                  int D, const int* rowmap, float* gb, hipStream_t s);
 // Batch loss mean_b [MSE + alpha TV(pred)] and its gradient dpred; part
 // receives nblocks partial sums of the loss.
 int launch_pretrain_loss(const float* pred, const void* gt, int B, int H, int W, int C, float alpha, float* dpred,

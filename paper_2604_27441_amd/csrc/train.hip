@@ -50,31 +50,24 @@ __global__ __launch_bounds__(TB) void sum_chunks_kernel(const float* __restrict_
   }
 }
 
-// Partial column sums of x [rows][cols] over chunks of `chunk` rows:
-// part[blockIdx.y][c].  64 columns x 4 row lanes per block.
-__global__ __launch_bounds__(TB) void colsum_part_kernel(const float* __restrict__ x, int rows, int cols, int ld,
-                                                         int chunk, float* __restrict__ part) {
-  __shared__ float red[4][64];
-  const int c = blockIdx.x * 64 + (threadIdx.x & 63), lane_r = threadIdx.x >> 6;
-  const int r0 = blockIdx.y * chunk, r1 = min(rows, r0 + chunk);
-  float s = 0.0f;
-  if (c < cols)
-    for (int r = r0 + lane_r; r < r1; r += 4) s += x[(size_t)r * ld + c];
-  red[lane_r][threadIdx.x & 63] = s;
-  __syncthreads();
-  if (lane_r == 0 && c < cols)
-    part[(size_t)blockIdx.y * cols + c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
-}
-
-// out[c] = sum of the chunk partials: 64 columns x 4 lanes per block, lane
-// l taking chunks l, l + 4, ..., then the four lanes in order
+// out[c] = sum of the block partials: 64 columns x 4 lanes per block, lane
+// l taking blocks l, l + 4, ... in groups of 8 (added as a pairwise tree,
+// the groups in order; eight loads in flight), then the four lanes in order
 __global__ __launch_bounds__(TB) void colsum_final_kernel(const float* __restrict__ part, int nchunk, int cols,
                                                           float* __restrict__ out) {
   __shared__ float red[4][64];
   const int c = blockIdx.x * 64 + (threadIdx.x & 63), l = threadIdx.x >> 6;
   float s = 0.0f;
-  if (c < cols)
-    for (int i = l; i < nchunk; i += 4) s += part[(size_t)i * cols + c];
+  if (c < cols) {
+    int i = l;
+    for (; i + 28 < nchunk; i += 32) {
+      float t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = part[(size_t)(i + 4 * u) * cols + c];
+      s += ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+    }
+    for (; i < nchunk; i += 4) s += part[(size_t)i * cols + c];
+  }
   red[l][threadIdx.x & 63] = s;
   __syncthreads();
   if (l == 0 && c < cols)
@@ -215,63 +208,84 @@ __global__ __launch_bounds__(TB) void gelu_bwd_kernel(const float* __restrict__ 
 
 // ---- LayerNorm backward -------------------------------------------------------------
 //
-// y = xhat g + b with xhat = (x - mean) rstd.  One wave per row:
-// dx = rstd (dy g - mean(dy g) - xhat mean(dy g xhat)), added into dres;
-// xdy = xhat dy for the gain gradient (its column sums).  With rowmap, row
-// i of dy / xdy belongs to row rowmap[i] of x and dres.
-__global__ __launch_bounds__(TB) void ln_bwd_kernel(const float* __restrict__ x, const float* __restrict__ g,
-                                                    const float* __restrict__ dy, float* __restrict__ dres,
-                                                    float* __restrict__ xdy, int rows, int D,
-                                                    const int* __restrict__ rowmap) {
-  const int wave = (blockIdx.x * TB + threadIdx.x) >> 6, lane = threadIdx.x & 63;
-  if (wave >= rows) return;
-  const int xr = rowmap ? rowmap[wave] : wave;
-  const float* xp = x + (size_t)xr * D;
-  const float* dp = dy + (size_t)wave * D;
+// y = xhat g + b with xhat = (x - mean) rstd.  One wave per row, 16 waves
+// per block: dx = rstd (dy g - mean(dy g) - xhat mean(dy g xhat)), added
+// into dres.  The gain and shift gradients are column sums over the rows of
+// xhat dy and dy: each block writes its 16 rows' sums (in row order),
+// part[block][d] (gain) and part[block][D + d] (shift), which
+// colsum_final_kernel then adds over the blocks in order.  With rowmap, row i
+// of dy belongs to row rowmap[i] of x and dres.
+constexpr int LN_WAVES = 16, LN_TB = 64 * LN_WAVES;
+__global__ __launch_bounds__(LN_TB) void ln_bwd_kernel(const float* __restrict__ x, const float* __restrict__ g,
+                                                       const float* __restrict__ dy, float* __restrict__ dres,
+                                                       float* __restrict__ part, int rows, int D,
+                                                       const int* __restrict__ rowmap) {
   constexpr int MAXE = 8;  // D <= 512
-  float xv[MAXE], gv[MAXE];
-  float s = 0.0f;
+  __shared__ float red[LN_WAVES][64 * MAXE];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = blockIdx.x * LN_WAVES + wave;
+  float pg[MAXE], pb[MAXE];  // this row's xhat dy and dy (zeros past the rows)
 #pragma unroll
-  for (int e = 0; e < MAXE; ++e) {
-    const int d = lane + 64 * e;
-    xv[e] = d < D ? xp[d] : 0.0f;
-    s += xv[e];
-  }
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  const float mean = s / D;
-  float v = 0.0f;
+  for (int e = 0; e < MAXE; ++e) { pg[e] = 0.0f; pb[e] = 0.0f; }
+  if (row < rows) {
+    const int xr = rowmap ? rowmap[row] : row;
+    const float* xp = x + (size_t)xr * D;
+    const float* dp = dy + (size_t)row * D;
+    float xv[MAXE], gv[MAXE];
+    float s = 0.0f;
 #pragma unroll
-  for (int e = 0; e < MAXE; ++e) {
-    const int d = lane + 64 * e;
-    const float c = d < D ? xv[e] - mean : 0.0f;
-    v += c * c;
-  }
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  const float rstd = 1.0f / sqrtf(v / D + 1e-6f);
-  float s1 = 0.0f, s2 = 0.0f;
+    for (int e = 0; e < MAXE; ++e) {
+      const int d = lane + 64 * e;
+      xv[e] = d < D ? xp[d] : 0.0f;
+      pb[e] = d < D ? dp[d] : 0.0f;
+      s += xv[e];
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    const float mean = s / D;
+    float v = 0.0f;
 #pragma unroll
-  for (int e = 0; e < MAXE; ++e) {
-    const int d = lane + 64 * e;
-    if (d < D) {
-      const float xh = (xv[e] - mean) * rstd;
-      const float dyv = dp[d];
-      gv[e] = dyv * g[d];
+    for (int e = 0; e < MAXE; ++e) {
+      const int d = lane + 64 * e;
+      const float c = d < D ? xv[e] - mean : 0.0f;
+      v += c * c;
+    }
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const float rstd = 1.0f / sqrtf(v / D + 1e-6f);
+    float s1 = 0.0f, s2 = 0.0f;
+#pragma unroll
+    for (int e = 0; e < MAXE; ++e) {
+      const int d = lane + 64 * e;
+      const float xh = d < D ? (xv[e] - mean) * rstd : 0.0f;
+      gv[e] = d < D ? pb[e] * g[d] : 0.0f;
       s1 += gv[e];
       s2 += gv[e] * xh;
-      xdy[(size_t)wave * D + d] = xh * dyv;
+      pg[e] = xh * pb[e];
       xv[e] = xh;
     }
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    s1 += __shfl_xor(s1, o);
-    s2 += __shfl_xor(s2, o);
-  }
-  const float m1 = s1 / D, m2 = s2 / D;
-  float* rp = dres + (size_t)xr * D;
+    for (int o = 32; o > 0; o >>= 1) {
+      s1 += __shfl_xor(s1, o);
+      s2 += __shfl_xor(s2, o);
+    }
+    const float m1 = s1 / D, m2 = s2 / D;
+    float* rp = dres + (size_t)xr * D;
 #pragma unroll
-  for (int e = 0; e < MAXE; ++e) {
-    const int d = lane + 64 * e;
-    if (d < D) rp[d] += rstd * (gv[e] - m1 - xv[e] * m2);
+    for (int e = 0; e < MAXE; ++e) {
+      const int d = lane + 64 * e;
+      if (d < D) rp[d] += rstd * (gv[e] - m1 - xv[e] * m2);
+    }
+  }
+  float* out = part + (size_t)blockIdx.x * 2 * D;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    if (k) __syncthreads();  // the gain sums have been read
+#pragma unroll
+    for (int e = 0; e < MAXE; ++e) red[wave][lane + 64 * e] = k ? pb[e] : pg[e];
+    __syncthreads();
+    for (int c = threadIdx.x; c < D; c += LN_TB) {
+      float t = 0.0f;
+      for (int w = 0; w < LN_WAVES; ++w) t += red[w][c];
+      out[k * D + c] = t;
+    }
   }
 }
 
@@ -648,17 +662,6 @@ int launch_sum_chunks(const float* part, int nb, long long n, float* out, hipStr
   return last();
 }
 
-int launch_colsum(const float* x, int rows, int cols, int ld, float* part, int max_chunks, float* out, hipStream_t s) {
-  if (cols <= 0) return 0;
-  const int chunk = 128;
-  const int nchunk = rows > 0 ? cdiv(rows, chunk) : 1;
-  if (nchunk > max_chunks) return -22;
-  colsum_part_kernel<<<dim3(cdiv(cols, 64), nchunk), TB, 0, s>>>(x, rows, cols, ld, chunk, part);
-  if (int e = last()) return e;
-  colsum_final_kernel<<<cdiv(cols, 64), TB, 0, s>>>(part, nchunk, cols, out);
-  return last();
-}
-
 int launch_wgrad(const float* dy, const float* x, int rows, int nout, int nin, int ldy, int ldx, int kc, int nchunk,
                  float* part, long long pstride, float* bpart, long long bstride, hipStream_t s) {
   // buffer-load byte offsets are 32-bit
@@ -685,11 +688,16 @@ int launch_gelu_bwd(const float* dg, const float* h, float* dh, long long n, hip
   return last();
 }
 
-int launch_ln_bwd(const float* x, const float* g, const float* dy, float* dres, float* xdy, int rows, int D,
-                  const int* rowmap, hipStream_t s) {
-  if (D > 512 || rows < 0) return -22;
-  if (rows == 0) return 0;
-  ln_bwd_kernel<<<cdiv(rows, TB / 64), TB, 0, s>>>(x, g, dy, dres, xdy, rows, D, rowmap);
+int ln_bwd_blocks(int rows) { return rows > 0 ? cdiv(rows, LN_WAVES) : 1; }
+
+int launch_ln_bwd(const float* x, const float* g, const float* dy, float* dres, float* part, int max_blocks, int rows,
+                  int D, const int* rowmap, float* gb, hipStream_t s) {
+  if (D <= 0 || D > 512 || rows < 0) return -22;
+  const int nblk = ln_bwd_blocks(rows);
+  if (nblk > max_blocks) return -22;
+  ln_bwd_kernel<<<nblk, LN_TB, 0, s>>>(x, g, dy, dres, part, rows, D, rowmap);
+  if (int e = last()) return e;
+  colsum_final_kernel<<<cdiv(2 * D, 64), TB, 0, s>>>(part, nblk, 2 * D, gb);
   return last();
 }
 
