@@ -222,9 +222,10 @@ int block_bwd(revo_trainer* t, const BlockL& b, const BlockAct& A, float* dx, in
   if ((e = input_grad(t, dx, b.proj, t->dO, M))) return e;
   if ((e = weight_grad(t, dx, A.o, M, b.proj, t->grad))) return e;
   // the attention backward writes the rows of the batch's tokens only; the
-  // alignment gaps between requests must read as zero gradient (the buffer
-  // is shared by the encoder and decoder widths)
-  if (hipMemsetAsync(t->dqkv, 0, (size_t)M * 3 * D * 4, s) != hipSuccess) return REVO_EDEVICE;
+  // alignment gaps between requests and past the last one, if any, must read
+  // as zero gradient (the buffer is shared by the encoder and decoder widths)
+  if (t->Nal != t->N || t->M != M)
+    if (hipMemsetAsync(t->dqkv, 0, (size_t)M * 3 * D * 4, s) != hipSuccess) return REVO_EDEVICE;
   if ((e = launch_attention_bwd(A.q, A.k, A.vt, A.o, t->dO, A.lse, t->dvec, t->dqkv, M, heads, t->ld, t->d_reqs,
                                 t->d_work_b, t->nwork_b, s)))
     return e;
