@@ -101,6 +101,9 @@ struct revo_trainer {
   float *dG = nullptr, *dH1 = nullptr, *da = nullptr, *dO = nullptr, *dqkv = nullptr;
   float *part = nullptr, *dvec = nullptr, *splitk = nullptr;
   size_t splitk_elems = 0;
+  TrDesc* d_tr = nullptr;  // the weight transposes of a step
+  int ntr = 0;
+  long long tr_tiles = 0;
   double* loss_part = nullptr;
   std::vector<double> h_loss_part;
 };
@@ -234,20 +237,36 @@ int block_bwd(revo_trainer* t, const BlockL& b, const BlockAct& A, float* dx, in
   return ln_grad(t, A.xin, b.ln1g, b.ln1b, t->da, dx, M, D, nullptr);
 }
 
+// the transposed weights the dX products read (every layer but the
+// embedding, whose input gradient is not needed): one launch per step
 int transpose_weights(revo_trainer* t) {
-  int e;
-  auto tr = [&](const Lin& l) { return launch_transpose(t->theta + l.w, t->wT + l.w, l.out, l.in, l.in, l.out, t->s); };
-  if ((e = tr(t->L.emb)) || (e = tr(t->L.e2d))) return e;
+  return launch_transpose_batch(t->d_tr, t->ntr, t->tr_tiles, t->s);
+}
+
+int plan_transposes(revo_trainer* t) {
+  std::vector<TrDesc> d;
+  auto add = [&](size_t off, int rows, int cols) {
+    TrDesc x;
+    x.in = t->theta + off; x.out = t->wT + off;
+    x.rows = rows; x.cols = cols; x.ld_in = cols; x.ld_out = rows; x.tile0 = 0;
+    d.push_back(x);
+  };
+  auto lin = [&](const Lin& l) { add(l.w, l.out, l.in); };
+  lin(t->L.e2d);
   // head: only the target time slot's rows take part; their transpose
   // [Dd][256 C] sits at the slot block's own offset
-  const size_t slot = (size_t)(t->T - 1) * 256 * t->C * t->L.head.in;
-  if ((e = launch_transpose(t->theta + t->L.head.w + slot, t->wT + t->L.head.w + slot, 256 * t->C, t->L.head.in,
-                            t->L.head.in, 256 * t->C, t->s)))
-    return e;
+  add(t->L.head.w + (size_t)(t->T - 1) * 256 * t->C * t->L.head.in, 256 * t->C, t->L.head.in);
   for (auto* v : {&t->L.enc, &t->L.dec})
-    for (const BlockL& b : *v)
-      if ((e = tr(b.qkv)) || (e = tr(b.proj)) || (e = tr(b.fc1)) || (e = tr(b.fc2))) return e;
-  return 0;
+    for (const BlockL& b : *v) {
+      lin(b.qkv); lin(b.proj); lin(b.fc1); lin(b.fc2);
+    }
+  t->tr_tiles = transpose_plan(d.data(), (int)d.size());
+  t->ntr = (int)d.size();
+  if (int e = alloc_n(t, &t->d_tr, d.size())) return e;
+  // on the trainer's stream, after the allocation's clearing; d is local
+  if (hipMemcpyAsync(t->d_tr, d.data(), d.size() * sizeof(TrDesc), hipMemcpyHostToDevice, t->s) != hipSuccess)
+    return REVO_EDEVICE;
+  return hipStreamSynchronize(t->s) == hipSuccess ? 0 : REVO_EDEVICE;
 }
 
 int run_step(revo_trainer* t, const revo_train_batch* bt, double* loss_out) {
@@ -384,7 +403,9 @@ int setup(revo_trainer* t, const revo_train_config& c) {
   if ((e = alloc_n(t, &t->theta, n)) || (e = alloc_n(t, &t->grad, n)) || (e = alloc_n(t, &t->mom, n)) ||
       (e = alloc_n(t, &t->vel, n)) || (e = alloc_n(t, &t->wT, n)) || (e = alloc_n(t, &t->zero, 4096)))
     return e;
-  if (hipMemcpy(t->theta, c.weights, n * 4, hipMemcpyHostToDevice) != hipSuccess) return REVO_EDEVICE;
+  // uploads go on the trainer's stream (non-blocking), behind the clearing
+  // of the buffers they fill; the end of set-up synchronizes it
+  if (hipMemcpyAsync(t->theta, c.weights, n * 4, hipMemcpyHostToDevice, t->s) != hipSuccess) return REVO_EDEVICE;
   if ((e = alloc_n(t, &t->d_reqs, t->B))) return e;
   t->h_reqs.resize(t->B);
   // work lists: 128-query tiles (forward attention), 64-row blocks (backward)
@@ -399,9 +420,10 @@ int setup(revo_trainer* t, const revo_train_config& c) {
   if ((e = alloc_n(t, &t->d_work_f, wf.size())) || (e = alloc_n(t, &t->d_work_b, wb.size())) ||
       (e = alloc_n(t, &t->d_rowmap, rowmap.size())))
     return e;
-  if (hipMemcpy(t->d_work_f, wf.data(), wf.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(t->d_work_b, wb.data(), wb.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(t->d_rowmap, rowmap.data(), rowmap.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+  if (hipMemcpyAsync(t->d_work_f, wf.data(), wf.size() * 4, hipMemcpyHostToDevice, t->s) != hipSuccess ||
+      hipMemcpyAsync(t->d_work_b, wb.data(), wb.size() * 4, hipMemcpyHostToDevice, t->s) != hipSuccess ||
+      hipMemcpyAsync(t->d_rowmap, rowmap.data(), rowmap.size() * 4, hipMemcpyHostToDevice, t->s) != hipSuccess ||
+      hipStreamSynchronize(t->s) != hipSuccess)
     return REVO_EDEVICE;
   const size_t Mp = t->Mpad;
   if ((e = alloc_n(t, &t->U, Mp * t->Lt)) || (e = alloc_n(t, &t->xe, Mp * De)) || (e = alloc_n(t, &t->ae, Mp * De)) ||
@@ -434,6 +456,7 @@ int setup(revo_trainer* t, const revo_train_config& c) {
   t->splitk_elems = (size_t)512 * 128 * 128 + (size_t)64 * 1536 * 64;
   if ((e = alloc_n(t, &t->splitk, t->splitk_elems))) return e;
   t->h_loss_part.assign(t->loss_blocks, 0.0);
+  if ((e = plan_transposes(t))) return e;
   return hipStreamSynchronize(t->s) == hipSuccess ? 0 : REVO_EDEVICE;
 }
 
@@ -489,7 +512,8 @@ int revo_train_step(revo_trainer* t, const revo_train_batch* b, double* loss) {
 static int copy_out(revo_trainer* t, const float* src, float* out, size_t n, size_t have) {
   if (!t || !out || n != have) return REVO_EINVAL;
   if (hipSetDevice(t->dev) != hipSuccess) return REVO_EDEVICE;
-  if (hipMemcpy(out, src, n * 4, hipMemcpyDeviceToHost) != hipSuccess) return REVO_EDEVICE;
+  if (hipStreamSynchronize(t->s) != hipSuccess || hipMemcpy(out, src, n * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return REVO_EDEVICE;
   return 0;
 }
 

@@ -4,8 +4,19 @@
 
 namespace revo {
 
-// out[c][r] = in[r][c] for r < rows, c < cols.
-int launch_transpose(const float* in, float* out, int rows, int cols, int ld_in, int ld_out, hipStream_t s);
+// One block of a batched transpose: out[c][r] = in[r][c] for r < rows,
+// c < cols (row pitches ld_in, ld_out); its 64 x 64 tiles are numbers
+// tile0 .. tile0 + cdiv(rows, 64) cdiv(cols, 64) - 1 of the launch.
+struct TrDesc {
+  const float* in;
+  float* out;
+  int rows, cols, ld_in, ld_out, tile0;
+};
+// Fills tile0 of the n descriptors and returns the launch's tile count.
+long long transpose_plan(TrDesc* d, int n);
+// Every listed transpose in one launch (d: n device-resident descriptors
+// in tile0 order, tiles their total).
+int launch_transpose_batch(const TrDesc* d, int n, long long tiles, hipStream_t s);
 // out[i] = sum_b part[b n + i] for b = 0 .. nb-1 in order.
 int launch_sum_chunks(const float* part, int nb, long long n, float* out, hipStream_t s);
 // Weight-gradient chunks: part[c pstride + o nin + i] = sum over rows m of

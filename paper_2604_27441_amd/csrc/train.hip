@@ -23,20 +23,30 @@ __device__ inline float erf_as_t(float x) {
 
 // ---- transposes and column sums ---------------------------------------------
 
-// out[c][r] = in[r][c] for a rows x cols block (row pitches ld_in, ld_out)
-__global__ __launch_bounds__(TB) void transpose_kernel(const float* __restrict__ in, float* __restrict__ out, int rows,
-                                                       int cols, int ld_in, int ld_out) {
+// out[c][r] = in[r][c] for every block of the list, one 64 x 64 tile per
+// workgroup: the descriptor is the last one whose first tile is at or below
+// the workgroup's (a binary search over the list)
+__global__ __launch_bounds__(TB) void transpose_batch_kernel(const TrDesc* __restrict__ list, int n) {
   __shared__ float t[64][65];
-  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+  const int tile = blockIdx.x;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (list[mid].tile0 <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  const TrDesc d = list[lo];
+  const int tc = (d.cols + 63) / 64, tl = tile - d.tile0;
+  const int r0 = (tl / tc) * 64, c0 = (tl - (tl / tc) * tc) * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   for (int i = ty; i < 64; i += 4) {
     const int r = r0 + i, c = c0 + tx;
-    t[i][tx] = (r < rows && c < cols) ? in[(size_t)r * ld_in + c] : 0.0f;
+    t[i][tx] = (r < d.rows && c < d.cols) ? d.in[(size_t)r * d.ld_in + c] : 0.0f;
   }
   __syncthreads();
   for (int i = ty; i < 64; i += 4) {
     const int c = c0 + i, r = r0 + tx;
-    if (c < cols && r < rows) out[(size_t)c * ld_out + r] = t[tx][i];
+    if (c < d.cols && r < d.rows) d.out[(size_t)c * d.ld_out + r] = t[tx][i];
   }
 }
 
@@ -684,9 +694,19 @@ int last() { return hipGetLastError() == hipSuccess ? 0 : -5; }
 
 }  // namespace
 
-int launch_transpose(const float* in, float* out, int rows, int cols, int ld_in, int ld_out, hipStream_t s) {
-  if (rows <= 0 || cols <= 0) return 0;
-  transpose_kernel<<<dim3(cdiv(cols, 64), cdiv(rows, 64)), TB, 0, s>>>(in, out, rows, cols, ld_in, ld_out);
+long long transpose_plan(TrDesc* d, int n) {
+  long long tiles = 0;
+  for (int i = 0; i < n; ++i) {
+    d[i].tile0 = (int)tiles;
+    tiles += (long long)cdiv(d[i].rows, 64) * cdiv(d[i].cols, 64);
+  }
+  return tiles;
+}
+
+int launch_transpose_batch(const TrDesc* d, int n, long long tiles, hipStream_t s) {
+  if (n <= 0 || tiles <= 0) return 0;
+  if (tiles > (1LL << 31) - 1) return -22;
+  transpose_batch_kernel<<<(unsigned)tiles, TB, 0, s>>>(d, n);
   return last();
 }
 
