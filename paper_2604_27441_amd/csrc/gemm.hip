@@ -69,6 +69,11 @@ __device__ inline float erf_as(float x) {
 }
 
 __device__ inline float gelu_erf(float v) { return 0.5f * v * (1.0f + erf_as(v * 0.70710678118654752f)); }
+// d gelu / dv = Phi(v) + v phi(v)
+__device__ inline float gelu_erf_grad(float v) {
+  return 0.5f * (1.0f + erf_as(v * 0.70710678118654752f)) +
+         v * 0.3989422804014327f * __builtin_amdgcn_exp2f(-0.5f * v * v * 1.4426950408889634f);
+}
 
 // sin (odd == 0) or cos (odd == 1) of x for |x| up to a few thousand, without
 // scratch memory: x = n (pi/2) + r with a three-part Cody-Waite reduction,
@@ -272,7 +277,7 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[B
           Vec4<OutT>::store((OutT*)a.out + (size_t)m * a.ldo + n, v, oinv);
         } else if (EPI == EPI_RESIDUAL) {
           float* p = (float*)a.out + (size_t)m * a.ldo + n;
-          f32x4 old = *reinterpret_cast<f32x4*>(p);
+          f32x4 old = *reinterpret_cast<const f32x4*>(a.res ? a.res + (size_t)m * a.ldo + n : p);
           *reinterpret_cast<f32x4*>(p) = f32x4{old[0] + v[0], old[1] + v[1], old[2] + v[2], old[3] + v[3]};
         } else if (EPI == EPI_PE) {
           const ReqDesc& d = a.reqs[r];
@@ -434,20 +439,56 @@ __device__ __forceinline__ void gemm_epilogue_staged(const GemmArgs& a, f32x16 (
     return;
   }
   constexpr int CPRO = BN / EO;
+  if constexpr (EPI == EPI_GELU_PRE || EPI == EPI_GELU_BWD) {
+    static_assert(sizeof(OutT) == 4, "FP32 outputs");
+    static_assert(BM_ * CPRO % NT_ == 0, "whole chunks per thread");
+    constexpr int IT = BM_ * CPRO / NT_;
+    // EPI_GELU_BWD: every pre-activation chunk of this thread is loaded
+    // before the first store
+    f32x4 pv[EPI == EPI_GELU_BWD ? IT : 1];
+    if constexpr (EPI == EPI_GELU_BWD) {
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int i = tid + it * NT_;
+        const int rl = i / CPRO, c = (i - rl * CPRO) * EO;
+        const int m = m0 + rl;
+        pv[it] = m < Mlive ? *reinterpret_cast<const f32x4*>(a.pre + (size_t)m * a.ldo + n0 + c) : f32x4{};
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int i = tid + it * NT_;
+      const int rl = i / CPRO, c = (i - rl * CPRO) * EO;
+      const int m = m0 + rl;
+      if (m >= Mlive) continue;
+      const f32x4 v = *reinterpret_cast<const f32x4*>(smem + rl * TPB + c * (int)sizeof(OutT));
+      f32x4 r;
+      if constexpr (EPI == EPI_GELU_PRE) {
+        *reinterpret_cast<f32x4*>(a.pre + (size_t)m * a.ldo + n0 + c) = v;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) r[e] = gelu_erf(v[e]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) r[e] = v[e] * gelu_erf_grad(pv[it][e]);
+      }
+      *reinterpret_cast<f32x4*>((float*)a.out + (size_t)m * a.ldo + n0 + c) = r;
+    }
+    return;
+  }
   if constexpr (EPI == EPI_RESIDUAL) {
     // every residual chunk of this thread is loaded before the first add and
     // store (a load after a store to the same buffer would otherwise wait
     // out one memory round trip per chunk)
     static_assert(BM_ * CPRO % NT_ == 0, "whole chunks per thread");
     constexpr int IT = BM_ * CPRO / NT_;
+    const float* rsrc = a.res ? a.res : (const float*)a.out;
     f32x4 res[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int i = tid + it * NT_;
       const int rl = i / CPRO, c = (i - rl * CPRO) * EO;
       const int m = m0 + rl;
-      res[it] = m < Mlive ? *reinterpret_cast<const f32x4*>((const float*)a.out + (size_t)m * a.ldo + n0 + c)
-                          : f32x4{};
+      res[it] = m < Mlive ? *reinterpret_cast<const f32x4*>(rsrc + (size_t)m * a.ldo + n0 + c) : f32x4{};
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
@@ -884,6 +925,13 @@ int launch_op(int epi, int xmode, const GemmArgs& a, hipStream_t s) {
     case EPI_QKV: return launch_t<Op, EPI_QKV, X_DENSE, T>(a, s);
     case EPI_PE: return launch_t<Op, EPI_PE, X_DENSE, float>(a, s);
     case EPI_HEAD: return launch_t<Op, EPI_HEAD, X_DENSE, float>(a, s);
+    case EPI_GELU_PRE:
+    case EPI_GELU_BWD:
+      if constexpr (sizeof(T) == 4) {
+        if (epi == EPI_GELU_PRE) return launch_t<Op, EPI_GELU_PRE, X_DENSE, float>(a, s);
+        return launch_t<Op, EPI_GELU_BWD, X_DENSE, float>(a, s);
+      }
+      return -22;
   }
   return -22;
 }
@@ -930,6 +978,11 @@ int launch_gemm(Prec prec, int epi, int xmode, const GemmArgs& a, hipStream_t s)
   if (((uintptr_t)a.bias | (uintptr_t)a.wscale) & 15) return -22;
   // the head's unpatchify knows RGB and depth pixels
   if (epi == EPI_HEAD && a.channels != 3 && a.channels != 1) return -22;
+  // the FP32 GELU epilogues move pre-activations as 16-byte vectors
+  if (epi == EPI_GELU_PRE || epi == EPI_GELU_BWD) {
+    if (prec != P_FP32 || xmode != X_DENSE || !a.pre || ((uintptr_t)a.pre & 15) || a.ldo % 4) return -22;
+  }
+  if (epi == EPI_RESIDUAL && a.res && (((uintptr_t)a.res & 15) || a.ldo % 4)) return -22;
   if (prec == P_BF16) {
     if (a.K % OpBF16::BK != 0) return -22;
     return launch_op<OpBF16>(epi, xmode, a, s);

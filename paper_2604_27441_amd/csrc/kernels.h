@@ -29,11 +29,14 @@ struct ReqDesc {
 // GEMM epilogues.  The product is C^T[n][m] = sum_k W[n][k] X[m][k].
 enum EpiMode {
   EPI_STORE = 0,     // out[m][n] = acc + bias[n]                (OutT)
-  EPI_RESIDUAL = 1,  // res[m][n] += acc + bias[n]               (fp32)
+  EPI_RESIDUAL = 1,  // out[m][n] = res[m][n] + acc + bias[n]   (fp32)
   EPI_GELU = 2,      // out[m][n] = gelu(acc + bias[n])          (OutT)
   EPI_QKV = 3,       // q/k [h][m][64] (q scaled), vt [h][64][ldv]
   EPI_PE = 4,        // out[m][n] = acc + bias[n] + PE(token m, n)  (fp32)
   EPI_HEAD = 5,      // pred pixel of compact target row m, slot column n
+  // FP32 operands only (the pretraining step):
+  EPI_GELU_PRE = 6,  // pre[m][n] = acc + bias[n], out[m][n] = gelu(pre[m][n])
+  EPI_GELU_BWD = 7,  // out[m][n] = (acc + bias[n]) gelu'(pre[m][n])
 };
 
 enum XMode {
@@ -54,6 +57,8 @@ struct GemmArgs {
   const float* bias; // [N]
   void* out;         // EPI_STORE / GELU / PE: [M][ldo]; RESIDUAL: fp32 [M][ldo]
   int ldo;
+  const float* res;  // EPI_RESIDUAL: out = res + acc + bias ([M][ldo]; nullable: res = out, in place)
+  float* pre;        // EPI_GELU_PRE (written) / EPI_GELU_BWD (read): fp32 [M][ldo] pre-activations
   // EPI_QKV
   void* q; void* k; void* vt; int heads; int ldqk; int ldv; float qscale;
   // FP8 operands: acc * wscale[n] * (*xscale) + bias[n]; an FP8 result is

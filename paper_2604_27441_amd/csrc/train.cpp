@@ -98,7 +98,7 @@ struct revo_trainer {
   float *U = nullptr, *xe = nullptr, *ae = nullptr, *zd = nullptr, *ahead = nullptr, *pred = nullptr;
   std::vector<BlockAct> act;  // ne encoder blocks, then nd decoder blocks
   float *dpred = nullptr, *dhead = nullptr, *dahead = nullptr, *lnpart = nullptr, *dxe = nullptr, *dz = nullptr;
-  float *dG = nullptr, *dH1 = nullptr, *da = nullptr, *dO = nullptr, *dqkv = nullptr;
+  float *dH1 = nullptr, *da = nullptr, *dO = nullptr, *dqkv = nullptr;
   float *part = nullptr, *dvec = nullptr, *splitk = nullptr;
   size_t splitk_elems = 0;
   TrDesc* d_tr = nullptr;  // the weight transposes of a step
@@ -173,14 +173,14 @@ int ln_grad(revo_trainer* t, const float* x, size_t g_off, size_t b_off, const f
   return launch_ln_bwd(x, t->theta + g_off, dy, dres, t->lnpart, t->ln_blocks, rows, D, rowmap, t->grad + g_off, t->s);
 }
 
-// forward of one block on the residual stream x (updated in place), saving
-// what the backward pass reads
-int block_fwd(revo_trainer* t, const BlockL& b, BlockAct& A, float* x, int D, int heads) {
+// forward of one block from its input A.xin into xout, saving what the
+// backward pass reads (the residual adds read one buffer and write another,
+// so no copies of the stream are made)
+int block_fwd(revo_trainer* t, const BlockL& b, BlockAct& A, float* xout, int D, int heads) {
   int e;
   hipStream_t s = t->s;
-  const size_t bytes = (size_t)t->Mpad * D * 4;
-  if (hipMemcpyAsync(A.xin, x, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) return REVO_EDEVICE;
-  if ((e = launch_layernorm(P_FP32, x, t->theta + b.ln1g, t->theta + b.ln1b, A.a1, t->Mpad, D, nullptr, 0, s))) return e;
+  if ((e = launch_layernorm(P_FP32, A.xin, t->theta + b.ln1g, t->theta + b.ln1b, A.a1, t->Mpad, D, nullptr, 0, s)))
+    return e;
   GemmArgs g;
   memset(&g, 0, sizeof(g));
   g.reqs = t->d_reqs; g.nreq = t->B; g.channels = t->C; g.M = t->Mpad;
@@ -195,17 +195,18 @@ int block_fwd(revo_trainer* t, const BlockL& b, BlockAct& A, float* x, int D, in
   at.reqs = t->d_reqs; at.nreq = t->B; at.work = t->d_work_f; at.nwork = t->nwork_f; at.lse = A.lse;
   if ((e = launch_attention(P_FP32, at, s))) return e;
   GemmArgs pr = g;
-  pr.X = A.o; pr.K = D; pr.N = D; pr.W = t->theta + b.proj.w; pr.bias = t->theta + b.proj.b; pr.out = x; pr.ldo = D;
+  pr.X = A.o; pr.K = D; pr.N = D; pr.W = t->theta + b.proj.w; pr.bias = t->theta + b.proj.b;
+  pr.res = A.xin; pr.out = A.xmid; pr.ldo = D;
   if ((e = launch_gemm(P_FP32, EPI_RESIDUAL, X_DENSE, pr, s))) return e;
-  if (hipMemcpyAsync(A.xmid, x, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) return REVO_EDEVICE;
-  if ((e = launch_layernorm(P_FP32, x, t->theta + b.ln2g, t->theta + b.ln2b, A.a2, t->Mpad, D, nullptr, 0, s))) return e;
+  if ((e = launch_layernorm(P_FP32, A.xmid, t->theta + b.ln2g, t->theta + b.ln2b, A.a2, t->Mpad, D, nullptr, 0, s)))
+    return e;
   GemmArgs f1 = g;
-  f1.X = A.a2; f1.K = D; f1.N = 4 * D; f1.W = t->theta + b.fc1.w; f1.bias = t->theta + b.fc1.b; f1.out = A.h1;
-  f1.ldo = 4 * D;
-  if ((e = launch_gemm(P_FP32, EPI_STORE, X_DENSE, f1, s))) return e;
-  if ((e = launch_gelu_fwd(A.h1, A.g, (long long)t->Mpad * 4 * D, s))) return e;
+  f1.X = A.a2; f1.K = D; f1.N = 4 * D; f1.W = t->theta + b.fc1.w; f1.bias = t->theta + b.fc1.b;
+  f1.pre = A.h1; f1.out = A.g; f1.ldo = 4 * D;
+  if ((e = launch_gemm(P_FP32, EPI_GELU_PRE, X_DENSE, f1, s))) return e;
   GemmArgs f2 = g;
-  f2.X = A.g; f2.K = 4 * D; f2.N = D; f2.W = t->theta + b.fc2.w; f2.bias = t->theta + b.fc2.b; f2.out = x; f2.ldo = D;
+  f2.X = A.g; f2.K = 4 * D; f2.N = D; f2.W = t->theta + b.fc2.w; f2.bias = t->theta + b.fc2.b;
+  f2.res = A.xmid; f2.out = xout; f2.ldo = D;
   return launch_gemm(P_FP32, EPI_RESIDUAL, X_DENSE, f2, s);
 }
 
@@ -215,9 +216,15 @@ int block_bwd(revo_trainer* t, const BlockL& b, const BlockAct& A, float* dx, in
   hipStream_t s = t->s;
   const int M = t->Mpad;
   // x_out = xmid + FC2(GELU(FC1(LN2(xmid))))
-  if ((e = input_grad(t, dx, b.fc2, t->dG, M))) return e;                        // dG = dx W2
+  {
+    // dH1 = (dx W2) gelu'(h1), the GELU backward in the product's epilogue
+    GemmArgs a;
+    memset(&a, 0, sizeof(a));
+    a.M = M; a.N = 4 * D; a.K = D; a.X = dx; a.W = t->wT + b.fc2.w; a.bias = t->zero;
+    a.pre = A.h1; a.out = t->dH1; a.ldo = 4 * D;
+    if ((e = launch_gemm(P_FP32, EPI_GELU_BWD, X_DENSE, a, s))) return e;
+  }
   if ((e = weight_grad(t, dx, A.g, M, b.fc2, t->grad))) return e;
-  if ((e = launch_gelu_bwd(t->dG, A.h1, t->dH1, (long long)M * 4 * D, s))) return e;
   if ((e = input_grad(t, t->dH1, b.fc1, t->da, M))) return e;                     // da2 = dH1 W1
   if ((e = weight_grad(t, t->dH1, A.a2, M, b.fc1, t->grad))) return e;
   if ((e = ln_grad(t, A.xmid, b.ln2g, b.ln2b, t->da, dx, M, D, nullptr))) return e;  // dx = d(xmid)
@@ -309,20 +316,25 @@ int run_step(revo_trainer* t, const revo_train_batch* bt, double* loss_out) {
   g.reqs = t->d_reqs; g.nreq = t->B; g.channels = t->C; g.M = t->Mpad;
   g.N = De; g.K = t->Lt; g.W = t->theta + t->L.emb.w; g.bias = t->theta + t->L.emb.b; g.out = t->xe; g.ldo = De;
   if ((e = launch_tubelet_pack(P_FP32, g, t->U, s))) return e;
+  // each block reads its input from its own saved buffer: the embedding
+  // writes the first encoder block's, every block the next one's and the
+  // last block of a stack the stack's output (xe, zd)
+  auto enc_in = [&](int i) { return i < t->ne ? t->act[i].xin : t->xe; };
+  auto dec_in = [&](int i) { return i < t->nd ? t->act[t->ne + i].xin : t->zd; };
   GemmArgs ge = g;
-  ge.X = t->U;
+  ge.X = t->U; ge.out = enc_in(0);
   if ((e = launch_gemm(P_FP32, EPI_PE, X_DENSE, ge, s))) return e;
   for (int i = 0; i < t->ne; ++i)
-    if ((e = block_fwd(t, t->L.enc[i], t->act[i], t->xe, De, 6))) return e;
+    if ((e = block_fwd(t, t->L.enc[i], t->act[i], enc_in(i + 1), De, 6))) return e;
   if ((e = launch_layernorm(P_FP32, t->xe, t->theta + t->L.encg, t->theta + t->L.encb, t->ae, t->Mpad, De, nullptr, 0,
                             s)))
     return e;
   GemmArgs e2 = g;
-  e2.X = t->ae; e2.K = De; e2.N = Dd; e2.W = t->theta + t->L.e2d.w; e2.bias = t->theta + t->L.e2d.b; e2.out = t->zd;
+  e2.X = t->ae; e2.K = De; e2.N = Dd; e2.W = t->theta + t->L.e2d.w; e2.bias = t->theta + t->L.e2d.b; e2.out = dec_in(0);
   e2.ldo = Dd;
   if ((e = launch_gemm(P_FP32, EPI_PE, X_DENSE, e2, s))) return e;
   for (int i = 0; i < t->nd; ++i)
-    if ((e = block_fwd(t, t->L.dec[i], t->act[t->ne + i], t->zd, Dd, 3))) return e;
+    if ((e = block_fwd(t, t->L.dec[i], t->act[t->ne + i], dec_in(i + 1), Dd, 3))) return e;
   if ((e = launch_layernorm(P_FP32, t->zd, t->theta + t->L.decg, t->theta + t->L.decb, t->ahead, t->Mh, Dd, t->d_reqs,
                             t->B, s)))
     return e;
@@ -447,7 +459,7 @@ int setup(revo_trainer* t, const revo_train_config& c) {
   if ((e = alloc_n(t, &t->dpred, (size_t)t->B * t->H * t->W * t->C)) ||
       (e = alloc_n(t, &t->dhead, (size_t)t->Mh_pad * 256 * t->C)) || (e = alloc_n(t, &t->dahead, (size_t)t->Mh_pad * Dd)) ||
       (e = alloc_n(t, &t->lnpart, (size_t)t->ln_blocks * 2 * 512)) || (e = alloc_n(t, &t->dxe, Mp * De)) || (e = alloc_n(t, &t->dz, Mp * Dd)) ||
-      (e = alloc_n(t, &t->dG, Mp * 4 * De)) || (e = alloc_n(t, &t->dH1, Mp * 4 * De)) || (e = alloc_n(t, &t->da, Mp * De)) ||
+      (e = alloc_n(t, &t->dH1, Mp * 4 * De)) || (e = alloc_n(t, &t->da, Mp * De)) ||
       (e = alloc_n(t, &t->dO, Mp * De)) || (e = alloc_n(t, &t->dqkv, Mp * 3 * De)) ||
       (e = alloc_n(t, &t->part, (size_t)t->max_chunks * widest)) || (e = alloc_n(t, &t->dvec, (size_t)6 * t->ld)) ||
       (e = alloc_n(t, &t->loss_part, t->loss_blocks)))

@@ -26,8 +26,6 @@ int launch_sum_chunks(const float* part, int nb, long long n, float* out, hipStr
 // chunk holds rows.
 int launch_wgrad(const float* dy, const float* x, int rows, int nout, int nin, int ldy, int ldx, int kc, int nchunk,
                  float* part, long long pstride, float* bpart, long long bstride, hipStream_t s);
-int launch_gelu_fwd(const float* h, float* g, long long n, hipStream_t s);
-int launch_gelu_bwd(const float* dg, const float* h, float* dh, long long n, hipStream_t s);
 // LayerNorm backward (y = LN(x) g + b, eps 1e-6) of rows [0, rows):
 // dres[row] += dL/dx, gb[0, D) = the gain gradient and gb[D, 2D) the shift
 // gradient (column sums over the rows; zeros for rows == 0).  part holds

@@ -11,16 +11,6 @@ namespace {
 
 constexpr int TB = 256;
 
-// erf by Abramowitz & Stegun 7.1.26 (|error| <= 1.5e-7), as the forward GELU
-__device__ inline float erf_as_t(float x) {
-  const float ax = fabsf(x);
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
-  const float poly = t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f),
-                              0.254829592f);
-  const float r = 1.0f - poly * __builtin_amdgcn_exp2f(-ax * ax * 1.4426950408889634f);
-  return copysignf(r, x);
-}
-
 // ---- transposes and column sums ---------------------------------------------
 
 // out[c][r] = in[r][c] for every block of the list, one 64 x 64 tile per
@@ -226,26 +216,6 @@ __global__ __launch_bounds__(TB, 2) void wgrad_kernel(const WgradArgs a) {
       for (int r = 0; r < 8; ++r) t += red[r * 128 + tid];
       a.bpart[(size_t)blockIdx.y * a.bstride + o0 + tid] = t;
     }
-  }
-}
-
-// ---- elementwise ----------------------------------------------------------------
-
-__global__ __launch_bounds__(TB) void gelu_fwd_kernel(const float* __restrict__ h, float* __restrict__ g, long long n) {
-  for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB) {
-    const float v = h[i];
-    g[i] = 0.5f * v * (1.0f + erf_as_t(v * 0.70710678118654752f));
-  }
-}
-
-// dh = dg * GELU'(h), GELU'(v) = Phi(v) + v phi(v)
-__global__ __launch_bounds__(TB) void gelu_bwd_kernel(const float* __restrict__ dg, const float* __restrict__ h,
-                                                      float* __restrict__ dh, long long n) {
-  for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB) {
-    const float v = h[i];
-    const float cdf = 0.5f * (1.0f + erf_as_t(v * 0.70710678118654752f));
-    const float pdf = 0.3989422804014327f * __builtin_amdgcn_exp2f(-0.5f * v * v * 1.4426950408889634f);
-    dh[i] = dg[i] * (cdf + v * pdf);
   }
 }
 
@@ -730,16 +700,6 @@ int launch_wgrad(const float* dy, const float* x, int rows, int nout, int nin, i
   a.dy = dy; a.x = x; a.rows = rows; a.nout = nout; a.nin = nin; a.ldy = ldy; a.ldx = ldx; a.kc = kc;
   a.part = part; a.bpart = bpart; a.pstride = pstride; a.bstride = bstride;
   wgrad_kernel<<<dim3(cdiv(nout, 128) * cdiv(nin, 128), nchunk), TB, 0, s>>>(a);
-  return last();
-}
-
-int launch_gelu_fwd(const float* h, float* g, long long n, hipStream_t s) {
-  gelu_fwd_kernel<<<grid_for(n), TB, 0, s>>>(h, g, n);
-  return last();
-}
-
-int launch_gelu_bwd(const float* dg, const float* h, float* dh, long long n, hipStream_t s) {
-  gelu_bwd_kernel<<<grid_for(n), TB, 0, s>>>(dg, h, dh, n);
   return last();
 }
 
