@@ -160,6 +160,46 @@ int weight_grad(revo_trainer* t, const float* dy, const float* x, int Mrows, con
   return launch_sum_chunks(t->part, S, l.out, gblob + l.b, t->s);
 }
 
+// dW and db of two layers over the same Mrows rows in one launch (two
+// independent products of one block's backward pass): the tiles of both
+// share the split into S row chunks, then each layer's chunks are summed.
+// Both layers keep their bias right after their weights in the blob.
+int weight_grad2(revo_trainer* t, const float* dy0, const float* x0, const Lin& l0, const float* dy1,
+                 const float* x1, const Lin& l1, int Mrows, float* gblob) {
+  int e;
+  const Lin* L[2] = {&l0, &l1};
+  int tiles = 0;
+  for (const Lin* l : L) tiles += cdiv(l->out, 128) * cdiv(l->in, 128);
+  int S = 512 / tiles;
+  if (S > Mrows / 64) S = Mrows / 64;  // at least 64 rows (4 stages) per chunk
+  if (S < 1) S = 1;
+  const int kc = align_up(cdiv(Mrows, S), 16);
+  S = cdiv(Mrows, kc);
+  WgradJob w[2];
+  const float* dys[2] = {dy0, dy1};
+  const float* xs[2] = {x0, x1};
+  size_t off = 0;
+  for (int j = 0; j < 2; ++j) {
+    const Lin& l = *L[j];
+    const long long nw = (long long)l.out * l.in;
+    if (l.b != l.w + (size_t)nw) return -22;
+    w[j].dy = dys[j]; w[j].x = xs[j]; w[j].nout = l.out; w[j].nin = l.in; w[j].ldy = l.out; w[j].ldx = l.in;
+    if (S == 1) {
+      w[j].part = gblob + l.w; w[j].pstride = nw; w[j].bpart = gblob + l.b; w[j].bstride = 0;
+    } else {
+      w[j].part = t->splitk + off; w[j].pstride = nw + l.out;
+      w[j].bpart = t->splitk + off + nw; w[j].bstride = nw + l.out;
+      off += (size_t)S * (nw + l.out);
+    }
+  }
+  if (off > t->splitk_elems) return -22;
+  if ((e = launch_wgrad2(w, 2, Mrows, kc, S, t->s))) return e;
+  if (S == 1) return 0;
+  for (int j = 0; j < 2; ++j)
+    if ((e = launch_sum_chunks(w[j].part, S, w[j].pstride, gblob + L[j]->w, t->s))) return e;
+  return 0;
+}
+
 // dX [Mrows][in] = dY W (dY [Mrows][out]) on the transposed weights
 int input_grad(revo_trainer* t, const float* dy, const Lin& l, float* dx, int Mrows) {
   return mm(t, dy, t->wT + l.w, dx, Mrows, l.in, l.out, l.in);
@@ -224,13 +264,11 @@ int block_bwd(revo_trainer* t, const BlockL& b, const BlockAct& A, float* dx, in
     a.pre = A.h1; a.out = t->dH1; a.ldo = 4 * D;
     if ((e = launch_gemm(P_FP32, EPI_GELU_BWD, X_DENSE, a, s))) return e;
   }
-  if ((e = weight_grad(t, dx, A.g, M, b.fc2, t->grad))) return e;
+  if ((e = weight_grad2(t, dx, A.g, b.fc2, t->dH1, A.a2, b.fc1, M, t->grad))) return e;
   if ((e = input_grad(t, t->dH1, b.fc1, t->da, M))) return e;                     // da2 = dH1 W1
-  if ((e = weight_grad(t, t->dH1, A.a2, M, b.fc1, t->grad))) return e;
   if ((e = ln_grad(t, A.xmid, b.ln2g, b.ln2b, t->da, dx, M, D, nullptr))) return e;  // dx = d(xmid)
   // xmid = xin + Proj(Attn(LN1(xin)))
   if ((e = input_grad(t, dx, b.proj, t->dO, M))) return e;
-  if ((e = weight_grad(t, dx, A.o, M, b.proj, t->grad))) return e;
   // the attention backward writes the rows of the batch's tokens only; the
   // alignment gaps between requests and past the last one, if any, must read
   // as zero gradient (the buffer is shared by the encoder and decoder widths)
@@ -240,7 +278,7 @@ int block_bwd(revo_trainer* t, const BlockL& b, const BlockAct& A, float* dx, in
                                 t->d_work_b, t->nwork_b, s)))
     return e;
   if ((e = input_grad(t, t->dqkv, b.qkv, t->da, M))) return e;
-  if ((e = weight_grad(t, t->dqkv, A.a1, M, b.qkv, t->grad))) return e;
+  if ((e = weight_grad2(t, dx, A.o, b.proj, t->dqkv, A.a1, b.qkv, M, t->grad))) return e;
   return ln_grad(t, A.xin, b.ln1g, b.ln1b, t->da, dx, M, D, nullptr);
 }
 

@@ -26,6 +26,18 @@ int launch_sum_chunks(const float* part, int nb, long long n, float* out, hipStr
 // chunk holds rows.
 int launch_wgrad(const float* dy, const float* x, int rows, int nout, int nin, int ldy, int ldx, int kc, int nchunk,
                  float* part, long long pstride, float* bpart, long long bstride, hipStream_t s);
+// One weight-gradient product of launch_wgrad2 (fields as launch_wgrad's).
+struct WgradJob {
+  const float* dy;
+  const float* x;
+  int nout, nin, ldy, ldx;
+  float* part;
+  float* bpart;
+  long long pstride, bstride;
+};
+// One or two weight-gradient products over the same rows and chunks in one
+// launch (the tiles of both fill the GPU together).
+int launch_wgrad2(const WgradJob* jobs, int njobs, int rows, int kc, int nchunk, hipStream_t s);
 // LayerNorm backward (y = LN(x) g + b, eps 1e-6) of rows [0, rows):
 // dres[row] += dL/dx, gb[0, D) = the gain gradient and gb[D, 2D) the shift
 // gradient (column sums over the rows; zeros for rows == 0).  part holds

@@ -5,6 +5,8 @@
 // Kingma & Ba 2015, Algorithm 1).  FP32 throughout.
 #include "train.h"
 
+#include <cstring>
+
 namespace revo {
 
 namespace {
@@ -116,22 +118,32 @@ __global__ __launch_bounds__(TB) void colsum_final_kernel(const float* __restric
 // contiguous), so no transposed copies are made.  Tile 128 (o) x 128 (i) on
 // 4 waves of 64 x 64 (2 x 2 FP32 32x32x2 MFMA blocks); stages of 16 rows of
 // each operand double-buffered in LDS, the next stage fetched into registers
-// during the current one's products.
-struct WgradArgs {
+// during the current one's products.  One launch can hold two layers over
+// the same rows (independent products of one block's backward pass): the
+// tiles from tile1 on belong to the second.
+struct WgradLayer {
   const float* dy;
   const float* x;
-  int rows, nout, nin, ldy, ldx, kc;
+  int nout, nin, ldy, ldx;
   float* part;
   float* bpart;
   long long pstride, bstride;  // elements from one chunk's part / bpart to the next
 };
+struct WgradArgs {
+  WgradLayer l0, l1;
+  int tile1;  // the first tile of l1 (the grid's width with one layer)
+  int rows, kc;
+};
 
-__global__ __launch_bounds__(TB, 2) void wgrad_kernel(const WgradArgs a) {
+__global__ __launch_bounds__(TB, 2) void wgrad_kernel(const WgradArgs args) {
   constexpr int R = 16, P = 160;  // rows per stage; row pitch (half-waves read rows 2s and 2s + 1 on disjoint banks)
   __shared__ __attribute__((aligned(16))) float sy[2][R][P], sx[2][R][P];
+  const bool second = (int)blockIdx.x >= args.tile1;
+  const WgradLayer a = second ? args.l1 : args.l0;
+  const int tile = (int)blockIdx.x - (second ? args.tile1 : 0);
   const int gi = (a.nin + 127) / 128;
-  const int o0 = (blockIdx.x / gi) * 128, i0 = (blockIdx.x - (blockIdx.x / gi) * gi) * 128;
-  const int m0 = blockIdx.y * a.kc, m1 = min(a.rows, m0 + a.kc);
+  const int o0 = (tile / gi) * 128, i0 = (tile - (tile / gi) * gi) * 128;
+  const int m0 = blockIdx.y * args.kc, m1 = min(args.rows, m0 + args.kc);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5, l32 = lane & 31;
   const int wo = wave >> 1, wi = wave & 1;
   // loader: rows tid / 32 and tid / 32 + 8 of the stage, columns 4 (tid %
@@ -687,20 +699,39 @@ int launch_sum_chunks(const float* part, int nb, long long n, float* out, hipStr
   return last();
 }
 
-int launch_wgrad(const float* dy, const float* x, int rows, int nout, int nin, int ldy, int ldx, int kc, int nchunk,
-                 float* part, long long pstride, float* bpart, long long bstride, hipStream_t s) {
-  // buffer-load byte offsets are 32-bit
-  if ((long long)rows * (ldy > ldx ? ldy : ldx) * 4 + 64 >= (1LL << 31)) return -22;
-  if (nout % 8 || nin % 8 || ldy % 4 || ldx % 4 || ldy < nout || ldx < nin || kc <= 0 || nchunk <= 0 || nchunk > 65535 ||
-      (nchunk > 1 && (pstride < (long long)nout * nin || (bpart && bstride < nout))) ||
-      (size_t)(nchunk - 1) * kc >= (size_t)(rows > 0 ? rows : 1) ||
-      (((uintptr_t)dy | (uintptr_t)x) & 15))
+int launch_wgrad2(const WgradJob* jobs, int njobs, int rows, int kc, int nchunk, hipStream_t s) {
+  if (njobs < 1 || njobs > 2 || kc <= 0 || nchunk <= 0 || nchunk > 65535 ||
+      (size_t)(nchunk - 1) * kc >= (size_t)(rows > 0 ? rows : 1))
     return -22;
   WgradArgs a;
-  a.dy = dy; a.x = x; a.rows = rows; a.nout = nout; a.nin = nin; a.ldy = ldy; a.ldx = ldx; a.kc = kc;
-  a.part = part; a.bpart = bpart; a.pstride = pstride; a.bstride = bstride;
-  wgrad_kernel<<<dim3(cdiv(nout, 128) * cdiv(nin, 128), nchunk), TB, 0, s>>>(a);
+  memset(&a, 0, sizeof(a));
+  a.rows = rows; a.kc = kc;
+  int tiles = 0;
+  for (int j = 0; j < njobs; ++j) {
+    const WgradJob& w = jobs[j];
+    // buffer-load byte offsets are 32-bit
+    if ((long long)rows * (w.ldy > w.ldx ? w.ldy : w.ldx) * 4 + 64 >= (1LL << 31)) return -22;
+    if (w.nout % 8 || w.nin % 8 || w.ldy % 4 || w.ldx % 4 || w.ldy < w.nout || w.ldx < w.nin ||
+        (nchunk > 1 && (w.pstride < (long long)w.nout * w.nin || (w.bpart && w.bstride < w.nout))) ||
+        (((uintptr_t)w.dy | (uintptr_t)w.x) & 15))
+      return -22;
+    WgradLayer& l = j ? a.l1 : a.l0;
+    l.dy = w.dy; l.x = w.x; l.nout = w.nout; l.nin = w.nin; l.ldy = w.ldy; l.ldx = w.ldx;
+    l.part = w.part; l.bpart = w.bpart; l.pstride = w.pstride; l.bstride = w.bstride;
+    if (j == 1) a.tile1 = tiles;
+    tiles += cdiv(w.nout, 128) * cdiv(w.nin, 128);
+  }
+  if (njobs == 1) a.tile1 = tiles;
+  wgrad_kernel<<<dim3(tiles, nchunk), TB, 0, s>>>(a);
   return last();
+}
+
+int launch_wgrad(const float* dy, const float* x, int rows, int nout, int nin, int ldy, int ldx, int kc, int nchunk,
+                 float* part, long long pstride, float* bpart, long long bstride, hipStream_t s) {
+  WgradJob w;
+  w.dy = dy; w.x = x; w.nout = nout; w.nin = nin; w.ldy = ldy; w.ldx = ldx;
+  w.part = part; w.bpart = bpart; w.pstride = pstride; w.bstride = bstride;
+  return launch_wgrad2(&w, 1, rows, kc, nchunk, s);
 }
 
 int ln_bwd_blocks(int rows) { return rows > 0 ? cdiv(rows, LN_WAVES) : 1; }
