@@ -112,7 +112,7 @@ __global__ __launch_bounds__(TB) void colsum_final_kernel(const float* __restric
 // ---- weight gradients ------------------------------------------------------------
 
 // part[c][o][i] = sum over the rows m of chunk c (rows c kc .. c kc + kc - 1
-// below `rows`) of dy[m][o] x[m][i], c = blockIdx.y; with bpart, the tiles of
+// below `rows`) of dy[m][o] x[m][i] for every chunk c; with bpart, the tiles of
 // the first input columns also write bpart[c][o] = the same rows' sum of
 // dy[m][o].  Both operands are read as they lie (token rows, features
 // contiguous), so no transposed copies are made.  Tile 128 (o) x 128 (i) on
@@ -138,12 +138,20 @@ struct WgradArgs {
 __global__ __launch_bounds__(TB, 2) void wgrad_kernel(const WgradArgs args) {
   constexpr int R = 16, P = 160;  // rows per stage; row pitch (half-waves read rows 2s and 2s + 1 on disjoint banks)
   __shared__ __attribute__((aligned(16))) float sy[2][R][P], sx[2][R][P];
-  const bool second = (int)blockIdx.x >= args.tile1;
+  // Workgroups go round-robin to the 8 XCDs, each with its own L2: give XCD
+  // x a contiguous range of (chunk, tile) pairs, tile fastest, so the tiles
+  // that read one chunk's rows share that XCD's L2 instead of every L2
+  // fetching them from HBM
+  const int nwg = gridDim.x * gridDim.y, L = blockIdx.y * gridDim.x + blockIdx.x;
+  const int xcd = L & 7, per = nwg >> 3, rem = nwg & 7;
+  const int q = xcd * per + (xcd < rem ? xcd : rem) + (L >> 3);
+  const int chunk = q / (int)gridDim.x, tall = q - chunk * (int)gridDim.x;
+  const bool second = tall >= args.tile1;
   const WgradLayer a = second ? args.l1 : args.l0;
-  const int tile = (int)blockIdx.x - (second ? args.tile1 : 0);
+  const int tile = tall - (second ? args.tile1 : 0);
   const int gi = (a.nin + 127) / 128;
   const int o0 = (tile / gi) * 128, i0 = (tile - (tile / gi) * gi) * 128;
-  const int m0 = blockIdx.y * args.kc, m1 = min(args.rows, m0 + args.kc);
+  const int m0 = chunk * args.kc, m1 = min(args.rows, m0 + args.kc);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5, l32 = lane & 31;
   const int wo = wave >> 1, wi = wave & 1;
   // loader: rows tid / 32 and tid / 32 + 8 of the stage, columns 4 (tid %
@@ -203,7 +211,7 @@ __global__ __launch_bounds__(TB, 2) void wgrad_kernel(const WgradArgs args) {
     if (st + 1 < nst) put(b ^ 1);
     __syncthreads();
   }
-  float* out = a.part + (size_t)blockIdx.y * a.pstride;
+  float* out = a.part + (size_t)chunk * a.pstride;
 #pragma unroll
   for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -226,7 +234,7 @@ __global__ __launch_bounds__(TB, 2) void wgrad_kernel(const WgradArgs args) {
     if (tid < 128 && o0 + tid < a.nout) {
       float t = 0.0f;
       for (int r = 0; r < 8; ++r) t += red[r * 128 + tid];
-      a.bpart[(size_t)blockIdx.y * a.bstride + o0 + tid] = t;
+      a.bpart[(size_t)chunk * a.bstride + o0 + tid] = t;
     }
   }
 }
