@@ -345,7 +345,7 @@ constexpr int epi_stage_bytes() {
 template <class Op, int BN, int EPI, class OutT, int BM_ = BM, int WM_ = 2>
 __device__ __forceinline__ void gemm_epilogue_staged(const GemmArgs& a, f32x16 (&acc)[BN / 64][2], int m0, int n0,
                                                      int Mlive, int nreq, int tid, uint8_t* smem,
-                                                     const EpiCols<BN>& cols) {
+                                                     const EpiCols<BN>& cols, bool active = true) {
   constexpr int NT_ = 128 * WM_;
   constexpr int NSUB = BN / 64;
   constexpr int TPB = BN * (int)sizeof(OutT) + 16;   // row pitch (bytes), row-major tile
@@ -360,6 +360,8 @@ __device__ __forceinline__ void gemm_epilogue_staged(const GemmArgs& a, f32x16 (
   const bool vtile = EPI == EPI_QKV && part == 2;
   constexpr bool SC = sizeof(typename Op::T) == 1;  // FP8 operands carry row scales
   __syncthreads();  // every wave is done with the operand tiles
+  // (threads beyond the tile's 2 WM_ waves, !active, only join the barriers)
+  if (active) {
 #pragma unroll
   for (int ms = 0; ms < 2; ++ms) {
     const int ml = wm * 64 + ms * 32 + l32;
@@ -415,7 +417,9 @@ __device__ __forceinline__ void gemm_epilogue_staged(const GemmArgs& a, f32x16 (
       }
     }
   }
+  }
   __syncthreads();
+  if (!active) return;
   if (vtile) {
     // V^T rows: EO consecutive columns per 16-byte chunk; a 2-byte chunk
     // can hold permuted tokens up to the end of its group of 16 (a 1-byte
@@ -517,15 +521,22 @@ __device__ __forceinline__ void gemm_epilogue_staged(const GemmArgs& a, f32x16 (
   }
 }
 
-template <class Op, int BN, int EPI, int XM, class OutT>
-__global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
+// KS = 2 (FP32 products of at most one workgroup per CU): 8 waves, the
+// second four taking the second half of every stage's k steps into
+// accumulators of their own, added to the first four's through LDS before
+// the epilogue, so each SIMD holds two waves
+template <class Op, int BN, int EPI, int XM, class OutT, int KS = 1>
+__global__ __launch_bounds__(NT * KS, KS == 1 ? 2 : 1) void gemm_kernel(const GemmArgs a) {
   typedef typename Op::T T;
+  static_assert(KS == 1 || (KS == 2 && EPI != EPI_HEAD), "K split: staged epilogues only");
+  constexpr int NT_ = NT * KS;
   constexpr int BK = Op::BK;
   constexpr int E = 16 / sizeof(T);               // elements per 16-byte chunk
   constexpr int CPR = BK * sizeof(T) / 16;        // chunks per stage row
   constexpr int PITCH = (BK * sizeof(T) + 16) / sizeof(T);  // LDS row pitch, padded by 16 bytes
-  constexpr int XC = BM * CPR / NT;
-  constexpr int WC = BN * CPR / NT;
+  constexpr int XC = BM * CPR / NT_;
+  constexpr int WC = BN * CPR / NT_;
+  static_assert(XC * NT_ == BM * CPR && WC * NT_ == BN * CPR, "whole chunks per thread");
   constexpr int NSUB = BN / 64;
   constexpr int FB = Op::KPL * sizeof(T);          // operand bytes per lane per MFMA step
   constexpr int G = FB >= 16 ? 1 : 16 / FB;        // MFMA steps per 16-byte LDS read
@@ -562,7 +573,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
   if (XM == X_GATHER) {
 #pragma unroll
     for (int i = 0; i < XC; ++i) {
-      const int m = m0 + (tid + i * NT) / CPR;
+      const int m = m0 + (tid + i * NT_) / CPR;
       g_req[i] = -1;
       if (m < Mlive) {
         const int r = find_req_tok(a.reqs, nreq, m);
@@ -579,8 +590,8 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
   int c_row[XC > WC ? XC : WC], c_k[XC > WC ? XC : WC];
 #pragma unroll
   for (int i = 0; i < (XC > WC ? XC : WC); ++i) {
-    c_row[i] = (tid + i * NT) / CPR;
-    c_k[i] = ((tid + i * NT) % CPR) * E;
+    c_row[i] = (tid + i * NT_) / CPR;
+    c_k[i] = ((tid + i * NT_) % CPR) * E;
   }
   // two register sets of stage operands: the loads for stage k+2 are
   // issued while stage k is multiplied, so two stages of compute cover the
@@ -625,15 +636,18 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
       *reinterpret_cast<uint4*>(&ws[buf_][c_row[i] * PITCH + c_k[i]]) = WR[i];                               \
   } while (0)
 
-  const int wn = wave >> 1, wm = wave & 1;
+  // waves 4..7 (KS = 2) repeat waves 0..3's tile positions on the other k steps
+  const int wq = wave & 3, kgrp = KS == 1 ? 0 : wave >> 2;
+  const int wn = wq >> 1, wm = wq & 1;
+  static_assert(STEPS % (KS * G) == 0, "whole LDS reads per k group");
   f32x16 acc[NSUB][2];
 #pragma unroll
   for (int i = 0; i < NSUB; ++i) { acc[i][0] = f32x16{}; acc[i][1] = f32x16{}; }
 
   // one K stage from LDS buffer buf_ into the accumulators
 #define REVO_GEMM_COMPUTE(buf_)                                                                              \
-  _Pragma("unroll") for (int s = 0; s < STEPS; s += G) {                                                     \
-    const int koff = half * (BK / 2) + s * Op::KPL;                                                          \
+  _Pragma("unroll") for (int s0 = 0; s0 < STEPS / KS; s0 += G) {                                            \
+    const int koff = half * (BK / 2) + (kgrp * (STEPS / KS) + s0) * Op::KPL;                                 \
     if constexpr (FB == 32) {                                                                                \
       uint4 wf[NSUB][2], xf[2][2];                                                                           \
       _Pragma("unroll") for (int ns = 0; ns < NSUB; ++ns) {                                                  \
@@ -689,6 +703,31 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
 #undef REVO_GEMM_STORE
 #undef REVO_GEMM_COMPUTE
 
+  if constexpr (KS == 2) {
+    // the second k group's accumulators into the first's, lane by lane
+    // (identical fragment layouts), through the operand stages' LDS
+    static_assert(4 * NSUB * 2 * 16 * 64 * 4 <= (OPB > EPB ? OPB : EPB), "reduction fits the stages");
+    float* red = reinterpret_cast<float*>(smem);
+    __syncthreads();  // every wave is done with the operand stages
+    if (kgrp == 1) {
+#pragma unroll
+      for (int ns = 0; ns < NSUB; ++ns)
+#pragma unroll
+        for (int ms = 0; ms < 2; ++ms)
+#pragma unroll
+          for (int j = 0; j < 16; ++j) red[(((wq * NSUB + ns) * 2 + ms) * 16 + j) * 64 + lane] = acc[ns][ms][j];
+    }
+    __syncthreads();
+    if (kgrp == 0) {
+#pragma unroll
+      for (int ns = 0; ns < NSUB; ++ns)
+#pragma unroll
+        for (int ms = 0; ms < 2; ++ms)
+#pragma unroll
+          for (int j = 0; j < 16; ++j) acc[ns][ms][j] += red[(((wq * NSUB + ns) * 2 + ms) * 16 + j) * 64 + lane];
+    }
+  }
+  const bool act = kgrp == 0;
   // bias (and scale) vectors fetched together after the K loop: this
   // kernel has no registers to hold them through it
   EpiCols<BN> cols;
@@ -700,12 +739,12 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(const GemmArgs a) {
       // product blockIdx.y of a batch
       GemmArgs ab = a;
       ab.out = (OutT*)a.out + (size_t)blockIdx.y * a.bso;
-      gemm_epilogue_staged<Op, BN, EPI, OutT>(ab, acc, m0, n0, Mlive, nreq, tid, smem, cols);
+      gemm_epilogue_staged<Op, BN, EPI, OutT>(ab, acc, m0, n0, Mlive, nreq, tid, smem, cols, act);
     } else {
-      gemm_epilogue_staged<Op, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, tid, smem, cols);
+      gemm_epilogue_staged<Op, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, tid, smem, cols, act);
     }
   } else {
-    gemm_epilogue_staged<Op, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, tid, smem, cols);
+    gemm_epilogue_staged<Op, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, tid, smem, cols, act);
   }
 }
 
@@ -898,6 +937,14 @@ int launch_t(const GemmArgs& a, hipStream_t s) {
     // tiles unless 64-wide ones (twice as many, half the work each) spread
     // better over the 256 CUs: the busiest CU then holds fewer feature columns
     const int nb = a.batch > 1 ? a.batch : 1;
+    if constexpr (XM == X_DENSE && sizeof(typename Op::T) == 4 && EPI != EPI_HEAD) {
+      // FP32 products of at most one 64-wide workgroup per CU: eight waves
+      // that split each stage's k steps, two per SIMD instead of one
+      if ((long long)gm * (a.N / 64) * nb <= 256) {
+        gemm_kernel<Op, 64, EPI, XM, OutT, 2><<<dim3(gm * (a.N / 64), nb), 2 * NT, 0, s>>>(a);
+        return hipGetLastError() == hipSuccess ? 0 : -5;
+      }
+    }
     if constexpr (XM == X_DENSE) {
       const long long t128 = (long long)gm * (a.N / 128) * nb;
       const bool wide = a.N % 128 == 0 && (2 * t128 + 255) / 256 >= 2 * ((t128 + 255) / 256);
