@@ -102,6 +102,12 @@ struct revo_trainer {
   float *part = nullptr, *dvec = nullptr, *splitk = nullptr;
   size_t splitk_elems = 0;
   TrDesc* d_tr = nullptr;  // the weight transposes of a step
+  // the weight gradients run on s2 beside the input-gradient chain on s:
+  // ev_fork orders s2 after s, ev_p1 / ev_p2 mark a block's first and
+  // second dW pair done, ev_join the last dW launch of the step
+  hipStream_t s2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_p1 = nullptr, ev_p2 = nullptr, ev_join = nullptr;
+  float* dmid = nullptr;  // a block's midpoint gradient
   int ntr = 0;
   long long tr_tiles = 0;
   double* loss_part = nullptr;
@@ -144,20 +150,20 @@ int weight_grad(revo_trainer* t, const float* dy, const float* x, int Mrows, con
   const int kc = align_up(cdiv(Mrows, S), 16);
   S = cdiv(Mrows, kc);
   const long long nw = (long long)l.out * l.in;
-  if (S == 1) return launch_wgrad(dy, x, Mrows, l.out, l.in, l.out, l.in, kc, 1, gblob + l.w, nw, gblob + l.b, 0, t->s);
+  if (S == 1) return launch_wgrad(dy, x, Mrows, l.out, l.in, l.out, l.in, kc, 1, gblob + l.w, nw, gblob + l.b, 0, t->s2);
   if (l.b == l.w + (size_t)nw) {
     // the blob keeps a layer's bias right after its weights: chunk c's
     // partial dW and db are laid out the same way, and one sum covers both
     if ((size_t)S * (nw + l.out) > t->splitk_elems) return -22;
     if ((e = launch_wgrad(dy, x, Mrows, l.out, l.in, l.out, l.in, kc, S, t->splitk, nw + l.out, t->splitk + nw,
-                          nw + l.out, t->s)))
+                          nw + l.out, t->s2)))
       return e;
-    return launch_sum_chunks(t->splitk, S, nw + l.out, gblob + l.w, t->s);
+    return launch_sum_chunks(t->splitk, S, nw + l.out, gblob + l.w, t->s2);
   }
   if ((size_t)S * nw > t->splitk_elems || S > t->max_chunks) return -22;
-  if ((e = launch_wgrad(dy, x, Mrows, l.out, l.in, l.out, l.in, kc, S, t->splitk, nw, t->part, l.out, t->s))) return e;
-  if ((e = launch_sum_chunks(t->splitk, S, nw, gblob + l.w, t->s))) return e;
-  return launch_sum_chunks(t->part, S, l.out, gblob + l.b, t->s);
+  if ((e = launch_wgrad(dy, x, Mrows, l.out, l.in, l.out, l.in, kc, S, t->splitk, nw, t->part, l.out, t->s2))) return e;
+  if ((e = launch_sum_chunks(t->splitk, S, nw, gblob + l.w, t->s2))) return e;
+  return launch_sum_chunks(t->part, S, l.out, gblob + l.b, t->s2);
 }
 
 // dW and db of two layers over the same Mrows rows in one launch (two
@@ -193,10 +199,10 @@ int weight_grad2(revo_trainer* t, const float* dy0, const float* x0, const Lin& 
     }
   }
   if (off > t->splitk_elems) return -22;
-  if ((e = launch_wgrad2(w, 2, Mrows, kc, S, t->s))) return e;
+  if ((e = launch_wgrad2(w, 2, Mrows, kc, S, t->s2))) return e;
   if (S == 1) return 0;
   for (int j = 0; j < 2; ++j)
-    if ((e = launch_sum_chunks(w[j].part, S, w[j].pstride, gblob + L[j]->w, t->s))) return e;
+    if ((e = launch_sum_chunks(w[j].part, S, w[j].pstride, gblob + L[j]->w, t->s2))) return e;
   return 0;
 }
 
@@ -207,10 +213,23 @@ int input_grad(revo_trainer* t, const float* dy, const Lin& l, float* dx, int Mr
 
 // LayerNorm backward of rows [0, rows): adds dL/dx into dres, writes the
 // gain and shift gradients
-int ln_grad(revo_trainer* t, const float* x, size_t g_off, size_t b_off, const float* dy, float* dres, int rows, int D,
-            const int* rowmap) {
+int ln_grad(revo_trainer* t, const float* x, size_t g_off, size_t b_off, const float* dy, const float* din, float* dout,
+            int rows, int D, const int* rowmap) {
   if (b_off != g_off + (size_t)D) return -22;  // one sum writes both vectors
-  return launch_ln_bwd(x, t->theta + g_off, dy, dres, t->lnpart, t->ln_blocks, rows, D, rowmap, t->grad + g_off, t->s);
+  return launch_ln_bwd(x, t->theta + g_off, dy, din, dout, t->lnpart, t->ln_blocks, rows, D, rowmap, t->grad + g_off,
+                       t->s);
+}
+
+// s2 continues after everything enqueued on s so far
+int fork_wgrad(revo_trainer* t) {
+  return hipEventRecord(t->ev_fork, t->s) == hipSuccess && hipStreamWaitEvent(t->s2, t->ev_fork, 0) == hipSuccess
+             ? 0
+             : REVO_EDEVICE;
+}
+// ev marks the point s2 has reached; s waits for the latest mark of ev
+int mark_wgrad(revo_trainer* t, hipEvent_t ev) { return hipEventRecord(ev, t->s2) == hipSuccess ? 0 : REVO_EDEVICE; }
+int wait_wgrad(revo_trainer* t, hipEvent_t ev) {
+  return hipStreamWaitEvent(t->s, ev, 0) == hipSuccess ? 0 : REVO_EDEVICE;
 }
 
 // forward of one block from its input A.xin into xout, saving what the
@@ -250,7 +269,12 @@ int block_fwd(revo_trainer* t, const BlockL& b, BlockAct& A, float* xout, int D,
   return launch_gemm(P_FP32, EPI_RESIDUAL, X_DENSE, f2, s);
 }
 
-// backward of one block: dx holds dL/d(block output) and becomes dL/d(input)
+// backward of one block: dx holds dL/d(block output) and becomes dL/d(input).
+// The block's two dW pairs run on s2 while s carries on with the input
+// gradients: the first pair reads dx and dH1, the second dmid and dqkv, so
+// s waits for the first before it rewrites dx, and for the previous block's
+// second before it rewrites dmid and dqkv.  dH1 is rewritten only after
+// the previous block's first pair, which s waited for at that block's end.
 int block_bwd(revo_trainer* t, const BlockL& b, const BlockAct& A, float* dx, int D, int heads) {
   int e;
   hipStream_t s = t->s;
@@ -264,11 +288,14 @@ int block_bwd(revo_trainer* t, const BlockL& b, const BlockAct& A, float* dx, in
     a.pre = A.h1; a.out = t->dH1; a.ldo = 4 * D;
     if ((e = launch_gemm(P_FP32, EPI_GELU_BWD, X_DENSE, a, s))) return e;
   }
-  if ((e = weight_grad2(t, dx, A.g, b.fc2, t->dH1, A.a2, b.fc1, M, t->grad))) return e;
-  if ((e = input_grad(t, t->dH1, b.fc1, t->da, M))) return e;                     // da2 = dH1 W1
-  if ((e = ln_grad(t, A.xmid, b.ln2g, b.ln2b, t->da, dx, M, D, nullptr))) return e;  // dx = d(xmid)
+  if ((e = fork_wgrad(t)) || (e = weight_grad2(t, dx, A.g, b.fc2, t->dH1, A.a2, b.fc1, M, t->grad)) ||
+      (e = mark_wgrad(t, t->ev_p1)))
+    return e;
+  if ((e = input_grad(t, t->dH1, b.fc1, t->da, M))) return e;  // da2 = dH1 W1
+  if ((e = wait_wgrad(t, t->ev_p2))) return e;                  // the previous block's dmid and dqkv readers
+  if ((e = ln_grad(t, A.xmid, b.ln2g, b.ln2b, t->da, dx, t->dmid, M, D, nullptr))) return e;  // d(xmid)
   // xmid = xin + Proj(Attn(LN1(xin)))
-  if ((e = input_grad(t, dx, b.proj, t->dO, M))) return e;
+  if ((e = input_grad(t, t->dmid, b.proj, t->dO, M))) return e;
   // the attention backward writes the rows of the batch's tokens only; the
   // alignment gaps between requests and past the last one, if any, must read
   // as zero gradient (the buffer is shared by the encoder and decoder widths)
@@ -278,8 +305,11 @@ int block_bwd(revo_trainer* t, const BlockL& b, const BlockAct& A, float* dx, in
                                 t->d_work_b, t->nwork_b, s)))
     return e;
   if ((e = input_grad(t, t->dqkv, b.qkv, t->da, M))) return e;
-  if ((e = weight_grad2(t, dx, A.o, b.proj, t->dqkv, A.a1, b.qkv, M, t->grad))) return e;
-  return ln_grad(t, A.xin, b.ln1g, b.ln1b, t->da, dx, M, D, nullptr);
+  if ((e = fork_wgrad(t)) || (e = weight_grad2(t, t->dmid, A.o, b.proj, t->dqkv, A.a1, b.qkv, M, t->grad)) ||
+      (e = mark_wgrad(t, t->ev_p2)))
+    return e;
+  if ((e = wait_wgrad(t, t->ev_p1))) return e;  // the first pair has read dx
+  return ln_grad(t, A.xin, b.ln1g, b.ln1b, t->da, t->dmid, dx, M, D, nullptr);
 }
 
 // the transposed weights the dX products read (every layer but the
@@ -391,6 +421,8 @@ int run_step(revo_trainer* t, const revo_train_batch* bt, double* loss_out) {
   if (hipMemsetAsync(t->grad, 0, t->L.count * 4, s) != hipSuccess) return REVO_EDEVICE;
   if (hipMemsetAsync(t->dz, 0, (size_t)t->Mpad * Dd * 4, s) != hipSuccess) return REVO_EDEVICE;
   if ((e = transpose_weights(t))) return e;
+  // the dW launches' marks start out passed (s2 is idle)
+  if ((e = fork_wgrad(t)) || (e = mark_wgrad(t, t->ev_p1)) || (e = mark_wgrad(t, t->ev_p2))) return e;
   // head: o = LN_dec(z) W_slot^T + b_slot on the target rows
   if ((e = launch_head_grad(t->d_reqs, t->B, t->Mh, t->Mh_pad, t->C, t->dpred, (long long)t->H * t->W * t->C, t->dhead,
                             s)))
@@ -398,20 +430,22 @@ int run_step(revo_trainer* t, const revo_train_batch* bt, double* loss_out) {
   Lin hs;
   hs.out = 256 * t->C; hs.in = Dd;
   hs.w = t->L.head.w + slot * Dd; hs.b = t->L.head.b + slot;
-  if ((e = weight_grad(t, t->dhead, t->ahead, t->Mh_pad, hs, t->grad))) return e;
+  if ((e = fork_wgrad(t)) || (e = weight_grad(t, t->dhead, t->ahead, t->Mh_pad, hs, t->grad))) return e;
   if ((e = input_grad(t, t->dhead, hs, t->dahead, t->Mh_pad))) return e;
-  if ((e = ln_grad(t, t->zd, t->L.decg, t->L.decb, t->dahead, t->dz, t->Mh, Dd, t->d_rowmap))) return e;
+  if ((e = ln_grad(t, t->zd, t->L.decg, t->L.decb, t->dahead, t->dz, t->dz, t->Mh, Dd, t->d_rowmap))) return e;
   for (int i = t->nd - 1; i >= 0; --i)
     if ((e = block_bwd(t, t->L.dec[i], t->act[t->ne + i], t->dz, Dd, 3))) return e;
   // z0 = LN_enc(h) W_e2d^T + b + PE
-  if ((e = weight_grad(t, t->dz, t->ae, t->Mpad, t->L.e2d, t->grad))) return e;
+  if ((e = fork_wgrad(t)) || (e = weight_grad(t, t->dz, t->ae, t->Mpad, t->L.e2d, t->grad))) return e;
   if ((e = input_grad(t, t->dz, t->L.e2d, t->da, t->Mpad))) return e;
   if (hipMemsetAsync(t->dxe, 0, (size_t)t->Mpad * De * 4, s) != hipSuccess) return REVO_EDEVICE;
-  if ((e = ln_grad(t, t->xe, t->L.encg, t->L.encb, t->da, t->dxe, t->Mpad, De, nullptr))) return e;
+  if ((e = ln_grad(t, t->xe, t->L.encg, t->L.encb, t->da, t->dxe, t->dxe, t->Mpad, De, nullptr))) return e;
   for (int i = t->ne - 1; i >= 0; --i)
     if ((e = block_bwd(t, t->L.enc[i], t->act[i], t->dxe, De, 6))) return e;
   // h0 = U W_emb^T + b + PE
-  if ((e = weight_grad(t, t->dxe, t->U, t->Mpad, t->L.emb, t->grad))) return e;
+  if ((e = fork_wgrad(t)) || (e = weight_grad(t, t->dxe, t->U, t->Mpad, t->L.emb, t->grad))) return e;
+  // every dW launch is done before Adam reads the gradients
+  if ((e = mark_wgrad(t, t->ev_join)) || (e = wait_wgrad(t, t->ev_join))) return e;
 
   // ---- Adam ----
   t->step += 1;
@@ -497,7 +531,7 @@ int setup(revo_trainer* t, const revo_train_config& c) {
   if ((e = alloc_n(t, &t->dpred, (size_t)t->B * t->H * t->W * t->C)) ||
       (e = alloc_n(t, &t->dhead, (size_t)t->Mh_pad * 256 * t->C)) || (e = alloc_n(t, &t->dahead, (size_t)t->Mh_pad * Dd)) ||
       (e = alloc_n(t, &t->lnpart, (size_t)t->ln_blocks * 2 * 512)) || (e = alloc_n(t, &t->dxe, Mp * De)) || (e = alloc_n(t, &t->dz, Mp * Dd)) ||
-      (e = alloc_n(t, &t->dH1, Mp * 4 * De)) || (e = alloc_n(t, &t->da, Mp * De)) ||
+      (e = alloc_n(t, &t->dH1, Mp * 4 * De)) || (e = alloc_n(t, &t->da, Mp * De)) || (e = alloc_n(t, &t->dmid, Mp * De)) ||
       (e = alloc_n(t, &t->dO, Mp * De)) || (e = alloc_n(t, &t->dqkv, Mp * 3 * De)) ||
       (e = alloc_n(t, &t->part, (size_t)t->max_chunks * widest)) || (e = alloc_n(t, &t->dvec, (size_t)6 * t->ld)) ||
       (e = alloc_n(t, &t->loss_part, t->loss_blocks)))
@@ -538,7 +572,12 @@ int revo_train_create(const revo_train_config* cfg, revo_trainer** out) {
   t->eps = c.eps > 0 ? c.eps : 1e-8f;
   t->alpha = c.tv_weight > 0 ? c.tv_weight : (c.tv_weight < 0 ? 0.0f : 0.01f);
   int rc = 0;
-  if (hipSetDevice(t->dev) != hipSuccess || hipStreamCreateWithFlags(&t->s, hipStreamNonBlocking) != hipSuccess) {
+  if (hipSetDevice(t->dev) != hipSuccess || hipStreamCreateWithFlags(&t->s, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&t->s2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&t->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&t->ev_p1, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&t->ev_p2, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&t->ev_join, hipEventDisableTiming) != hipSuccess) {
     rc = REVO_EDEVICE;
   } else {
     rc = setup(t, c);
@@ -555,14 +594,18 @@ int revo_train_step(revo_trainer* t, const revo_train_batch* b, double* loss) {
   if (!t || !b || !b->refs || !b->target || !b->mask || !b->ref_idx || !b->t_target) return REVO_EINVAL;
   if (hipSetDevice(t->dev) != hipSuccess) return REVO_EDEVICE;
   const int rc = run_step(t, b, loss);
-  if (rc) (void)hipStreamSynchronize(t->s);
+  if (rc) {
+    (void)hipStreamSynchronize(t->s);
+    (void)hipStreamSynchronize(t->s2);
+  }
   return rc;
 }
 
 static int copy_out(revo_trainer* t, const float* src, float* out, size_t n, size_t have) {
   if (!t || !out || n != have) return REVO_EINVAL;
   if (hipSetDevice(t->dev) != hipSuccess) return REVO_EDEVICE;
-  if (hipStreamSynchronize(t->s) != hipSuccess || hipMemcpy(out, src, n * 4, hipMemcpyDeviceToHost) != hipSuccess)
+  if (hipStreamSynchronize(t->s) != hipSuccess || hipStreamSynchronize(t->s2) != hipSuccess ||
+      hipMemcpy(out, src, n * 4, hipMemcpyDeviceToHost) != hipSuccess)
     return REVO_EDEVICE;
   return 0;
 }
@@ -581,7 +624,11 @@ void revo_train_destroy(revo_trainer* t) {
   if (!t) return;
   (void)hipSetDevice(t->dev);
   if (t->s) (void)hipStreamSynchronize(t->s);
+  if (t->s2) (void)hipStreamSynchronize(t->s2);
   for (void* p : t->allocs) (void)hipFree(p);
+  for (hipEvent_t ev : {t->ev_fork, t->ev_p1, t->ev_p2, t->ev_join})
+    if (ev) (void)hipEventDestroy(ev);
+  if (t->s2) (void)hipStreamDestroy(t->s2);
   if (t->s) (void)hipStreamDestroy(t->s);
   delete t;
 }

@@ -39,13 +39,14 @@ struct WgradJob {
 // launch (the tiles of both fill the GPU together).
 int launch_wgrad2(const WgradJob* jobs, int njobs, int rows, int kc, int nchunk, hipStream_t s);
 // LayerNorm backward (y = LN(x) g + b, eps 1e-6) of rows [0, rows):
-// dres[row] += dL/dx, gb[0, D) = the gain gradient and gb[D, 2D) the shift
+// dout[row] = din[row] + dL/dx (din == dout: in place; another buffer only
+// without rowmap), gb[0, D) = the gain gradient and gb[D, 2D) the shift
 // gradient (column sums over the rows; zeros for rows == 0).  part holds
 // ln_bwd_blocks(rows) <= max_blocks partial rows of 2D floats.  With rowmap,
-// dy row i belongs to x / dres row rowmap[i].
+// dy row i belongs to x / din / dout row rowmap[i].
 int ln_bwd_blocks(int rows);
-int launch_ln_bwd(const float* x, const float* g, const float* dy, float* dres, float* part, int max_blocks, int rows,
-                  int D, const int* rowmap, float* gb, hipStream_t s);
+int launch_ln_bwd(const float* x, const float* g, const float* dy, const float* din, float* dout, float* part,
+                  int max_blocks, int rows, int D, const int* rowmap, float* gb, hipStream_t s);
 // Batch loss mean_b [MSE + alpha TV(pred)] and its gradient dpred; part
 // receives nblocks partial sums of the loss.
 int launch_pretrain_loss(const float* pred, const void* gt, int B, int H, int W, int C, float alpha, float* dpred,

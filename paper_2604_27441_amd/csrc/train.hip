@@ -243,15 +243,15 @@ __global__ __launch_bounds__(TB, 2) void wgrad_kernel(const WgradArgs args) {
 //
 // y = xhat g + b with xhat = (x - mean) rstd.  One wave per row, 16 waves
 // per block: dx = rstd (dy g - mean(dy g) - xhat mean(dy g xhat)), added
-// into dres.  The gain and shift gradients are column sums over the rows of
+// to din into dout (the same buffer or, without rowmap, another one).  The gain and shift gradients are column sums over the rows of
 // xhat dy and dy: each block writes its 16 rows' sums (in row order),
 // part[block][d] (gain) and part[block][D + d] (shift), which
 // colsum_final_kernel then adds over the blocks in order.  With rowmap, row i
 // of dy belongs to row rowmap[i] of x and dres.
 constexpr int LN_WAVES = 16, LN_TB = 64 * LN_WAVES;
 __global__ __launch_bounds__(LN_TB) void ln_bwd_kernel(const float* __restrict__ x, const float* __restrict__ g,
-                                                       const float* __restrict__ dy, float* __restrict__ dres,
-                                                       float* __restrict__ part, int rows, int D,
+                                                       const float* __restrict__ dy, const float* din,
+                                                       float* dout, float* __restrict__ part, int rows, int D,
                                                        const int* __restrict__ rowmap) {
   constexpr int MAXE = 8;  // D <= 512
   __shared__ float red[LN_WAVES][64 * MAXE];
@@ -300,11 +300,12 @@ __global__ __launch_bounds__(LN_TB) void ln_bwd_kernel(const float* __restrict__
       s2 += __shfl_xor(s2, o);
     }
     const float m1 = s1 / D, m2 = s2 / D;
-    float* rp = dres + (size_t)xr * D;
+    const float* ri = din + (size_t)xr * D;
+    float* ro = dout + (size_t)xr * D;
 #pragma unroll
     for (int e = 0; e < MAXE; ++e) {
       const int d = lane + 64 * e;
-      if (d < D) rp[d] += rstd * (gv[e] - m1 - xv[e] * m2);
+      if (d < D) ro[d] = ri[d] + rstd * (gv[e] - m1 - xv[e] * m2);
     }
   }
   float* out = part + (size_t)blockIdx.x * 2 * D;
@@ -744,12 +745,12 @@ int launch_wgrad(const float* dy, const float* x, int rows, int nout, int nin, i
 
 int ln_bwd_blocks(int rows) { return rows > 0 ? cdiv(rows, LN_WAVES) : 1; }
 
-int launch_ln_bwd(const float* x, const float* g, const float* dy, float* dres, float* part, int max_blocks, int rows,
-                  int D, const int* rowmap, float* gb, hipStream_t s) {
-  if (D <= 0 || D > 512 || rows < 0) return -22;
+int launch_ln_bwd(const float* x, const float* g, const float* dy, const float* din, float* dout, float* part,
+                  int max_blocks, int rows, int D, const int* rowmap, float* gb, hipStream_t s) {
+  if (D <= 0 || D > 512 || rows < 0 || (rowmap && din != dout)) return -22;
   const int nblk = ln_bwd_blocks(rows);
   if (nblk > max_blocks) return -22;
-  ln_bwd_kernel<<<nblk, LN_TB, 0, s>>>(x, g, dy, dres, part, rows, D, rowmap);
+  ln_bwd_kernel<<<nblk, LN_TB, 0, s>>>(x, g, dy, din, dout, part, rows, D, rowmap);
   if (int e = last()) return e;
   colsum_final_kernel<<<cdiv(2 * D, 64), TB, 0, s>>>(part, nblk, 2 * D, gb);
   return last();
