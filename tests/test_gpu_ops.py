@@ -29,8 +29,12 @@ def _as_op(a, prec):
     return t.cuda(), t.to(torch.float64).numpy()
 
 
+# FP32 products of at most 256 workgroups of 64-wide tiles run 8-wave
+# workgroups that split each stage's k steps; 12800 x 384 (600 tiles of 64)
+# and 4608 x 1536 (432 tiles of 128) take the 4-wave forms
 @pytest.mark.parametrize("prec", [FP32, BF16])
-@pytest.mark.parametrize("M,N,K", [(1, 64, 64), (300, 192, 384), (1000, 1152, 384), (257, 384, 1536), (77, 64, 192), (200, 256, 320)])
+@pytest.mark.parametrize("M,N,K", [(1, 64, 64), (300, 192, 384), (1000, 1152, 384), (257, 384, 1536), (77, 64, 192),
+                                   (200, 256, 320), (12800, 384, 384), (4608, 1536, 384)])
 @pytest.mark.parametrize("epi", [0, 1, 2])
 def test_linear(prec, M, N, K, epi):
     x = RNG.standard_normal((M, K))
