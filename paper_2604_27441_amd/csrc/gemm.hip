@@ -565,8 +565,8 @@ __global__ __launch_bounds__(NT * KS, KS == 1 ? 2 : 1) void gemm_kernel(const Ge
   const int nreq = a.dyn_nreq ? *a.dyn_nreq : a.nreq;
   if (m0 >= Mlive) return;  // grid sized for a capacity
   const int KT = a.K / BK;
-  const T* __restrict__ W = (const T*)a.W + (size_t)blockIdx.y * a.bsw;
-  const T* __restrict__ X = (const T*)a.X + (size_t)blockIdx.y * a.bsx;
+  const T* __restrict__ W = (const T*)a.W;
+  const T* __restrict__ X = (const T*)a.X;
 
   // gather: token coordinates of this thread's rows
   int g_req[XC], g_j[XC], g_y[XC], g_x[XC];
@@ -734,15 +734,6 @@ __global__ __launch_bounds__(NT * KS, KS == 1 ? 2 : 1) void gemm_kernel(const Ge
   epi_load_cols<Op, BN>(a, n0, wn, half, cols);
   if constexpr (EPI == EPI_HEAD) {
     gemm_epilogue<Op, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, lane, wave, cols);
-  } else if constexpr (EPI == EPI_STORE && XM == X_DENSE) {
-    if (blockIdx.y) {
-      // product blockIdx.y of a batch
-      GemmArgs ab = a;
-      ab.out = (OutT*)a.out + (size_t)blockIdx.y * a.bso;
-      gemm_epilogue_staged<Op, BN, EPI, OutT>(ab, acc, m0, n0, Mlive, nreq, tid, smem, cols, act);
-    } else {
-      gemm_epilogue_staged<Op, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, tid, smem, cols, act);
-    }
   } else {
     gemm_epilogue_staged<Op, BN, EPI, OutT>(a, acc, m0, n0, Mlive, nreq, tid, smem, cols, act);
   }
@@ -936,24 +927,23 @@ int launch_t(const GemmArgs& a, hipStream_t s) {
     // 128-wide tile with two prefetched stages.  Dense products take 128-wide
     // tiles unless 64-wide ones (twice as many, half the work each) spread
     // better over the 256 CUs: the busiest CU then holds fewer feature columns
-    const int nb = a.batch > 1 ? a.batch : 1;
     if constexpr (XM == X_DENSE && sizeof(typename Op::T) == 4 && EPI != EPI_HEAD) {
       // FP32 products of at most one 64-wide workgroup per CU: eight waves
       // that split each stage's k steps, two per SIMD instead of one
-      if ((long long)gm * (a.N / 64) * nb <= 256) {
-        gemm_kernel<Op, 64, EPI, XM, OutT, 2><<<dim3(gm * (a.N / 64), nb), 2 * NT, 0, s>>>(a);
+      if ((long long)gm * (a.N / 64) <= 256) {
+        gemm_kernel<Op, 64, EPI, XM, OutT, 2><<<gm * (a.N / 64), 2 * NT, 0, s>>>(a);
         return hipGetLastError() == hipSuccess ? 0 : -5;
       }
     }
     if constexpr (XM == X_DENSE) {
-      const long long t128 = (long long)gm * (a.N / 128) * nb;
+      const long long t128 = (long long)gm * (a.N / 128);
       const bool wide = a.N % 128 == 0 && (2 * t128 + 255) / 256 >= 2 * ((t128 + 255) / 256);
       if (wide) {
-        gemm_kernel<Op, 128, EPI, XM, OutT><<<dim3(gm * (a.N / 128), nb), NT, 0, s>>>(a);
+        gemm_kernel<Op, 128, EPI, XM, OutT><<<gm * (a.N / 128), NT, 0, s>>>(a);
         return hipGetLastError() == hipSuccess ? 0 : -5;
       }
     }
-    gemm_kernel<Op, 64, EPI, XM, OutT><<<dim3(gm * (a.N / 64), nb), NT, 0, s>>>(a);
+    gemm_kernel<Op, 64, EPI, XM, OutT><<<gm * (a.N / 64), NT, 0, s>>>(a);
     return hipGetLastError() == hipSuccess ? 0 : -5;
   }
 }
@@ -1018,8 +1008,6 @@ int launch_tubelet_pack(Prec prec, const GemmArgs& a, void* out, hipStream_t s) 
 
 int launch_gemm(Prec prec, int epi, int xmode, const GemmArgs& a, hipStream_t s) {
   if (a.M <= 0) return 0;
-  // batches: plain FP32 stores of dense products only (the weight gradients)
-  if (a.batch > 1 && (prec != P_FP32 || epi != EPI_STORE || xmode != X_DENSE || a.batch > 65535)) return -22;
   if (a.N % 64 != 0) return -22;
   // the epilogue reads bias and row scales as 16-byte vectors
   if (((uintptr_t)a.bias | (uintptr_t)a.wscale) & 15) return -22;

@@ -69,9 +69,6 @@ struct GemmArgs {
   const float* head_inv;
   // gather / PE / head
   const ReqDesc* reqs; int nreq; int channels;
-  // batched FP32 products (EPI_STORE, dense): grid.y = batch, product b takes
-  // X + b bsx, W + b bsw and writes out + b bso (element strides)
-  int batch; long long bsx, bsw, bso;
 };
 
 constexpr int ATTN_TARGET_TILE = 0x8000;
