@@ -572,6 +572,7 @@ def train_bench(log, steps=5, warmup=1, batch=8, height=192, width=256):
     P = gy * gx
     N = 3 * P
     total_flop, total_s = 0.0, 0.0
+    data = {}
     for C, name in ((3, "rgb"), (1, "depth")):
         batches = []
         for i in range(warmup + steps):
@@ -584,6 +585,7 @@ def train_bench(log, steps=5, warmup=1, batch=8, height=192, width=256):
                             torch.from_numpy(np.ascontiguousarray(tgt)).cuda(),
                             torch.from_numpy(np.ascontiguousarray(np.stack([x["mask"] for x in sm]))).cuda(),
                             np.stack([x["ref_idx"] for x in sm]), np.array([x["t_target"] for x in sm])))
+        data[name] = batches
         with Trainer(blobs[0 if C == 3 else 1], C, batch, height, width) as tr:
             losses = [tr.step(*batches[i]) for i in range(warmup)]
             torch.cuda.synchronize()
@@ -601,6 +603,43 @@ def train_bench(log, steps=5, warmup=1, batch=8, height=192, width=256):
     out["flop_per_sample"] = {"rgb": train_flop_per_sample(N, P, 3), "depth": train_flop_per_sample(N, P, 1)}
     out["tflops"] = total_flop / total_s / 1e12
     out["frac_of_fp32_peak"] = out["tflops"] / FP32_PEAK_TFLOPS
+
+    # both models at once: each trainer stepped by its own host thread (the
+    # library call releases the interpreter lock), so their kernels share the
+    # GPU; the same batches and starting weights as above
+    import threading
+    trs = [Trainer(blobs[0], 3, batch, height, width), Trainer(blobs[1], 1, batch, height, width)]
+    try:
+        names = ("rgb", "depth")
+        for tr, name in zip(trs, names):
+            for i in range(warmup):
+                tr.step(*data[name][i])
+        torch.cuda.synchronize()
+        errors = []
+
+        def run(tr, name):
+            try:
+                for i in range(steps):
+                    tr.step(*data[name][warmup + i])
+            except Exception as e:  # re-raised below on the main thread
+                errors.append(e)
+
+        threads = [threading.Thread(target=run, args=(tr, name)) for tr, name in zip(trs, names)]
+        t0 = time.perf_counter()
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+        dt = time.perf_counter() - t0
+        if errors:
+            raise errors[0]
+    finally:
+        for tr in trs:
+            tr.close()
+    flop = (train_flop_per_sample(N, P, 3) + train_flop_per_sample(N, P, 1)) * batch
+    out["both_models_concurrent"] = {"ms_per_step_pair": 1e3 * dt / steps, "samples_per_s": 2 * batch * steps / dt,
+                                     "tflops": flop * steps / dt / 1e12}
+    log(f"train rgb + depth at once: {1e3 * dt / steps:.2f} ms per pair of steps, {flop * steps / dt / 1e12:.1f} TFLOP/s")
     return out
 
 
