@@ -517,7 +517,7 @@ __global__ __launch_bounds__(TB, 2) void attn_bwd_dkdv_kernel(const AttnBwdArgs 
   float pq[16], pd[16], plse = 0.0f, pdv = 0.0f;
   fetch_rows(pq, qh, 64, base, base + N);
   fetch_rows(pd, doh, dpitch, base, base + N);
-  if (threadIdx.x < 64 && threadIdx.x < N) {
+  if (threadIdx.x < 64 && (int)threadIdx.x < N) {
     plse = a.lse[(size_t)h * a.ld + base + threadIdx.x];
     pdv = a.dv[(size_t)h * a.ld + base + threadIdx.x];
   }
