@@ -185,3 +185,24 @@ def test_batch_gradient_is_the_mean_of_its_halves():
     arch = oracle.Arch(channels=1)
     worst = _check_grads(g.astype(np.float32), want, arch, rtol=1e-4)
     print(f"batch 16 against the mean of its halves: worst per-tensor gradient error {worst:.3g} of the tensor's max")
+
+
+def test_steps_are_bit_identical_across_trainers():
+    """Every sum in the step has a fixed order (row-chunk partials, their sums,
+    the LayerNorm column sums, the loss partials), and the weight-gradient
+    launches on the second stream are ordered by events against the input-
+    gradient chain that reads and rewrites the same buffers; so two trainers
+    from the same weights give bit-identical losses, gradients and weights
+    over two steps at the benchmark's shape (256 x 192, batch 8, 12 + 4
+    blocks). A missing ordering would show up here as differing bits."""
+    from paper_2604_27441_amd import Trainer
+    blob = synth.make_weights(19)[0]
+    batches = [_dev(synth.make_pretrain_batch(50 + i, 8, 192, 256, 3), 3) for i in range(2)]
+    runs = []
+    for _ in range(2):
+        with Trainer(blob, 3, 8, 192, 256) as tr:
+            losses = [tr.step(*b) for b in batches]
+            runs.append((losses, tr.grads(), tr.weights()))
+    assert runs[0][0] == runs[1][0], (runs[0][0], runs[1][0])
+    assert np.array_equal(runs[0][1], runs[1][1])
+    assert np.array_equal(runs[0][2], runs[1][2])
