@@ -206,3 +206,31 @@ def test_steps_are_bit_identical_across_trainers():
     assert runs[0][0] == runs[1][0], (runs[0][0], runs[1][0])
     assert np.array_equal(runs[0][1], runs[1][1])
     assert np.array_equal(runs[0][2], runs[1][2])
+
+
+def test_trainers_stepped_from_two_threads_match_sequential_steps():
+    """The RGB and depth trainers stepped at once from two host threads (as
+    bench.py times them) give the same bits as when stepped one after the
+    other: each trainer owns its streams and buffers."""
+    import threading
+
+    from paper_2604_27441_amd import Trainer
+    blobs = synth.make_weights(23)
+    data = {C: _dev(synth.make_pretrain_batch(60 + C, 4, 192, 256, C), C) for C in (3, 1)}
+
+    def one(C, out):
+        with Trainer(blobs[0 if C == 3 else 1], C, 4, 192, 256) as tr:
+            out[C] = (tr.step(*data[C]), tr.grads())
+
+    seq, par = {}, {}
+    for C in (3, 1):
+        one(C, seq)
+    threads = [threading.Thread(target=one, args=(C, par)) for C in (3, 1)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    for C in (3, 1):
+        assert C in par, "a trainer thread failed"
+        assert seq[C][0] == par[C][0], (C, seq[C][0], par[C][0])
+        assert np.array_equal(seq[C][1], par[C][1]), C
